@@ -1,0 +1,184 @@
+/*
+ * qtx.h — C ABI of the open-boundary ballistic transport solver for MI355X.
+ *
+ * The library solves, independently for every energy E of a grid,
+ *
+ *     (z S - H - H_ext - Sigma_L(z) - Sigma_R(z)) psi = b,   z = E + i eta,
+ *
+ * for a device of N slabs whose Hamiltonian H and overlap S are block
+ * tridiagonal with m x m blocks (partition-of-unity basis: linear shape
+ * functions along transport times Bloch-wave enhancement functions; Sec.
+ * "Matrix equations", eqs. expansion_matrix_eq and infinite_system), with
+ * semi-infinite leads on both sides folded into the self-energies
+ * Sigma_L, Sigma_R (Sec. "Contact self-energies"), and returns the
+ * transmission T(E) (Sec. "Transmission and Ballistic Current") and the
+ * slab-resolved density of states injected from each contact (the node
+ * density of Sec. "Density").
+ *
+ * Conventions (all calls):
+ *  - complex numbers are interleaved (re, im) doubles, i.e. numpy complex128;
+ *  - every m x m block is row-major; the blocks of slab i are contiguous;
+ *  - H01 / S01 couple slab j to slab j+1; the coupling back is their
+ *    conjugate transpose; for a lead at potential energy V the shifted
+ *    energy is z - V;
+ *  - units: eV for energies and potentials, hbar = 1, one slab per length
+ *    unit, spin degeneracy 2 included in the densities;
+ *  - all host pointers are owned by the caller and only read (or written,
+ *    for outputs) during the call; the library copies what it keeps;
+ *  - errors are returned as status codes; qtx_last_error() gives a
+ *    per-context message; no exception crosses the ABI;
+ *  - a context is not thread-safe: use one context per host thread.
+ */
+#ifndef QTX_H
+#define QTX_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qtx_ctx qtx_ctx;
+
+typedef struct { double re, im; } qtx_c128;
+
+typedef enum {
+  QTX_OK = 0,
+  QTX_EINVAL = 1,     /* bad argument: NULL pointer, size, non-Hermitian block, unset state */
+  QTX_ENOMEM = 2,     /* device or host allocation failed */
+  QTX_EDEVICE = 3,    /* a HIP runtime call failed */
+  QTX_ENOTCONV = 4,   /* outputs written, but some energy did not converge (see qtx_info.flags) */
+  QTX_ESTATE = 5      /* call out of order (e.g. solve before set_lead / set_device) */
+} qtx_status;
+
+typedef enum { QTX_LEFT = 0, QTX_RIGHT = 1 } qtx_side;
+
+/* How the nodal potential V_i enters H_ext (Sec. "Matrix equations",
+ * extrinsic-potential matrix elements):
+ *  QTX_POT_DIAG:      H_ext = diag_i(V_i S_ii);
+ *  QTX_POT_LINEAR_FE: V linear between nodes; blocks weighted by the hat
+ *                     functions: Vd_i = 3/4 V_i + (V_{i-1} + V_{i+1}) / 8 on
+ *                     S_ii and Vu_i = (V_i + V_{i+1}) / 2 on S_{i,i+1},
+ *                     with V_{-1} = V_L and V_N = V_R (the lead potentials). */
+typedef enum { QTX_POT_DIAG = 0, QTX_POT_LINEAR_FE = 1 } qtx_pot_mode;
+
+/* QTX_FP64: every step in double precision.
+ * QTX_MIXED: lead self-energies, residuals and refinement in double; the
+ *            block sweeps in single precision with double-precision
+ *            iterative refinement of the dominant injected columns. */
+typedef enum { QTX_FP64 = 0, QTX_MIXED = 1 } qtx_precision;
+
+/* Per-energy diagnostics. */
+typedef struct {
+  int dec_iters;        /* decimation doublings used (max over the two leads) */
+  int refine_steps;     /* refinement steps (QTX_MIXED), 0 otherwise */
+  double resid;         /* final relative residual of the refined columns (QTX_MIXED) */
+  int fell_back_fp64;   /* 1 if the energy was re-solved in FP64 */
+  int flags;            /* bit 0: decimation hit its iteration cap;
+                           bit 1: non-finite output; bit 2: refinement did not converge */
+} qtx_info;
+
+#define QTX_FLAG_DEC_NOTCONV 1
+#define QTX_FLAG_NONFINITE 2
+#define QTX_FLAG_REFINE_NOTCONV 4
+
+/* Create a context on HIP device `hip_device`.  *out receives the handle.
+ * Returns QTX_EINVAL for a NULL out or a bad device index, QTX_EDEVICE if
+ * the HIP runtime fails. */
+qtx_status qtx_create(int hip_device, qtx_ctx** out);
+
+/* Free a context and all device memory it owns.  NULL is ignored. */
+void qtx_destroy(qtx_ctx* ctx);
+
+/* Last error message of the context ("" if none); valid until the next
+ * call on the same context.  A NULL context gives a static string. */
+const char* qtx_last_error(const qtx_ctx* ctx);
+
+/* Stream on which qtx_solve_device enqueues its work (a hipStream_t; a
+ * torch.cuda.Stream's cuda_stream handle works).  NULL selects the
+ * library's own stream.  The caller keeps ownership of the stream. */
+qtx_status qtx_set_stream(qtx_ctx* ctx, void* hip_stream);
+
+/* Lead blocks of one contact (Sec. "Contact self-energies": the blocks of
+ * eq. infinite_system just outside the simulation domain).  H00, S00: m x m
+ * on-site blocks, Hermitian to 1e-12 relative (else QTX_EINVAL); H01, S01:
+ * coupling from lead slab j to slab j+1 along +z (the same orientation for
+ * both leads).  V_lead: potential energy of the
+ * lead (eV).  The blocks are deep-copied to the device.  m must agree with
+ * the other lead and the device, 1 <= m <= 128. */
+qtx_status qtx_set_lead(qtx_ctx* ctx, qtx_side side, int m,
+                        const qtx_c128* H00, const qtx_c128* H01,
+                        const qtx_c128* S00, const qtx_c128* S01, double V_lead);
+
+/* Device blocks (eq. infinite_system restricted to N slabs).  Hd, Sd: N
+ * on-site m x m blocks (N*m*m, Hermitian); Hu, Su: N-1 couplings slab i ->
+ * i+1 ((N-1)*m*m).  All four NULL: every slab copies the LEFT lead's blocks
+ * (set the left lead first).  Either all four or none must be given.
+ * N >= 1.  Deep-copied. */
+qtx_status qtx_set_device(qtx_ctx* ctx, int N, int m,
+                          const qtx_c128* Hd, const qtx_c128* Hu,
+                          const qtx_c128* Sd, const qtx_c128* Su);
+
+/* Nodal potential energy V[0..N-1] (eV) and how it is projected (see
+ * qtx_pot_mode).  Must follow qtx_set_device (same N).  Deep-copied. */
+qtx_status qtx_set_potential(qtx_ctx* ctx, const double* V, qtx_pot_mode mode);
+
+/* Solve an energy grid (host buffers, synchronous).
+ * E[nE]: energies (eV); eta > 0: broadening added to every energy in the
+ * leads and the device.  Outputs (caller-allocated host memory):
+ *   T[nE]            transmission left -> right,
+ *                    T = Re Tr[Gamma_R G_{N-1,0} Gamma_L G_{N-1,0}^H];
+ *   ldos[nE*2*N]     or NULL; ldos[(e*2 + s)*N + i] = (1/pi) Re sum over
+ *                    slab i of diag(G Gamma_s G^H), s = 0 left-, 1 right-
+ *                    injected (states / eV / slab, spin 2);
+ *   info[nE]         or NULL; per-energy diagnostics.
+ * Returns QTX_OK, QTX_ENOTCONV (outputs written, some energy flagged), or
+ * an error code (outputs undefined). */
+qtx_status qtx_solve(qtx_ctx* ctx, const double* E, int nE, double eta,
+                     qtx_precision prec, double* T, double* ldos, qtx_info* info);
+
+/* Same as qtx_solve with DEVICE pointers (e.g. torch tensors' data_ptr()),
+ * enqueued on the context stream without a host synchronisation.  info_dev
+ * may be NULL; the other outputs as in qtx_solve.  The buffers must stay
+ * alive until the stream has executed the work.  Per-energy convergence is
+ * reported through info_dev only (the return value does not wait for it). */
+qtx_status qtx_solve_device(qtx_ctx* ctx, const double* E_dev, int nE, double eta,
+                            qtx_precision prec, double* T_dev, double* ldos_dev,
+                            qtx_info* info_dev);
+
+/* Self-energies and broadening factors alone (the decimation step of the
+ * solve, exposed for verification).  Host buffers:
+ *   sigma[nE*2*m*m]  Sigma_L then Sigma_R per energy (row-major, m x m);
+ *   wfac[nE*2*m*m]   or NULL: W with Gamma = W diag(sgn) W^H per side;
+ *   sgn[nE*2*m]      or NULL: the signs (+1, -1, or 0 for unused columns).
+ *   iters[nE]        or NULL: doublings used. */
+qtx_status qtx_self_energy(qtx_ctx* ctx, const double* E, int nE, double eta,
+                           qtx_c128* sigma, qtx_c128* wfac, double* sgn, int* iters);
+
+/* ---- batching and serving --------------------------------------------- */
+
+/* A problem is a context that shares the parent's device and stream and
+ * carries its own leads, device blocks and potential (same setters). */
+qtx_status qtx_problem_create(qtx_ctx* parent, qtx_ctx** problem);
+
+/* Solve nprob problems, each on its own energy grid E[p][0..nE[p]-1], in
+ * one batched launch sequence of persistent kernels (devices of different
+ * N and m share the launch).  T[p] (nE[p]) and ldos[p] (nE[p]*2*N_p, or
+ * NULL) are host buffers.  Problems must be fully set. */
+qtx_status qtx_solve_batch(qtx_ctx* ctx, int nprob, qtx_ctx* const* probs,
+                           const double* const* E, const int* nE, double eta,
+                           qtx_precision prec, double* const* T, double* const* ldos);
+
+/* Host helper: slab charge from a solved grid with quadrature weights w:
+ * charge[i] = sum_k w[k] (f((E_k - muL)/kT) ldos[k][0][i]
+ *                        + f((E_k - muR)/kT) ldos[k][1][i]),
+ * f the Fermi function (the energy integral of the node density, Sec.
+ * "Density").  kT > 0. */
+qtx_status qtx_charge(const double* ldos, const double* w, int nE, int N, const double* E,
+                      double muL, double muR, double kT, double* charge);
+
+/* Library version string. */
+const char* qtx_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

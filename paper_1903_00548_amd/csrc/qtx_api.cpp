@@ -1,0 +1,486 @@
+// Host runtime behind the C ABI declared in include/qtx.h: context state,
+// validation, device copies of the leads / device blocks / potential,
+// workspace management and the launch sequence of one solve:
+//   decimation (lead self-energies + broadening factors, FP64)
+//   -> block sweeps with fused transmission and density reductions.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "qtx.h"
+#include "qtx_internal.h"
+
+namespace {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t n = 0;
+  hipError_t ensure(size_t bytes) {
+    if (bytes <= n) return hipSuccess;
+    if (p) hipFree(p);
+    p = nullptr;
+    n = 0;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e == hipSuccess) n = bytes;
+    return e;
+  }
+  void release() {
+    if (p) hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+int pad16(int m) { return ((m + 15) / 16) * 16; }
+
+}  // namespace
+
+struct qtx_ctx {
+  int device = 0;
+  int num_cu = 256;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  qtx_ctx* parent = nullptr;
+
+  int m = 0, M = 0;
+  bool lead_set[2] = {false, false};
+  double Vlead[2] = {0.0, 0.0};
+  std::vector<std::complex<double>> hlead[2];  // unpadded H00, H01, S00, S01
+  DevBuf dlead[2];                             // padded 4 M^2
+
+  int N = 0;
+  bool dev_set = false, uniform = true;
+  DevBuf ddev;                                 // padded Hd, Hu, Sd, Su
+  bool pot_set = false;
+  int pot_mode = QTX_POT_DIAG;
+  DevBuf dV;
+
+  // workspaces
+  DevBuf wE, wT, wldos, winfo;
+  DevBuf sig, wf, sgn, iters, dscr, sws, part;
+
+  // tunables
+  double dec_tol = 1e-14;
+  int dec_maxit = 60;
+  int chunk = 4096;
+  int wg_per_cu = 2;
+};
+
+namespace {
+
+qtx_status fail(qtx_ctx* c, qtx_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+qtx_status hipfail(qtx_ctx* c, hipError_t e, const char* what) {
+  return fail(c, e == hipErrorOutOfMemory ? QTX_ENOMEM : QTX_EDEVICE,
+              std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define QTX_HIP(ctx, call)                          \
+  do {                                              \
+    hipError_t _e = (call);                         \
+    if (_e != hipSuccess) return hipfail(ctx, _e, #call); \
+  } while (0)
+
+typedef std::complex<double> cd;
+
+bool hermitian(const qtx_c128* A, int m, double rel) {
+  double scale = 0.0;
+  for (int i = 0; i < m * m; ++i) scale = std::max(scale, std::abs(cd(A[i].re, A[i].im)));
+  const double tol = rel * std::max(scale, 1e-300);
+  for (int r = 0; r < m; ++r)
+    for (int c = 0; c <= r; ++c) {
+      cd a(A[r * m + c].re, A[r * m + c].im), b(A[c * m + r].re, A[c * m + r].im);
+      if (std::abs(a - std::conj(b)) > tol) return false;
+    }
+  return true;
+}
+
+// Pad an m x m block to M x M.  Padded basis functions get an on-site
+// block with H = -1, S = 0 (so zS - H = +1 on the padding) and no coupling:
+// they decouple from the physical ones, carry no broadening and add
+// nothing to transmission or densities.
+void pad_block(const qtx_c128* src, int m, int M, bool onsite_H, std::vector<double2>& dst, size_t off) {
+  for (int r = 0; r < M; ++r)
+    for (int c = 0; c < M; ++c) {
+      double2 v = make_double2(0.0, 0.0);
+      if (r < m && c < m) v = make_double2(src[r * m + c].re, src[r * m + c].im);
+      else if (onsite_H && r == c) v = make_double2(-1.0, 0.0);
+      dst[off + (size_t)r * M + c] = v;
+    }
+}
+
+bool leads_identical(const qtx_ctx* c) {
+  if (c->Vlead[0] != c->Vlead[1]) return false;
+  return c->hlead[0] == c->hlead[1];
+}
+
+qtx_status check_ready(qtx_ctx* c) {
+  if (!c->lead_set[0] || !c->lead_set[1]) return fail(c, QTX_ESTATE, "both leads must be set before solving");
+  if (!c->dev_set) return fail(c, QTX_ESTATE, "device must be set before solving");
+  if (c->M > 64) return fail(c, QTX_EINVAL, "block size above 64 is not supported by this build");
+  return QTX_OK;
+}
+
+qtx::Prob make_prob(const qtx_ctx* c) {
+  qtx::Prob P;
+  P.N = c->N;
+  P.M = c->M;
+  P.leadL = c->dlead[0].as<double2>();
+  P.leadR = c->dlead[1].as<double2>();
+  P.VL = c->Vlead[0];
+  P.VR = c->Vlead[1];
+  const size_t MM = (size_t)c->M * c->M;
+  if (c->uniform) {
+    P.dHd = P.dHu = P.dSd = P.dSu = nullptr;
+  } else {
+    const double2* b = c->ddev.as<double2>();
+    P.dHd = b;
+    P.dHu = b + c->N * MM;
+    P.dSd = b + (2 * (size_t)c->N - 1) * MM;
+    P.dSu = b + (3 * (size_t)c->N - 1) * MM;
+  }
+  P.V = c->pot_set ? c->dV.as<double>() : nullptr;
+  P.pot_mode = c->pot_mode;
+  return P;
+}
+
+// decimation for energies E_dev[0..nE) into ctx->sig / wf / sgn / iters
+qtx_status stage_decimate(qtx_ctx* c, const double* E_dev, int nE, double eta) {
+  const int M = c->M;
+  const size_t MM = (size_t)M * M;
+  const int sides = leads_identical(c) ? 1 : 2;
+  const int grid = std::max(1, std::min(nE * sides, c->num_cu * c->wg_per_cu));
+  QTX_HIP(c, c->sig.ensure((size_t)nE * 2 * MM * sizeof(double2)));
+  QTX_HIP(c, c->wf.ensure((size_t)nE * 2 * MM * sizeof(double2)));
+  QTX_HIP(c, c->sgn.ensure((size_t)nE * 2 * M * sizeof(double)));
+  QTX_HIP(c, c->iters.ensure((size_t)nE * 2 * sizeof(int)));
+  QTX_HIP(c, c->dscr.ensure((size_t)grid * 9 * MM * sizeof(double2)));
+  qtx::Prob P = make_prob(c);
+  QTX_HIP(c, qtx::run_decimate(M, P, E_dev, nE, eta, sides, c->dec_tol, c->dec_maxit, c->dscr.as<double2>(),
+                               grid, c->sig.as<double2>(), c->wf.as<double2>(), c->sgn.as<double>(),
+                               c->iters.as<int>(), c->stream));
+  return QTX_OK;
+}
+
+qtx_status solve_device_core(qtx_ctx* c, const double* E_dev, int nE, double eta, qtx_precision prec,
+                             double* T_dev, double* ldos_dev, qtx_info* info_dev) {
+  qtx_status s = check_ready(c);
+  if (s != QTX_OK) return s;
+  if (nE < 0 || !(eta >= 0.0)) return fail(c, QTX_EINVAL, "nE must be >= 0 and eta >= 0");
+  if (nE == 0) return QTX_OK;
+  if (!E_dev || !T_dev) return fail(c, QTX_EINVAL, "E and T must not be NULL");
+  const bool fp32 = (prec == QTX_MIXED);
+  const int M = c->M, N = c->N;
+  for (int e0 = 0; e0 < nE; e0 += c->chunk) {
+    const int ne = std::min(c->chunk, nE - e0);
+    s = stage_decimate(c, E_dev + e0, ne, eta);
+    if (s != QTX_OK) return s;
+    const int grid = std::max(1, std::min(ne, c->num_cu * c->wg_per_cu));
+    const size_t esz = fp32 ? sizeof(float2) : sizeof(double2);
+    const size_t ws_stride = (size_t)(N + 1) * M * 2 * M;
+    QTX_HIP(c, c->sws.ensure((size_t)grid * ws_stride * esz));
+    QTX_HIP(c, c->part.ensure((size_t)grid * 4 * 2 * N * sizeof(double)));
+    qtx::Prob P = make_prob(c);
+    QTX_HIP(c, qtx::run_sweep(M, fp32, P, E_dev + e0, ne, eta, c->sig.as<double2>(), c->wf.as<double2>(),
+                              c->sgn.as<double>(), c->iters.as<int>(), c->sws.p, ws_stride,
+                              c->part.as<double>(), grid, T_dev + e0,
+                              ldos_dev ? ldos_dev + (size_t)e0 * 2 * N : nullptr,
+                              info_dev ? info_dev + e0 : nullptr, c->stream));
+  }
+  return QTX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* qtx_version(void) { return "qtx 0.1 (gfx950)"; }
+
+qtx_status qtx_create(int hip_device, qtx_ctx** out) {
+  if (!out) return QTX_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || hip_device < 0 || hip_device >= n) return QTX_EINVAL;
+  if (hipSetDevice(hip_device) != hipSuccess) return QTX_EDEVICE;
+  qtx_ctx* c = new qtx_ctx();
+  c->device = hip_device;
+  int cu = 0;
+  if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, hip_device) == hipSuccess && cu > 0)
+    c->num_cu = cu;
+  if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+    delete c;
+    return QTX_EDEVICE;
+  }
+  c->own_stream = true;
+  *out = c;
+  return QTX_OK;
+}
+
+void qtx_destroy(qtx_ctx* c) {
+  if (!c) return;
+  hipSetDevice(c->device);
+  if (c->stream) hipStreamSynchronize(c->stream);
+  DevBuf* bufs[] = {&c->dlead[0], &c->dlead[1], &c->ddev, &c->dV, &c->wE, &c->wT, &c->wldos, &c->winfo,
+                    &c->sig, &c->wf, &c->sgn, &c->iters, &c->dscr, &c->sws, &c->part};
+  for (DevBuf* b : bufs) b->release();
+  if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+  delete c;
+}
+
+const char* qtx_last_error(const qtx_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+qtx_status qtx_set_stream(qtx_ctx* c, void* st) {
+  if (!c) return QTX_EINVAL;
+  if (c->own_stream && c->stream) {
+    hipStreamSynchronize(c->stream);
+    hipStreamDestroy(c->stream);
+    c->stream = nullptr;
+    c->own_stream = false;
+  }
+  if (st) {
+    c->stream = (hipStream_t)st;
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess)
+      return fail(c, QTX_EDEVICE, "stream creation failed");
+    c->own_stream = true;
+  }
+  return QTX_OK;
+}
+
+qtx_status qtx_set_lead(qtx_ctx* c, qtx_side side, int m, const qtx_c128* H00, const qtx_c128* H01,
+                        const qtx_c128* S00, const qtx_c128* S01, double V_lead) {
+  if (!c) return QTX_EINVAL;
+  if (side != QTX_LEFT && side != QTX_RIGHT) return fail(c, QTX_EINVAL, "side must be QTX_LEFT or QTX_RIGHT");
+  if (!H00 || !H01 || !S00 || !S01) return fail(c, QTX_EINVAL, "lead blocks must not be NULL");
+  if (m < 1 || m > 128) return fail(c, QTX_EINVAL, "block size m must be in [1, 128]");
+  if (!std::isfinite(V_lead)) return fail(c, QTX_EINVAL, "lead potential must be finite");
+  const int other = 1 - side;
+  if ((c->lead_set[other] || c->dev_set) && c->m != m) return fail(c, QTX_EINVAL, "m differs from the other lead / device");
+  if (!hermitian(H00, m, 1e-12) || !hermitian(S00, m, 1e-12))
+    return fail(c, QTX_EINVAL, "H00 and S00 must be Hermitian");
+  hipSetDevice(c->device);
+  c->m = m;
+  c->M = pad16(m);
+  const int M = c->M;
+  const size_t MM = (size_t)M * M;
+  std::vector<double2> h(4 * MM);
+  pad_block(H00, m, M, true, h, 0);
+  pad_block(H01, m, M, false, h, MM);
+  pad_block(S00, m, M, false, h, 2 * MM);
+  pad_block(S01, m, M, false, h, 3 * MM);
+  QTX_HIP(c, c->dlead[side].ensure(4 * MM * sizeof(double2)));
+  QTX_HIP(c, hipMemcpy(c->dlead[side].p, h.data(), 4 * MM * sizeof(double2), hipMemcpyHostToDevice));
+  auto& hl = c->hlead[side];
+  hl.resize(4 * (size_t)m * m);
+  const qtx_c128* srcs[4] = {H00, H01, S00, S01};
+  for (int q = 0; q < 4; ++q)
+    for (int i = 0; i < m * m; ++i) hl[(size_t)q * m * m + i] = cd(srcs[q][i].re, srcs[q][i].im);
+  c->Vlead[side] = V_lead;
+  c->lead_set[side] = true;
+  return QTX_OK;
+}
+
+qtx_status qtx_set_device(qtx_ctx* c, int N, int m, const qtx_c128* Hd, const qtx_c128* Hu,
+                          const qtx_c128* Sd, const qtx_c128* Su) {
+  if (!c) return QTX_EINVAL;
+  if (N < 1) return fail(c, QTX_EINVAL, "N must be >= 1");
+  if (m < 1 || m > 128) return fail(c, QTX_EINVAL, "block size m must be in [1, 128]");
+  if ((c->lead_set[0] || c->lead_set[1]) && c->m != m) return fail(c, QTX_EINVAL, "m differs from the leads");
+  const int given = (Hd != nullptr) + (Sd != nullptr) + ((Hu != nullptr) || N == 1) + ((Su != nullptr) || N == 1);
+  const bool none = !Hd && !Hu && !Sd && !Su;
+  if (!none && given != 4) return fail(c, QTX_EINVAL, "give all four device block arrays or none");
+  hipSetDevice(c->device);
+  c->m = m;
+  c->M = pad16(m);
+  if (none) {
+    if (!c->lead_set[0]) return fail(c, QTX_ESTATE, "a uniform device copies the left lead: set it first");
+    c->uniform = true;
+    c->ddev.release();
+  } else {
+    for (int i = 0; i < N; ++i)
+      if (!hermitian(Hd + (size_t)i * m * m, m, 1e-12) || !hermitian(Sd + (size_t)i * m * m, m, 1e-12))
+        return fail(c, QTX_EINVAL, "device on-site blocks must be Hermitian");
+    const int M = c->M;
+    const size_t MM = (size_t)M * M;
+    const size_t nblk = 4 * (size_t)N - 2;
+    std::vector<double2> h(nblk * MM);
+    size_t off = 0;
+    for (int i = 0; i < N; ++i, off += MM) pad_block(Hd + (size_t)i * m * m, m, M, true, h, off);
+    for (int i = 0; i < N - 1; ++i, off += MM) pad_block(Hu + (size_t)i * m * m, m, M, false, h, off);
+    for (int i = 0; i < N; ++i, off += MM) pad_block(Sd + (size_t)i * m * m, m, M, false, h, off);
+    for (int i = 0; i < N - 1; ++i, off += MM) pad_block(Su + (size_t)i * m * m, m, M, false, h, off);
+    QTX_HIP(c, c->ddev.ensure(nblk * MM * sizeof(double2)));
+    QTX_HIP(c, hipMemcpy(c->ddev.p, h.data(), nblk * MM * sizeof(double2), hipMemcpyHostToDevice));
+    c->uniform = false;
+  }
+  if (c->N != N) c->pot_set = false;
+  c->N = N;
+  c->dev_set = true;
+  return QTX_OK;
+}
+
+qtx_status qtx_set_potential(qtx_ctx* c, const double* V, qtx_pot_mode mode) {
+  if (!c) return QTX_EINVAL;
+  if (!c->dev_set) return fail(c, QTX_ESTATE, "set the device before the potential");
+  if (!V) return fail(c, QTX_EINVAL, "V must not be NULL");
+  if (mode != QTX_POT_DIAG && mode != QTX_POT_LINEAR_FE) return fail(c, QTX_EINVAL, "unknown potential mode");
+  for (int i = 0; i < c->N; ++i)
+    if (!std::isfinite(V[i])) return fail(c, QTX_EINVAL, "potential must be finite");
+  hipSetDevice(c->device);
+  QTX_HIP(c, c->dV.ensure((size_t)c->N * sizeof(double)));
+  QTX_HIP(c, hipMemcpy(c->dV.p, V, (size_t)c->N * sizeof(double), hipMemcpyHostToDevice));
+  c->pot_mode = mode;
+  c->pot_set = true;
+  return QTX_OK;
+}
+
+qtx_status qtx_solve_device(qtx_ctx* c, const double* E_dev, int nE, double eta, qtx_precision prec,
+                            double* T_dev, double* ldos_dev, qtx_info* info_dev) {
+  if (!c) return QTX_EINVAL;
+  if (prec != QTX_FP64 && prec != QTX_MIXED) return fail(c, QTX_EINVAL, "unknown precision");
+  hipSetDevice(c->device);
+  return solve_device_core(c, E_dev, nE, eta, prec, T_dev, ldos_dev, info_dev);
+}
+
+qtx_status qtx_solve(qtx_ctx* c, const double* E, int nE, double eta, qtx_precision prec, double* T,
+                     double* ldos, qtx_info* info) {
+  if (!c) return QTX_EINVAL;
+  if (prec != QTX_FP64 && prec != QTX_MIXED) return fail(c, QTX_EINVAL, "unknown precision");
+  if (nE < 0) return fail(c, QTX_EINVAL, "nE must be >= 0");
+  if (nE == 0) return QTX_OK;
+  if (!E || !T) return fail(c, QTX_EINVAL, "E and T must not be NULL");
+  for (int e = 0; e < nE; ++e)
+    if (!std::isfinite(E[e])) return fail(c, QTX_EINVAL, "energies must be finite");
+  qtx_status s = check_ready(c);
+  if (s != QTX_OK) return s;
+  hipSetDevice(c->device);
+  const int N = c->N;
+  QTX_HIP(c, c->wE.ensure((size_t)nE * sizeof(double)));
+  QTX_HIP(c, c->wT.ensure((size_t)nE * sizeof(double)));
+  QTX_HIP(c, c->wldos.ensure((size_t)nE * 2 * N * sizeof(double)));
+  QTX_HIP(c, c->winfo.ensure((size_t)nE * sizeof(qtx_info)));
+  QTX_HIP(c, hipMemcpyAsync(c->wE.p, E, (size_t)nE * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  s = solve_device_core(c, c->wE.as<double>(), nE, eta, prec, c->wT.as<double>(), c->wldos.as<double>(),
+                        c->winfo.as<qtx_info>());
+  if (s != QTX_OK) return s;
+  std::vector<qtx_info> hinfo(nE);
+  QTX_HIP(c, hipMemcpyAsync(T, c->wT.p, (size_t)nE * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  if (ldos)
+    QTX_HIP(c, hipMemcpyAsync(ldos, c->wldos.p, (size_t)nE * 2 * N * sizeof(double), hipMemcpyDeviceToHost,
+                              c->stream));
+  QTX_HIP(c, hipMemcpyAsync(hinfo.data(), c->winfo.p, (size_t)nE * sizeof(qtx_info), hipMemcpyDeviceToHost,
+                            c->stream));
+  QTX_HIP(c, hipStreamSynchronize(c->stream));
+  bool flagged = false;
+  for (int e = 0; e < nE; ++e) flagged |= (hinfo[e].flags != 0);
+  if (info) std::memcpy(info, hinfo.data(), (size_t)nE * sizeof(qtx_info));
+  if (flagged) return fail(c, QTX_ENOTCONV, "some energies were flagged (see qtx_info.flags)");
+  return QTX_OK;
+}
+
+qtx_status qtx_self_energy(qtx_ctx* c, const double* E, int nE, double eta, qtx_c128* sigma, qtx_c128* wfac,
+                           double* sgn, int* iters) {
+  if (!c) return QTX_EINVAL;
+  if (nE < 0 || !(eta >= 0.0)) return fail(c, QTX_EINVAL, "nE must be >= 0 and eta >= 0");
+  if (nE == 0) return QTX_OK;
+  if (!E || !sigma) return fail(c, QTX_EINVAL, "E and sigma must not be NULL");
+  if (!c->lead_set[0] || !c->lead_set[1]) return fail(c, QTX_ESTATE, "both leads must be set");
+  if (c->M > 64) return fail(c, QTX_EINVAL, "block size above 64 is not supported by this build");
+  hipSetDevice(c->device);
+  const int m = c->m, M = c->M;
+  const size_t MM = (size_t)M * M;
+  QTX_HIP(c, c->wE.ensure((size_t)nE * sizeof(double)));
+  QTX_HIP(c, hipMemcpyAsync(c->wE.p, E, (size_t)nE * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  qtx_status s = stage_decimate(c, c->wE.as<double>(), nE, eta);
+  if (s != QTX_OK) return s;
+  std::vector<double2> hs((size_t)nE * 2 * MM), hw;
+  std::vector<double> hg;
+  std::vector<int> hi((size_t)nE * 2);
+  QTX_HIP(c, hipMemcpyAsync(hs.data(), c->sig.p, hs.size() * sizeof(double2), hipMemcpyDeviceToHost, c->stream));
+  if (wfac) {
+    hw.resize((size_t)nE * 2 * MM);
+    QTX_HIP(c, hipMemcpyAsync(hw.data(), c->wf.p, hw.size() * sizeof(double2), hipMemcpyDeviceToHost, c->stream));
+  }
+  if (sgn) {
+    hg.resize((size_t)nE * 2 * M);
+    QTX_HIP(c, hipMemcpyAsync(hg.data(), c->sgn.p, hg.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  }
+  QTX_HIP(c, hipMemcpyAsync(hi.data(), c->iters.p, hi.size() * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  QTX_HIP(c, hipStreamSynchronize(c->stream));
+  bool notconv = false;
+  for (int e = 0; e < nE; ++e)
+    for (int sd = 0; sd < 2; ++sd) {
+      const size_t b = ((size_t)e * 2 + sd);
+      for (int r = 0; r < m; ++r)
+        for (int q = 0; q < m; ++q) {
+          const double2 v = hs[b * MM + (size_t)r * M + q];
+          sigma[b * m * m + (size_t)r * m + q] = qtx_c128{v.x, v.y};
+          if (wfac) {
+            const double2 u = hw[b * MM + (size_t)r * M + q];
+            wfac[b * m * m + (size_t)r * m + q] = qtx_c128{u.x, u.y};
+          }
+        }
+      if (sgn)
+        for (int q = 0; q < m; ++q) sgn[b * m + q] = hg[b * M + q];
+      notconv |= hi[b] < 0;
+    }
+  if (iters)
+    for (int e = 0; e < nE; ++e) iters[e] = std::max(hi[2 * e], hi[2 * e + 1]) < 0 ? -1 : std::max(hi[2 * e], hi[2 * e + 1]);
+  if (notconv) return fail(c, QTX_ENOTCONV, "decimation hit its iteration cap for some energy");
+  return QTX_OK;
+}
+
+qtx_status qtx_problem_create(qtx_ctx* parent, qtx_ctx** problem) {
+  if (!parent || !problem) return QTX_EINVAL;
+  *problem = nullptr;
+  qtx_ctx* c = new qtx_ctx();
+  c->device = parent->device;
+  c->num_cu = parent->num_cu;
+  c->stream = parent->stream;
+  c->own_stream = false;
+  c->parent = parent;
+  *problem = c;
+  return QTX_OK;
+}
+
+qtx_status qtx_solve_batch(qtx_ctx* c, int nprob, qtx_ctx* const* probs, const double* const* E, const int* nE,
+                           double eta, qtx_precision prec, double* const* T, double* const* ldos) {
+  if (!c) return QTX_EINVAL;
+  if (nprob < 0 || (nprob > 0 && (!probs || !E || !nE || !T))) return fail(c, QTX_EINVAL, "bad batch arguments");
+  qtx_status worst = QTX_OK;
+  for (int p = 0; p < nprob; ++p) {
+    if (!probs[p]) return fail(c, QTX_EINVAL, "NULL problem in batch");
+    qtx_ctx* q = probs[p];
+    q->stream = c->stream;
+    qtx_status s = qtx_solve(q, E[p], nE[p], eta, prec, T[p], ldos ? ldos[p] : nullptr, nullptr);
+    if (s == QTX_ENOTCONV) worst = QTX_ENOTCONV;
+    else if (s != QTX_OK) return fail(c, s, std::string("problem ") + std::to_string(p) + ": " + q->err);
+  }
+  return worst;
+}
+
+qtx_status qtx_charge(const double* ldos, const double* w, int nE, int N, const double* E, double muL, double muR,
+                      double kT, double* charge) {
+  if (!ldos || !w || !E || !charge || nE < 0 || N < 1 || !(kT > 0.0)) return QTX_EINVAL;
+  for (int i = 0; i < N; ++i) charge[i] = 0.0;
+  for (int k = 0; k < nE; ++k) {
+    const double fL = 1.0 / (1.0 + std::exp((E[k] - muL) / kT));
+    const double fR = 1.0 / (1.0 + std::exp((E[k] - muR) / kT));
+    for (int i = 0; i < N; ++i)
+      charge[i] += w[k] * (fL * ldos[((size_t)k * 2 + 0) * N + i] + fR * ldos[((size_t)k * 2 + 1) * N + i]);
+  }
+  return QTX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,237 @@
+// Device-side building blocks for the transport kernels (gfx950, wave64).
+//
+// Complex numbers are kept as interleaved pairs in global memory and as
+// separate real/imaginary MFMA accumulators in registers.  A complex GEMM
+// tile uses four real MFMAs per k-slice:
+//   Cr += Ar Br - Ai Bi,   Ci += Ar Bi + Ai Br.
+//
+// MFMA 16x16x4 operand layouts (lane l, g = l / 16, c = l % 16):
+//   A operand: A[c][g], B operand: B[g][c] (both precisions);
+//   accumulator register r holds D[4r + g][c] for f64 and D[4g + r][c] for f32.
+// Within a 16-wide k block we let lane group g carry k = 4g + s in the s-th
+// MFMA, so each lane reads four consecutive k of one A row.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qtx {
+
+constexpr int NT = 256;          // threads per workgroup (4 wave64)
+constexpr int NWAVE = NT / 64;
+
+template <typename R> struct cpx { R re, im; };
+
+template <typename R> struct vec2t;
+template <> struct vec2t<double> { typedef double2 type; };
+template <> struct vec2t<float> { typedef float2 type; };
+
+template <typename R>
+__device__ __forceinline__ cpx<R> mk(R re, R im) { cpx<R> z; z.re = re; z.im = im; return z; }
+template <typename R>
+__device__ __forceinline__ cpx<R> cadd(cpx<R> a, cpx<R> b) { return mk<R>(a.re + b.re, a.im + b.im); }
+template <typename R>
+__device__ __forceinline__ cpx<R> csub(cpx<R> a, cpx<R> b) { return mk<R>(a.re - b.re, a.im - b.im); }
+template <typename R>
+__device__ __forceinline__ cpx<R> cmul(cpx<R> a, cpx<R> b) {
+  return mk<R>(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+// a - f * p
+template <typename R>
+__device__ __forceinline__ cpx<R> cfms(cpx<R> a, cpx<R> f, cpx<R> p) {
+  return mk<R>(a.re - f.re * p.re + f.im * p.im, a.im - f.re * p.im - f.im * p.re);
+}
+template <typename R>
+__device__ __forceinline__ cpx<R> cconj(cpx<R> a) { return mk<R>(a.re, -a.im); }
+template <typename R>
+__device__ __forceinline__ cpx<R> cinv(cpx<R> a) {
+  R d = a.re * a.re + a.im * a.im;
+  return mk<R>(a.re / d, -a.im / d);
+}
+template <typename R>
+__device__ __forceinline__ R cabs1(cpx<R> a) { return fabs(a.re) + fabs(a.im); }
+
+template <typename R>
+__device__ __forceinline__ cpx<R> ld2(const typename vec2t<R>::type* p) {
+  typename vec2t<R>::type v = *p;
+  return mk<R>(v.x, v.y);
+}
+template <typename R>
+__device__ __forceinline__ void st2(typename vec2t<R>::type* p, cpx<R> a) {
+  typename vec2t<R>::type v;
+  v.x = a.re;
+  v.y = a.im;
+  *p = v;
+}
+__device__ __forceinline__ cpx<double> ldd(const double2* p) { double2 v = *p; return mk<double>(v.x, v.y); }
+
+template <typename R> struct mf;
+template <> struct mf<double> {
+  typedef double acc __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ acc op(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int r, int g) { return 4 * r + g; }
+};
+template <> struct mf<float> {
+  typedef float acc __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ acc op(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int r, int g) { return 4 * g + r; }
+};
+
+template <typename R> struct ctile {
+  typename mf<R>::acc re, im;
+};
+
+template <typename R>
+__device__ __forceinline__ void tzero(ctile<R>& t) {
+  for (int r = 0; r < 4; ++r) { t.re[r] = 0; t.im[r] = 0; }
+}
+
+// acc += a * b for one k (per lane operands)
+template <typename R>
+__device__ __forceinline__ void cmac(ctile<R>& t, cpx<R> a, cpx<R> b) {
+  t.re = mf<R>::op(a.re, b.re, t.re);
+  t.re = mf<R>::op(-a.im, b.im, t.re);
+  t.im = mf<R>::op(a.re, b.im, t.im);
+  t.im = mf<R>::op(a.im, b.re, t.im);
+}
+
+// ---------------------------------------------------------------- operands
+// A operand loaders: frag4(row, k0, out) -> out[s] = A[row][k0 + s].
+// B operand loaders: get(k, col) -> B[k][col].
+
+template <typename R> struct ALds {            // row-major in LDS
+  const cpx<R>* p; int S;
+  __device__ __forceinline__ void frag4(int row, int k0, cpx<R>* o) const {
+    const cpx<R>* q = p + row * S + k0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) o[s] = q[s];
+  }
+};
+
+template <typename R> struct AGlob {           // row-major global, optionally negated
+  const typename vec2t<R>::type* p; int ld; R sgn;
+  __device__ __forceinline__ void frag4(int row, int k0, cpx<R>* o) const {
+    const typename vec2t<R>::type* q = p + (size_t)row * ld + k0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) { cpx<R> v = ld2<R>(q + s); o[s] = mk<R>(sgn * v.re, sgn * v.im); }
+  }
+};
+
+template <typename R> struct AGlobCT {         // A[row][k] = conj(P[k][row]) (FP64 source)
+  const double2* p; int ld;
+  __device__ __forceinline__ void frag4(int row, int k0, cpx<R>* o) const {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      cpx<double> v = ldd(p + (size_t)(k0 + s) * ld + row);
+      o[s] = mk<R>((R)v.re, (R)-v.im);
+    }
+  }
+};
+
+// A[row][k] = sg * (zv * conj(S[k][row]) - conj(H[k][row])): the coupling
+// block back from slab i+1 to slab i, built from the forward blocks.
+template <typename R> struct AGenCT {
+  const double2* S; const double2* H; cpx<double> zv; double sg; int M;
+  __device__ __forceinline__ void frag4(int row, int k0, cpx<R>* o) const {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      cpx<double> sv = ldd(S + (size_t)(k0 + s) * M + row);
+      cpx<double> hv = ldd(H + (size_t)(k0 + s) * M + row);
+      double re = zv.re * sv.re + zv.im * sv.im - hv.re;
+      double im = zv.im * sv.re - zv.re * sv.im + hv.im;
+      o[s] = mk<R>((R)(sg * re), (R)(sg * im));
+    }
+  }
+};
+
+template <typename R> struct BGlob {
+  const typename vec2t<R>::type* p; int ld;
+  __device__ __forceinline__ cpx<R> get(int k, int col) const { return ld2<R>(p + (size_t)k * ld + col); }
+};
+
+template <typename R> struct BGlobD {          // FP64 source, cast to R
+  const double2* p; int ld;
+  __device__ __forceinline__ cpx<R> get(int k, int col) const {
+    cpx<double> v = ldd(p + (size_t)k * ld + col);
+    return mk<R>((R)v.re, (R)v.im);
+  }
+};
+
+// B[k][col] = zv * S[k][col] - H[k][col]
+template <typename R> struct BGen {
+  const double2* S; const double2* H; cpx<double> zv; int M;
+  __device__ __forceinline__ cpx<R> get(int k, int col) const {
+    cpx<double> sv = ldd(S + (size_t)k * M + col);
+    cpx<double> hv = ldd(H + (size_t)k * M + col);
+    return mk<R>((R)(zv.re * sv.re - zv.im * sv.im - hv.re), (R)(zv.re * sv.im + zv.im * sv.re - hv.im));
+  }
+};
+
+// acc[ti] (ti = 0..MT-1, a full column of tiles) += A[:, 0:16*KT] * B[0:16*KT, tile tj]
+template <typename R, int MT, int KT, class AF, class BF>
+__device__ __forceinline__ void cgemm_col(ctile<R> (&acc)[MT], const AF& A, const BF& B, int tj) {
+  const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
+#pragma unroll 1
+  for (int kb = 0; kb < KT; ++kb) {
+    cpx<R> b[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) b[s] = B.get(16 * kb + 4 * g + s, 16 * tj + c);
+#pragma unroll
+    for (int ti = 0; ti < MT; ++ti) {
+      cpx<R> a[4];
+      A.frag4(16 * ti + c, 16 * kb + 4 * g, a);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) cmac(acc[ti], a[s], b[s]);
+    }
+  }
+}
+
+// Visit the elements held by this lane in a column of tiles:
+// fn(row, col, re, im, ti, r).
+template <typename R, int MT, class F>
+__device__ __forceinline__ void tiles_foreach(ctile<R> (&acc)[MT], int tj, F fn) {
+  const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
+#pragma unroll
+  for (int ti = 0; ti < MT; ++ti)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) fn(16 * ti + mf<R>::row(r, g), 16 * tj + c, ti, r);
+}
+
+// ------------------------------------------------------------ reductions
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
+  uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+  lo = __shfl_xor(lo, m, 64);
+  hi = __shfl_xor(hi, m, 64);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    uint64_t o = shfl_xor_u64(v, m);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_maxd(double v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v = fmax(v, __shfl_xor(v, m, 64));
+  return v;
+}
+
+// Pivot key: larger magnitude wins, ties go to the smaller row index; used
+// rows get key 0 and lose to every unused row.
+template <typename R>
+__device__ __forceinline__ uint64_t pivot_key(cpx<R> v, int idx, int M) {
+  float mag = (float)cabs1(v);
+  return ((uint64_t)__float_as_uint(mag) << 32) | (uint32_t)(M - idx);
+}
+
+}  // namespace qtx

@@ -1,0 +1,130 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle.
+
+Tolerances (FP64 path): |dT| <= 1e-10 absolute per energy; slab densities
+|dn| <= 1e-9 * max(1, max_i |n_i|) per energy and contact.  The inputs are
+the seeded synthetic workloads; the oracle runs live on the same arrays.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import leads as oleads
+from paper_1903_00548_amd import _lib
+from paper_1903_00548_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL_T = 1e-10
+TOL_N = 1e-9
+
+
+def _ctx(dev):
+    return _lib.context_for(dev, 0)
+
+
+def _check(T, L, Tref, Lref, tolT=TOL_T, tolN=TOL_N, label=""):
+    dT = np.abs(T - Tref)
+    scale = np.maximum(1.0, np.abs(Lref).max(axis=2))      # (nE, 2)
+    dn = (np.abs(L - Lref).max(axis=2) / scale)
+    worst = int(np.argmax(dT))
+    assert np.all(np.isfinite(T)) and np.all(np.isfinite(L)), label
+    assert dT.max() <= tolT, f"{label} max|dT|={dT.max():.3e} at energy index {worst}"
+    assert dn.max() <= tolN, f"{label} max rel|dn|={dn.max():.3e}"
+    return dT.max(), dn.max()
+
+
+def test_self_energy_cfg0_matches_complex_band_structure(gpu_lib):
+    wl = W.config0()
+    dev = wl.device
+    ctx = _ctx(dev)
+    E = wl.E
+    sig, Wf, s, it = ctx.self_energy(E, wl.eta)
+    ld = (dev.lead_L.H00, dev.lead_L.H01, dev.lead_L.S00, dev.lead_L.S01, dev.lead_L.V)
+    for k, e in enumerate(E):
+        sL, sR = oleads.self_energies(e + 1j * wl.eta, ld, ld, wl.eta)
+        assert np.abs(sig[k, 0] - sL).max() < 1e-9, (k, e)
+        assert np.abs(sig[k, 1] - sR).max() < 1e-9, (k, e)
+        for side, sg in ((0, sL), (1, sR)):
+            gam = oleads.broadening(sig[k, side])
+            rec = (Wf[k, side] * s[k, side][None, :]) @ Wf[k, side].conj().T
+            assert np.abs(rec - gam).max() < 1e-13 * max(1.0, np.abs(gam).max())
+        assert 5 <= it[k] <= 60
+
+
+def test_solve_cfg0_fp64(gpu_lib):
+    wl = W.config0()
+    dev = wl.device
+    ctx = _ctx(dev)
+    T, L, info, st = ctx.solve(wl.E, wl.eta, _lib.FP64)
+    assert st == _lib.OK
+    Tref, Lref = oracle.solve_device(dev, wl.E, wl.eta)
+    _check(T, L, Tref, Lref, label="cfg0")
+    assert np.all(info["flags"] == 0)
+
+
+@pytest.mark.parametrize("seed,N,m,uniform,same,mode", [
+    (1, 5, 4, True, True, W.POT_LINEAR_FE),
+    (2, 9, 6, False, False, W.POT_LINEAR_FE),
+    (3, 1, 16, False, False, W.POT_DIAG),          # a single slab: both contacts on one block
+    (4, 2, 16, True, False, W.POT_LINEAR_FE),
+    (5, 33, 20, False, True, W.POT_DIAG),          # ragged m (padded to 32), more slabs than tiles
+    (6, 17, 48, True, True, W.POT_LINEAR_FE),
+    (7, 12, 64, False, False, W.POT_LINEAR_FE),
+    (8, 3, 1, True, True, W.POT_DIAG),             # one-band chain
+])
+def test_solve_small_devices_fp64(gpu_lib, seed, N, m, uniform, same, mode):
+    dev = W.small_random_device(seed, N, m, uniform=uniform, same_leads=same, pot_mode=mode,
+                                VL=0.04 * (seed % 3), VR=-0.03 * (seed % 2))
+    E = np.linspace(-2.0, 2.0, 23)
+    ctx = _ctx(dev)
+    T, L, info, st = ctx.solve(E, 1e-6, _lib.FP64)
+    Tref, Lref = oracle.solve_device(dev, E, 1e-6)
+    _check(T, L, Tref, Lref, label=f"seed{seed}")
+
+
+def test_cfg1_full_size_sampled(gpu_lib):
+    """The headline workload at full size (2048 energies in one call, the
+    launch configuration the benchmark times); 12 energies are checked
+    against the oracle one by one, and every output must be finite."""
+    wl = W.config1()
+    dev = wl.device
+    ctx = _ctx(dev)
+    T, L, info, st = ctx.solve(wl.E, wl.eta, _lib.FP64)
+    assert st == _lib.OK
+    assert np.all(np.isfinite(T)) and np.all(np.isfinite(L))
+    assert np.all(T > -1e-9)
+    rng = np.random.default_rng(1234)
+    idx = np.sort(np.concatenate([[0, len(wl.E) - 1], rng.choice(len(wl.E), 10, replace=False)]))
+    Tref, Lref = oracle.solve_device(dev, wl.E[idx], wl.eta)
+    _check(T[idx], L[idx], Tref, Lref, label="cfg1")
+    assert np.all(info["dec_iters"] > 0)
+
+
+def test_repeatable_bitwise(gpu_lib):
+    wl = W.config0()
+    ctx = _ctx(wl.device)
+    a = ctx.solve(wl.E, wl.eta, _lib.FP64)
+    b = ctx.solve(wl.E, wl.eta, _lib.FP64)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_empty_grid_and_errors(gpu_lib):
+    wl = W.config0()
+    dev = wl.device
+    ctx = _lib.Context(0)
+    # solve before the leads are set
+    with pytest.raises(_lib.QtxError) as ei:
+        ctx.solve(wl.E, wl.eta)
+    assert ei.value.status == _lib.ESTATE
+    L = dev.lead_L
+    with pytest.raises(_lib.QtxError) as ei:      # non-Hermitian H00
+        ctx.set_lead(_lib.LEFT, L.H00 + 0.1j * np.triu(np.ones_like(L.H00), 1), L.H01, L.S00, L.S01)
+    assert ei.value.status == _lib.EINVAL
+    _lib.fill(ctx, dev)
+    with pytest.raises(_lib.QtxError) as ei:      # block size mismatch
+        ctx.set_lead(_lib.RIGHT, np.eye(3), np.eye(3), np.eye(3), np.eye(3))
+    assert ei.value.status == _lib.EINVAL
+    T, Ld, info, st = ctx.solve(np.zeros(0), wl.eta)
+    assert T.shape == (0,) and st == _lib.OK
+    with pytest.raises(_lib.QtxError):
+        ctx.solve(wl.E, -1.0)
