@@ -175,6 +175,14 @@ qtx_status qtx_solve_batch(qtx_ctx* ctx, int nprob, qtx_ctx* const* probs,
 qtx_status qtx_charge(const double* ldos, const double* w, int nE, int N, const double* E,
                       double muL, double muR, double kT, double* charge);
 
+/* Per-kernel device time of the solves since the last call (ms), from HIP
+ * events recorded on the context stream around every decimation and
+ * sweep launch while recording is enabled.  enable = 1 starts recording
+ * (and clears the totals), 0 stops it; the outputs (each may be NULL)
+ * receive the totals and the number of sweep launches accumulated before
+ * this call.  Synchronises the context stream. */
+qtx_status qtx_kernel_times(qtx_ctx* ctx, int enable, double* decimate_ms, double* sweep_ms, int* launches);
+
 /* Library version string. */
 const char* qtx_version(void);
 

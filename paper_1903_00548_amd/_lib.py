@@ -52,6 +52,7 @@ _SIGS = {
     "qtx_solve_device": (c_int, [c_void_p, c_void_p, c_int, c_double, c_int, c_void_p, c_void_p, c_void_p]),
     "qtx_self_energy": (c_int, [c_void_p, c_void_p, c_int, c_double, c_void_p, c_void_p, c_void_p, c_void_p]),
     "qtx_problem_create": (c_int, [c_void_p, POINTER(c_void_p)]),
+    "qtx_kernel_times": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p]),
     "qtx_solve_batch": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_double, c_int,
                                 c_void_p, c_void_p]),
     "qtx_charge": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_double, c_double, c_double,
@@ -182,6 +183,14 @@ class Context:
         st = self.lib.qtx_self_energy(self.h, _ptr(E), nE, float(eta), _ptr(sig), _ptr(W), _ptr(s), _ptr(it))
         self._check(st, allow_notconv=True)
         return sig, W, s, it
+
+    def kernel_times(self, enable=True):
+        """(decimate_ms, sweep_ms, sweep_launches) accumulated since the
+        previous call; enable=True keeps recording for later solves."""
+        d, s_, n = c_double(), c_double(), c_int()
+        self._check(self.lib.qtx_kernel_times(self.h, int(enable), ctypes.byref(d), ctypes.byref(s_),
+                                              ctypes.byref(n)))
+        return d.value, s_.value, n.value
 
     def problem(self):
         h = c_void_p()

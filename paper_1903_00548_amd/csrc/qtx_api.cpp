@@ -67,6 +67,11 @@ struct qtx_ctx {
   DevBuf wE, wT, wldos, winfo;
   DevBuf sig, wf, sgn, iters, dscr, sws, part;
 
+  // kernel timing: event pairs around decimation / sweep launches
+  bool timing = false;
+  std::vector<hipEvent_t> ev_dec, ev_sw;   // start/stop pairs
+  size_t n_dec = 0, n_sw = 0;
+
   // tunables
   double dec_tol = 1e-14;
   int dec_maxit = 60;
@@ -79,6 +84,17 @@ namespace {
 qtx_status fail(qtx_ctx* c, qtx_status s, const std::string& msg) {
   if (c) c->err = msg;
   return s;
+}
+
+hipError_t record(qtx_ctx* c, std::vector<hipEvent_t>& v, size_t& n) {
+  if (!c->timing) return hipSuccess;
+  if (n >= v.size()) {
+    hipEvent_t e;
+    hipError_t err = hipEventCreate(&e);
+    if (err != hipSuccess) return err;
+    v.push_back(e);
+  }
+  return hipEventRecord(v[n++], c->stream);
 }
 
 qtx_status hipfail(qtx_ctx* c, hipError_t e, const char* what) {
@@ -165,11 +181,13 @@ qtx_status stage_decimate(qtx_ctx* c, const double* E_dev, int nE, double eta) {
   QTX_HIP(c, c->wf.ensure((size_t)nE * 2 * MM * sizeof(double2)));
   QTX_HIP(c, c->sgn.ensure((size_t)nE * 2 * M * sizeof(double)));
   QTX_HIP(c, c->iters.ensure((size_t)nE * 2 * sizeof(int)));
-  QTX_HIP(c, c->dscr.ensure((size_t)grid * 9 * MM * sizeof(double2)));
+  QTX_HIP(c, c->dscr.ensure((size_t)grid * 11 * MM * sizeof(double2)));
   qtx::Prob P = make_prob(c);
+  QTX_HIP(c, record(c, c->ev_dec, c->n_dec));
   QTX_HIP(c, qtx::run_decimate(M, P, E_dev, nE, eta, sides, c->dec_tol, c->dec_maxit, c->dscr.as<double2>(),
                                grid, c->sig.as<double2>(), c->wf.as<double2>(), c->sgn.as<double>(),
                                c->iters.as<int>(), c->stream));
+  QTX_HIP(c, record(c, c->ev_dec, c->n_dec));
   return QTX_OK;
 }
 
@@ -192,11 +210,13 @@ qtx_status solve_device_core(qtx_ctx* c, const double* E_dev, int nE, double eta
     QTX_HIP(c, c->sws.ensure((size_t)grid * ws_stride * esz));
     QTX_HIP(c, c->part.ensure((size_t)grid * 4 * 2 * N * sizeof(double)));
     qtx::Prob P = make_prob(c);
+    QTX_HIP(c, record(c, c->ev_sw, c->n_sw));
     QTX_HIP(c, qtx::run_sweep(M, fp32, P, E_dev + e0, ne, eta, c->sig.as<double2>(), c->wf.as<double2>(),
                               c->sgn.as<double>(), c->iters.as<int>(), c->sws.p, ws_stride,
                               c->part.as<double>(), grid, T_dev + e0,
                               ldos_dev ? ldos_dev + (size_t)e0 * 2 * N : nullptr,
                               info_dev ? info_dev + e0 : nullptr, c->stream));
+    QTX_HIP(c, record(c, c->ev_sw, c->n_sw));
   }
   return QTX_OK;
 }
@@ -231,6 +251,8 @@ void qtx_destroy(qtx_ctx* c) {
   if (!c) return;
   hipSetDevice(c->device);
   if (c->stream) hipStreamSynchronize(c->stream);
+  for (hipEvent_t e : c->ev_dec) hipEventDestroy(e);
+  for (hipEvent_t e : c->ev_sw) hipEventDestroy(e);
   DevBuf* bufs[] = {&c->dlead[0], &c->dlead[1], &c->ddev, &c->dV, &c->wE, &c->wT, &c->wldos, &c->winfo,
                     &c->sig, &c->wf, &c->sgn, &c->iters, &c->dscr, &c->sws, &c->part};
   for (DevBuf* b : bufs) b->release();
@@ -438,6 +460,29 @@ qtx_status qtx_self_energy(qtx_ctx* c, const double* E, int nE, double eta, qtx_
   if (iters)
     for (int e = 0; e < nE; ++e) iters[e] = std::max(hi[2 * e], hi[2 * e + 1]) < 0 ? -1 : std::max(hi[2 * e], hi[2 * e + 1]);
   if (notconv) return fail(c, QTX_ENOTCONV, "decimation hit its iteration cap for some energy");
+  return QTX_OK;
+}
+
+qtx_status qtx_kernel_times(qtx_ctx* c, int enable, double* decimate_ms, double* sweep_ms, int* launches) {
+  if (!c) return QTX_EINVAL;
+  hipSetDevice(c->device);
+  QTX_HIP(c, hipStreamSynchronize(c->stream));
+  double td = 0.0, ts = 0.0;
+  for (size_t k = 0; k + 1 < c->n_dec; k += 2) {
+    float ms = 0.0f;
+    QTX_HIP(c, hipEventElapsedTime(&ms, c->ev_dec[k], c->ev_dec[k + 1]));
+    td += ms;
+  }
+  for (size_t k = 0; k + 1 < c->n_sw; k += 2) {
+    float ms = 0.0f;
+    QTX_HIP(c, hipEventElapsedTime(&ms, c->ev_sw[k], c->ev_sw[k + 1]));
+    ts += ms;
+  }
+  if (decimate_ms) *decimate_ms = td;
+  if (sweep_ms) *sweep_ms = ts;
+  if (launches) *launches = (int)(c->n_sw / 2);
+  c->n_dec = c->n_sw = 0;
+  c->timing = enable != 0;
   return QTX_OK;
 }
 

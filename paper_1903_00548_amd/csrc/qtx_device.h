@@ -104,30 +104,22 @@ __device__ __forceinline__ void cmac(ctile<R>& t, cpx<R> a, cpx<R> b) {
 
 template <typename R> struct ALds {            // row-major in LDS
   const cpx<R>* p; int S;
-  __device__ __forceinline__ void frag4(int row, int k0, cpx<R>* o) const {
-    const cpx<R>* q = p + row * S + k0;
-#pragma unroll
-    for (int s = 0; s < 4; ++s) o[s] = q[s];
-  }
+  __device__ __forceinline__ cpx<R> get(int row, int k) const { return p[row * S + k]; }
 };
 
 template <typename R> struct AGlob {           // row-major global, optionally negated
   const typename vec2t<R>::type* p; int ld; R sgn;
-  __device__ __forceinline__ void frag4(int row, int k0, cpx<R>* o) const {
-    const typename vec2t<R>::type* q = p + (size_t)row * ld + k0;
-#pragma unroll
-    for (int s = 0; s < 4; ++s) { cpx<R> v = ld2<R>(q + s); o[s] = mk<R>(sgn * v.re, sgn * v.im); }
+  __device__ __forceinline__ cpx<R> get(int row, int k) const {
+    cpx<R> v = ld2<R>(p + (size_t)row * ld + k);
+    return mk<R>(sgn * v.re, sgn * v.im);
   }
 };
 
 template <typename R> struct AGlobCT {         // A[row][k] = conj(P[k][row]) (FP64 source)
   const double2* p; int ld;
-  __device__ __forceinline__ void frag4(int row, int k0, cpx<R>* o) const {
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      cpx<double> v = ldd(p + (size_t)(k0 + s) * ld + row);
-      o[s] = mk<R>((R)v.re, (R)-v.im);
-    }
+  __device__ __forceinline__ cpx<R> get(int row, int k) const {
+    cpx<double> v = ldd(p + (size_t)k * ld + row);
+    return mk<R>((R)v.re, (R)-v.im);
   }
 };
 
@@ -135,16 +127,18 @@ template <typename R> struct AGlobCT {         // A[row][k] = conj(P[k][row]) (F
 // block back from slab i+1 to slab i, built from the forward blocks.
 template <typename R> struct AGenCT {
   const double2* S; const double2* H; cpx<double> zv; double sg; int M;
-  __device__ __forceinline__ void frag4(int row, int k0, cpx<R>* o) const {
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      cpx<double> sv = ldd(S + (size_t)(k0 + s) * M + row);
-      cpx<double> hv = ldd(H + (size_t)(k0 + s) * M + row);
-      double re = zv.re * sv.re + zv.im * sv.im - hv.re;
-      double im = zv.im * sv.re - zv.re * sv.im + hv.im;
-      o[s] = mk<R>((R)(sg * re), (R)(sg * im));
-    }
+  __device__ __forceinline__ cpx<R> get(int row, int k) const {
+    cpx<double> sv = ldd(S + (size_t)k * M + row);
+    cpx<double> hv = ldd(H + (size_t)k * M + row);
+    double re = zv.re * sv.re + zv.im * sv.im - hv.re;
+    double im = zv.im * sv.re - zv.re * sv.im + hv.im;
+    return mk<R>((R)(sg * re), (R)(sg * im));
   }
+};
+
+template <typename R> struct BLds {            // row-major in LDS
+  const cpx<R>* p; int ld;
+  __device__ __forceinline__ cpx<R> get(int k, int col) const { return p[k * ld + col]; }
 };
 
 template <typename R> struct BGlob {
@@ -170,22 +164,46 @@ template <typename R> struct BGen {
   }
 };
 
-// acc[ti] (ti = 0..MT-1, a full column of tiles) += A[:, 0:16*KT] * B[0:16*KT, tile tj]
+// acc[ti] (ti = 0..MT-1, a full column of tiles) += A[:, 0:16*KT] * B[0:16*KT, tile tj].
+// One k-slice per step (lane group g carries k = 16 kb + 4 g + s); the
+// operands of the next slice are loaded while the MFMAs of the current one
+// run, and the real/imaginary chains of the MT tiles are interleaved so that
+// no MFMA waits on the accumulator of the one before it.
 template <typename R, int MT, int KT, class AF, class BF>
 __device__ __forceinline__ void cgemm_col(ctile<R> (&acc)[MT], const AF& A, const BF& B, int tj) {
   const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
-#pragma unroll 1
-  for (int kb = 0; kb < KT; ++kb) {
-    cpx<R> b[4];
+  const int col = 16 * tj + c;
+  cpx<R> bq, aq[MT];
+  {
+    const int k = 4 * g;
+    bq = B.get(k, col);
 #pragma unroll
-    for (int s = 0; s < 4; ++s) b[s] = B.get(16 * kb + 4 * g + s, 16 * tj + c);
+    for (int ti = 0; ti < MT; ++ti) aq[ti] = A.get(16 * ti + c, k);
+  }
+#pragma unroll 2
+  for (int it = 0; it < 4 * KT; ++it) {
+    cpx<R> bn = bq, an[MT];
+#pragma unroll
+    for (int ti = 0; ti < MT; ++ti) an[ti] = aq[ti];
+    if (it + 1 < 4 * KT) {
+      const int k = 16 * ((it + 1) >> 2) + 4 * g + ((it + 1) & 3);
+      bn = B.get(k, col);
+#pragma unroll
+      for (int ti = 0; ti < MT; ++ti) an[ti] = A.get(16 * ti + c, k);
+    }
 #pragma unroll
     for (int ti = 0; ti < MT; ++ti) {
-      cpx<R> a[4];
-      A.frag4(16 * ti + c, 16 * kb + 4 * g, a);
-#pragma unroll
-      for (int s = 0; s < 4; ++s) cmac(acc[ti], a[s], b[s]);
+      acc[ti].re = mf<R>::op(aq[ti].re, bq.re, acc[ti].re);
+      acc[ti].im = mf<R>::op(aq[ti].re, bq.im, acc[ti].im);
     }
+#pragma unroll
+    for (int ti = 0; ti < MT; ++ti) {
+      acc[ti].re = mf<R>::op(-aq[ti].im, bq.im, acc[ti].re);
+      acc[ti].im = mf<R>::op(aq[ti].im, bq.re, acc[ti].im);
+    }
+    bq = bn;
+#pragma unroll
+    for (int ti = 0; ti < MT; ++ti) aq[ti] = an[ti];
   }
 }
 
@@ -224,6 +242,38 @@ __device__ __forceinline__ double wave_maxd(double v) {
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) v = fmax(v, __shfl_xor(v, m, 64));
   return v;
+}
+
+// Max over the 64 lanes of a wave with DPP row shifts and row broadcasts;
+// the result (lane 63) is returned wave-uniform.
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+  uint32_t o;
+  o = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false); v = o > v ? o : v;  // row_shr:1
+  o = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false); v = o > v ? o : v;  // row_shr:2
+  o = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false); v = o > v ? o : v;  // row_shr:4
+  o = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false); v = o > v ? o : v;  // row_shr:8
+  o = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false); v = o > v ? o : v;  // row_bcast:15
+  o = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false); v = o > v ? o : v;  // row_bcast:31
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(x & 0xffffffff), l);
+  const int hi = __builtin_amdgcn_readlane((int)(x >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ float readlane_d(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+// 32-bit pivot key: magnitude (float, low 8 mantissa bits dropped) above
+// 255 - row, so ties within 2^-15 relative go to the smaller row; used
+// rows take key 0.  Rows < 128.
+template <typename R>
+__device__ __forceinline__ uint32_t pivot_key32(cpx<R> v, int row) {
+  const float mag = (float)cabs1(v);
+  return (__float_as_uint(mag) & 0xffffff00u) | (uint32_t)(255 - row);
 }
 
 // Pivot key: larger magnitude wins, ties go to the smaller row index; used

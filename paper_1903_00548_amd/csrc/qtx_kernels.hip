@@ -12,95 +12,152 @@
 namespace qtx {
 
 // ------------------------------------------------------------ Gauss-Jordan
-// The matrix is distributed over a 16 x 16 grid of lanes (thread t owns rows
-// [b*(t/16), +b) and columns [b*(t%16), +b), b = M/16).  Each pivot step
-// publishes the pivot column and the scaled pivot row through LDS; the pivot
-// is the largest |re|+|im| among unused rows (partial pivoting without
-// physical row exchanges; the permutation is undone when the result is
-// written back).
+// Blocked Gauss-Jordan elimination with partial pivoting (no physical row
+// exchanges; the permutation is undone on the way out).  For each panel of
+// 16 columns one wave eliminates the panel in registers (one matrix row per
+// lane, pivot search by a DPP max reduction, no workgroup barrier), leaving
+// in the panel G = E e_p, the panel transform applied to the unit vectors of
+// its pivot rows.  Every other column x is then updated by
+//   x' = x (pivot rows of the panel zeroed) + G y,   y_jj = x[p_jj],
+// as 16x16 complex MFMA tiles shared by all waves.
 
-template <typename R, int M> struct GJScratch {
-  cpx<R> col[2][M];
-  cpx<R> row[M];
-  int piv[M];
+template <typename R, int M> struct BGJ {
+  int piv[M];        // pivot row chosen for column j
   int pinv[M];
+  int ppanel[M];     // panel in which row r became a pivot, -1 before
+  cpx<R> prow[16];   // pivot row of the current step (panel part)
 };
 
+// Wave-level elimination of panel k (columns 16k..16k+15) of the LDS matrix.
+// The step loop is unrolled (static column index) with a scheduling barrier
+// after every step so that steps do not interleave; the pivot lane
+// publishes the already scaled pivot row, and the pivot row itself is
+// produced by the same fused multiply-subtract as the others (base 0,
+// factor -1).
 template <typename R, int M>
-__device__ __forceinline__ int gj_pick_pivot(const cpx<R>* col, bool& used0, bool& used1) {
+__device__ void gj_panel(cpx<R>* mat, int S, int k, BGJ<R, M>& sc) {
+  constexpr int RL = (M + 63) / 64;  // rows per lane
   const int lane = threadIdx.x & 63;
-  uint64_t key = 0;
-  if (lane < M && !used0) key = pivot_key(col[lane], lane, M);
-  if (M > 64 && lane + 64 < M && !used1) {
-    uint64_t k2 = pivot_key(col[lane + 64], lane + 64, M);
-    key = k2 > key ? k2 : key;
+  cpx<R> pr[RL][16];
+  bool used[RL];
+#pragma unroll
+  for (int q = 0; q < RL; ++q) {
+    const int r = lane + 64 * q;
+    const bool ok = r < M;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) pr[q][c] = ok ? mat[r * S + 16 * k + c] : mk<R>(0, 0);
+    used[q] = !ok || sc.ppanel[r] >= 0;
   }
-  key = wave_max_u64(key);
-  const int p = M - (int)(uint32_t)key;
-  if (lane == p) used0 = true;
-  if (lane + 64 == p) used1 = true;
-  return p;
+#pragma unroll
+  for (int jj = 0; jj < 16; ++jj) {
+    uint32_t key = 0;
+#pragma unroll
+    for (int q = 0; q < RL; ++q)
+      if (!used[q]) {
+        const uint32_t kq = pivot_key32(pr[q][jj], lane + 64 * q);
+        key = kq > key ? kq : key;
+      }
+    key = wave_max_u32(key);
+    const int p = 255 - (int)(key & 0xff);
+    const int pl = p & 63, pq = p >> 6;
+    bool isp[RL];
+    cpx<R> f[RL];
+#pragma unroll
+    for (int q = 0; q < RL; ++q) {
+      isp[q] = (q == pq) && (lane == pl);
+      f[q] = isp[q] ? mk<R>(-1, 0) : pr[q][jj];
+    }
+#pragma unroll
+    for (int q = 0; q < RL; ++q)
+      if (isp[q]) {
+        const cpx<R> inv = cinv(pr[q][jj]);
+#pragma unroll
+        for (int c = 0; c < 16; ++c) sc.prow[c] = (c == jj) ? inv : cmul(pr[q][c], inv);
+      }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      const cpx<R> pvc = sc.prow[c];
+#pragma unroll
+      for (int q = 0; q < RL; ++q) {
+        const cpx<R> base = (c == jj || isp[q]) ? mk<R>(0, 0) : pr[q][c];
+        pr[q][c] = cfms(base, f[q], pvc);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < RL; ++q)
+      if (isp[q]) used[q] = true;
+    if (lane == 0) {
+      sc.piv[16 * k + jj] = p;
+      sc.ppanel[p] = k;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    __builtin_amdgcn_sched_barrier(0);
+  }
+#pragma unroll
+  for (int q = 0; q < RL; ++q) {
+    const int r = lane + 64 * q;
+    if (r < M)
+#pragma unroll
+      for (int c = 0; c < 16; ++c) mat[r * S + 16 * k + c] = pr[q][c];
+  }
 }
 
-// In-place inverse of the M x M matrix in LDS (row stride S).
+// One 16x16 output tile of the panel update: X[ti, tc] <- masked X + G Y.
+template <typename R, int M, class XLoad, class XStore>
+__device__ __forceinline__ void gj_update_tile(const cpx<R>* mat, int S, int k, const cpx<R>* Y, int ldy, int ycol,
+                                               int ti, const BGJ<R, M>& sc, XLoad xl, XStore xs) {
+  ctile<R> acc[1];
+  tiles_foreach<R, 1>(acc, 0, [&](int row, int col, int, int r) {
+    const int gr = 16 * ti + row;
+    cpx<R> v = sc.ppanel[gr] == k ? mk<R>(0, 0) : xl(gr, col);
+    acc[0].re[r] = v.re;
+    acc[0].im[r] = v.im;
+  });
+  cgemm_col<R, 1, 1>(acc, ALds<R>{mat + 16 * ti * S + 16 * k, S}, BLds<R>{Y + ycol, ldy}, 0);
+  tiles_foreach<R, 1>(acc, 0, [&](int row, int col, int, int r) {
+    xs(16 * ti + row, col, mk<R>(acc[0].re[r], acc[0].im[r]));
+  });
+}
+
+// In-place inverse of the M x M LDS matrix (row stride S); Y is LDS scratch
+// of 16 x M.  Ends with a barrier.
 template <typename R, int M>
-__device__ void gj_inverse(cpx<R>* mat, int S, GJScratch<R, M>& sc) {
+__device__ void gj_inverse(cpx<R>* mat, int S, cpx<R>* Y, BGJ<R, M>& sc) {
+  constexpr int NP = M / 16, MT = M / 16;
+  const int t = threadIdx.x, w = t >> 6;
+  if (t < M) sc.ppanel[t] = -1;
+  __syncthreads();
+  for (int k = 0; k < NP; ++k) {
+    if (w == 0) gj_panel<R, M>(mat, S, k, sc);
+    __syncthreads();
+    for (int idx = t; idx < 16 * M; idx += NT) {
+      const int jj = idx / M, c = idx - jj * M;
+      if ((c >> 4) != k) Y[idx] = mat[sc.piv[16 * k + jj] * S + c];
+    }
+    __syncthreads();
+    for (int tile = w; tile < MT * (NP - 1); tile += NWAVE) {
+      const int ti = tile % MT, tcx = tile / MT, tc = tcx + (tcx >= k ? 1 : 0);
+      gj_update_tile<R, M>(
+          mat, S, k, Y, M, 16 * tc, ti, sc,
+          [&](int row, int col) { return mat[row * S + 16 * tc + col]; },
+          [&](int row, int col, cpx<R> v) { mat[row * S + 16 * tc + col] = v; });
+    }
+    __syncthreads();
+  }
+  if (t < M) sc.pinv[sc.piv[t]] = t;
+  __syncthreads();
   constexpr int b = M / 16;
-  const int t = threadIdx.x, gr = t >> 4, gc = t & 15;
+  const int gr = t >> 4, gc = t & 15;
   cpx<R> a[b][b];
 #pragma unroll
   for (int rr = 0; rr < b; ++rr)
 #pragma unroll
     for (int cc = 0; cc < b; ++cc) a[rr][cc] = mat[(b * gr + rr) * S + b * gc + cc];
-  bool used0 = false, used1 = false;
-  if (gc == 0)
-#pragma unroll
-    for (int rr = 0; rr < b; ++rr) sc.col[0][b * gr + rr] = a[rr][0];
-  for (int j = 0; j < M; ++j) {
-    const cpx<R>* col = sc.col[j & 1];
-    __syncthreads();
-    const int p = gj_pick_pivot<R, M>(col, used0, used1);
-    const cpx<R> inv = cinv(col[p]);
-    if (t == 0) sc.piv[j] = p;
-    if (gr == p / b) {
-      const int pr = p - b * gr;
-#pragma unroll
-      for (int rr = 0; rr < b; ++rr)
-        if (rr == pr)
-#pragma unroll
-          for (int cc = 0; cc < b; ++cc) {
-            const int c = b * gc + cc;
-            cpx<R> v = (c == j) ? mk<R>(1, 0) : a[rr][cc];
-            sc.row[c] = cmul(v, inv);
-          }
-    }
-    __syncthreads();
-    cpx<R> pv[b];
-#pragma unroll
-    for (int cc = 0; cc < b; ++cc) pv[cc] = sc.row[b * gc + cc];
-#pragma unroll
-    for (int rr = 0; rr < b; ++rr) {
-      const int r = b * gr + rr;
-      const cpx<R> f = col[r];
-      const bool isp = (r == p);
-#pragma unroll
-      for (int cc = 0; cc < b; ++cc) {
-        const int c = b * gc + cc;
-        cpx<R> base = (c == j) ? mk<R>(0, 0) : a[rr][cc];
-        a[rr][cc] = isp ? pv[cc] : cfms(base, f, pv[cc]);
-      }
-    }
-    if (j + 1 < M && gc == (j + 1) / b) {
-      const int jc = (j + 1) - b * gc;
-#pragma unroll
-      for (int cc = 0; cc < b; ++cc)
-        if (cc == jc)
-#pragma unroll
-          for (int rr = 0; rr < b; ++rr) sc.col[(j + 1) & 1][b * gr + rr] = a[rr][cc];
-    }
-  }
-  __syncthreads();
-  if (t < M) sc.pinv[sc.piv[t]] = t;
   __syncthreads();
 #pragma unroll
   for (int rr = 0; rr < b; ++rr)
@@ -109,87 +166,186 @@ __device__ void gj_inverse(cpx<R>* mat, int S, GJScratch<R, M>& sc) {
   __syncthreads();
 }
 
-// Gauss-Jordan solve of eps * [ga | gb] = [alpha | beta] (M x 3M augmented,
-// no explicit inverse); writes [ga | gb] row-major with leading dim 2M.
-template <int M> struct GJ3Scratch {
-  cpx<double> col[2][M];
-  cpx<double> row[3 * M];
-  int piv[M];
-  int pinv[M];
+// Blocked LU solve eps * X = B with partial pivoting (implicit row order).
+// eps (M x M) lives in LDS (row stride S), B (M x 2M, leading dimension 2M)
+// in global memory and is transformed in place; the solution rows are
+// written un-permuted to out (M x 2M).  Y is LDS scratch of 16 x 3M.
+// Panel factorisation on one wave (rows already chosen as pivots are
+// frozen), then per panel: gather the pivot rows of the live columns,
+// forward substitution with the unit lower 16x16 block, and the trailing
+// update of the remaining rows as masked MFMA tiles; finally the block
+// back substitution with the upper triangular factor.  Ends with a barrier.
+template <int M>
+__device__ void lu_panel(cpx<double>* eps, int S, int k, BGJ<double, M>& sc) {
+  const int lane = threadIdx.x & 63;
+  cpx<double> pr[16];
+  const bool ok = lane < M;
+  bool used = !ok || sc.ppanel[lane] >= 0;
+#pragma unroll
+  for (int c = 0; c < 16; ++c) pr[c] = ok ? eps[lane * S + 16 * k + c] : mk<double>(0, 0);
+#pragma unroll 1
+  for (int jj = 0; jj < 16; ++jj) {
+    cpx<double> f = pr[0];
+#pragma unroll
+    for (int c = 1; c < 16; ++c)
+      if (c == jj) f = pr[c];
+    const uint32_t key = used ? 0u : pivot_key32(f, lane);
+    const uint32_t kmax = wave_max_u32(key);
+    const int p = 255 - (int)(kmax & 0xff);
+    const cpx<double> pvt = mk<double>(readlane_d(f.re, p), readlane_d(f.im, p));
+    if (lane == p)
+#pragma unroll
+      for (int c = 0; c < 16; ++c) sc.prow[c] = pr[c];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const bool elim = !used && lane != p;
+    const cpx<double> l = cmul(f, cinv(pvt));
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      if (c > jj && elim) pr[c] = cfms(pr[c], l, sc.prow[c]);
+      if (c == jj && elim) pr[c] = l;
+    }
+    if (lane == p) used = true;
+    if (lane == 0) {
+      sc.piv[16 * k + jj] = p;
+      sc.ppanel[p] = k;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  if (ok)
+#pragma unroll
+    for (int c = 0; c < 16; ++c) eps[lane * S + 16 * k + c] = pr[c];
+}
+
+// A operand: rows of the LDS matrix restricted to columns [c0, c0+16); rows
+// whose ppanel is >= 0 and <= kmax read as zero (frozen rows).
+struct ALdsMask {
+  const cpx<double>* p; int S; int c0; const int* ppanel; int kmax; int kmin;
+  __device__ __forceinline__ cpx<double> get(int row, int k) const {
+    const int pp = ppanel[row];
+    const bool live = kmin < 0 ? !(pp >= 0 && pp <= kmax) : (pp >= 0 && pp < kmin);
+    return live ? p[row * S + c0 + k] : mk<double>(0, 0);
+  }
 };
 
 template <int M>
-__device__ void gj_solve3(const double2* eps, const double2* al, const double2* be, double2* gout,
-                          GJ3Scratch<M>& sc) {
-  constexpr int b = M / 16;
-  const int t = threadIdx.x, gr = t >> 4, gc = t & 15;
-  cpx<double> a[3][b][b];
-  const double2* src[3] = {eps, al, be};
-#pragma unroll
-  for (int q = 0; q < 3; ++q)
-#pragma unroll
-    for (int rr = 0; rr < b; ++rr)
-#pragma unroll
-      for (int cc = 0; cc < b; ++cc) a[q][rr][cc] = ldd(src[q] + (b * gr + rr) * M + b * gc + cc);
-  bool used0 = false, used1 = false;
-  if (gc == 0)
-#pragma unroll
-    for (int rr = 0; rr < b; ++rr) sc.col[0][b * gr + rr] = a[0][rr][0];
-  for (int j = 0; j < M; ++j) {
-    const cpx<double>* col = sc.col[j & 1];
+__device__ void lu_solve(cpx<double>* eps, int S, double2* B, double2* out, cpx<double>* Y, BGJ<double, M>& sc) {
+  constexpr int NP = M / 16, MT = M / 16, W = 3 * M, LB = 2 * M;
+  static_assert(3 * M - 16 <= NT, "one live column per thread");
+  const int t = threadIdx.x, w = t >> 6;
+  if (t < M) sc.ppanel[t] = -1;
+  __syncthreads();
+  // ---- forward: P A = L U, B <- L^-1 P B
+  for (int k = 0; k < NP; ++k) {
+    if (w == 0) lu_panel<M>(eps, S, k, sc);
     __syncthreads();
-    const int p = gj_pick_pivot<double, M>(col, used0, used1);
-    const cpx<double> inv = cinv(col[p]);
-    if (t == 0) sc.piv[j] = p;
-    if (gr == p / b) {
-      const int pr = p - b * gr;
-#pragma unroll
-      for (int rr = 0; rr < b; ++rr)
-        if (rr == pr)
-#pragma unroll
-          for (int q = 0; q < 3; ++q)
-#pragma unroll
-            for (int cc = 0; cc < b; ++cc) sc.row[q * M + b * gc + cc] = cmul(a[q][rr][cc], inv);
+    const int c0 = 16 * (k + 1);          // first live eps column
+    const int nl = M - c0 + LB;           // live columns: eps [c0, M), then B
+    for (int idx = t; idx < 16 * nl; idx += NT) {
+      const int jj = idx / nl, c = idx - jj * nl;
+      const int p = sc.piv[16 * k + jj];
+      Y[jj * W + c] = (c < M - c0) ? eps[p * S + c0 + c] : ldd(B + (size_t)p * LB + (c - (M - c0)));
     }
     __syncthreads();
+    // unit lower 16x16 forward substitution, one live column per thread
+    // (nl <= 3M - 16 <= NT; a loop here would let the compiler hoist all
+    // 120 loads of the triangular block out of it)
+    if (t < nl) {
+      const int c = t;
+      cpx<double> y[16];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      cpx<double> pv[b];
+      for (int a = 0; a < 16; ++a) y[a] = Y[a * W + c];
+      // column-oriented; the scheduling barriers keep the LDS loads of one
+      // column of L in flight at a time (otherwise all 120 are hoisted)
 #pragma unroll
-      for (int cc = 0; cc < b; ++cc) pv[cc] = sc.row[q * M + b * gc + cc];
+      for (int b = 0; b < 15; ++b) {
 #pragma unroll
-      for (int rr = 0; rr < b; ++rr) {
-        const int r = b * gr + rr;
-        const cpx<double> f = col[r];
-        const bool isp = (r == p);
+        for (int a = b + 1; a < 16; ++a) y[a] = cfms(y[a], eps[sc.piv[16 * k + a] * S + 16 * k + b], y[b]);
+        __builtin_amdgcn_sched_barrier(0);
+      }
 #pragma unroll
-        for (int cc = 0; cc < b; ++cc) a[q][rr][cc] = isp ? pv[cc] : cfms(a[q][rr][cc], f, pv[cc]);
+      for (int a = 0; a < 16; ++a) Y[a * W + c] = y[a];
+      if (c < M - c0) {
+#pragma unroll
+        for (int a = 0; a < 16; ++a) eps[sc.piv[16 * k + a] * S + c0 + c] = y[a];
+      } else {
+#pragma unroll
+        for (int a = 0; a < 16; ++a)
+          B[(size_t)sc.piv[16 * k + a] * LB + (c - (M - c0))] = make_double2(y[a].re, y[a].im);
       }
     }
-    if (j + 1 < M && gc == (j + 1) / b) {
-      const int jc = (j + 1) - b * gc;
+    __syncthreads();
+    // trailing update of the rows that are not pivots yet
+    const int ncol = (M - c0) / 16 + 2 * NP;
+    for (int tile = w; tile < MT * ncol; tile += NWAVE) {
+      const int ti = tile % MT, tcx = tile / MT;
+      ctile<double> acc[1];
+      const bool is_eps = tcx < (M - c0) / 16;
+      const int xc = is_eps ? c0 + 16 * tcx : 16 * (tcx - (M - c0) / 16);
+      tiles_foreach<double, 1>(acc, 0, [&](int row, int col, int, int r) {
+        const int gr = 16 * ti + row;
+        cpx<double> v = is_eps ? eps[gr * S + xc + col] : ldd(B + (size_t)gr * LB + xc + col);
+        acc[0].re[r] = -v.re;
+        acc[0].im[r] = -v.im;
+      });
+      // acc = -x + L y  (then negated on store): x - L y
+      cgemm_col<double, 1, 1>(acc, ALdsMask{eps + 16 * ti * S, S, 16 * k, sc.ppanel + 16 * ti, k, -1},
+                              BLds<double>{Y + 16 * tcx, W}, 0);
+      tiles_foreach<double, 1>(acc, 0, [&](int row, int col, int, int r) {
+        const int gr = 16 * ti + row;
+        const cpx<double> v = mk<double>(-acc[0].re[r], -acc[0].im[r]);
+        if (is_eps) eps[gr * S + xc + col] = v;
+        else B[(size_t)gr * LB + xc + col] = make_double2(v.re, v.im);
+      });
+    }
+    __syncthreads();
+  }
+  // ---- backward: U X = B, panels from the last one
+  for (int k = NP - 1; k >= 0; --k) {
+    if (t < LB) {
+      const int c = t;
+      cpx<double> y[16];
 #pragma unroll
-      for (int cc = 0; cc < b; ++cc)
-        if (cc == jc)
+      for (int a = 0; a < 16; ++a) y[a] = ldd(B + (size_t)sc.piv[16 * k + a] * LB + c);
 #pragma unroll
-          for (int rr = 0; rr < b; ++rr) sc.col[(j + 1) & 1][b * gr + rr] = a[0][rr][cc];
+      for (int b = 15; b >= 0; --b) {
+        y[b] = cmul(y[b], cinv(eps[sc.piv[16 * k + b] * S + 16 * k + b]));
+#pragma unroll
+        for (int a = 0; a < b; ++a) y[a] = cfms(y[a], eps[sc.piv[16 * k + a] * S + 16 * k + b], y[b]);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+#pragma unroll
+      for (int a = 0; a < 16; ++a) {
+        Y[a * W + c] = y[a];
+        B[(size_t)sc.piv[16 * k + a] * LB + c] = make_double2(y[a].re, y[a].im);
+      }
+    }
+    __syncthreads();
+    if (k > 0) {
+      // rows that became pivots in earlier panels: x -= U[:, panel k] y
+      for (int tile = w; tile < MT * 2 * NP; tile += NWAVE) {
+        const int ti = tile % MT, tb = tile / MT;
+        ctile<double> acc[1];
+        tiles_foreach<double, 1>(acc, 0, [&](int row, int col, int, int r) {
+          cpx<double> v = ldd(B + (size_t)(16 * ti + row) * LB + 16 * tb + col);
+          acc[0].re[r] = -v.re;
+          acc[0].im[r] = -v.im;
+        });
+        cgemm_col<double, 1, 1>(acc, ALdsMask{eps + 16 * ti * S, S, 16 * k, sc.ppanel + 16 * ti, 0, k},
+                                BLds<double>{Y + 16 * tb, W}, 0);
+        tiles_foreach<double, 1>(acc, 0, [&](int row, int col, int, int r) {
+          B[(size_t)(16 * ti + row) * LB + 16 * tb + col] = make_double2(-acc[0].re[r], -acc[0].im[r]);
+        });
+      }
+      __syncthreads();
     }
   }
-  __syncthreads();
-  if (t < M) sc.pinv[sc.piv[t]] = t;
-  __syncthreads();
-#pragma unroll
-  for (int rr = 0; rr < b; ++rr) {
-    const int orow = sc.pinv[b * gr + rr];
-#pragma unroll
-    for (int cc = 0; cc < b; ++cc) {
-      const int c = b * gc + cc;
-      double2 v1, v2;
-      v1.x = a[1][rr][cc].re; v1.y = a[1][rr][cc].im;
-      v2.x = a[2][rr][cc].re; v2.y = a[2][rr][cc].im;
-      gout[orow * 2 * M + c] = v1;
-      gout[orow * 2 * M + M + c] = v2;
-    }
+  for (int idx = t; idx < M * LB; idx += NT) {
+    const int j = idx / LB, c = idx - j * LB;
+    out[idx] = B[(size_t)sc.piv[j] * LB + c];
   }
   __syncthreads();
 }
@@ -279,24 +435,29 @@ __device__ void gamma_ldl(const double2* sig, double2* W, double* sg, LDLScratch
 // gives e' = e - a g b - b g a, a' = -a g a, b' = -b g b with g = e^-1; the
 // surface of a right lead keeps only -a g b and that of a left lead only
 // -b g a.  Sigma = D0 - (converged surface block).  g [a | b] is obtained
-// by a Gauss-Jordan solve, not from an explicit inverse: the explicit
-// inverse loses up to two extra digits when D0 is ill-conditioned.
+// by an LU solve with partial pivoting, not from an explicit inverse (nor a
+// blocked Gauss-Jordan, which inverts its 16x16 pivot blocks explicitly):
+// those lose up to two extra digits when D0 is ill-conditioned.
 template <int M>
-__global__ __launch_bounds__(NT) void k_decimate(Prob P, const double* E, int nE, double eta, int sides,
+__global__ __launch_bounds__(NT, 2) void k_decimate(Prob P, const double* E, int nE, double eta, int sides,
                                                  double tol, int maxit, double2* scratch, double2* sig,
                                                  double2* wf, double* sgn, int* iters) {
   constexpr int MT = M / 16, MM = M * M;
-  __shared__ GJ3Scratch<M> sc;
+  constexpr int S = M + 1;
+  __shared__ cpx<double> epsL[M * S];
+  __shared__ cpx<double> Ysc[16 * 3 * M];
+  __shared__ BGJ<double, M> sc;
   __shared__ LDLScratch<M> lsc;
   __shared__ double red[2][NWAVE];
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
-  double2* ws = scratch + (size_t)blockIdx.x * 9 * MM;
+  double2* ws = scratch + (size_t)blockIdx.x * 11 * MM;
   double2* eps = ws;
   double2* esL = ws + MM;
   double2* esR = ws + 2 * MM;
   double2* al[2] = {ws + 3 * MM, ws + 5 * MM};
   double2* be[2] = {ws + 4 * MM, ws + 6 * MM};
-  double2* g = ws + 7 * MM;  // M x 2M
+  double2* g = ws + 7 * MM;    // M x 2M: solution [g alpha | g beta]
+  double2* rhs = ws + 9 * MM;  // M x 2M: right-hand side being eliminated
   const int njobs = nE * sides;
   for (int job = blockIdx.x; job < njobs; job += gridDim.x) {
     const int e = job / sides;
@@ -325,7 +486,14 @@ __global__ __launch_bounds__(NT) void k_decimate(Prob P, const double* E, int nE
     int cur = 0, it = 0;
     bool conv = false;
     for (it = 1; it <= maxit; ++it) {
-      gj_solve3<M>(eps, al[cur], be[cur], g, sc);
+      for (int idx = t; idx < MM; idx += NT) {
+        const int r = idx / M, c = idx - r * M;
+        epsL[r * S + c] = ldd(eps + idx);
+        rhs[r * 2 * M + c] = al[cur][idx];
+        rhs[r * 2 * M + M + c] = be[cur][idx];
+      }
+      __syncthreads();
+      lu_solve<M>(epsL, S, rhs, g, Ysc, sc);
       double na = 0.0, nb = 0.0;
       for (int tj = w; tj < MT; tj += NWAVE) {
         ctile<double> a1[MT], a2[MT];
@@ -392,14 +560,15 @@ __global__ __launch_bounds__(NT) void k_decimate(Prob P, const double* E, int nE
 // D_i, U_i and L_i = A_{i,i-1} are generated from the stored H/S blocks and
 // the potential weights while they are loaded as MFMA operands.
 template <typename R, int M>
-__global__ __launch_bounds__(NT) void k_sweep(Prob P, const double* E, int nE, double eta,
+__global__ __launch_bounds__(NT, 2) void k_sweep(Prob P, const double* E, int nE, double eta,
                                               const double2* sig, const double2* wf, const double* sgn,
                                               const int* iters, typename vec2t<R>::type* ws, size_t ws_stride,
                                               double* part, double* T, double* ldos, qtx_info* info) {
   typedef typename vec2t<R>::type V2;
   constexpr int MT = M / 16, MM = M * M, S = M + 1, LD = 2 * M;
   __shared__ cpx<R> mat[M * S];
-  __shared__ GJScratch<R, M> sc;
+  __shared__ cpx<R> Ysc[16 * M];
+  __shared__ BGJ<R, M> sc;
   __shared__ double tred[NWAVE];
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   const int N = P.N;
@@ -460,7 +629,7 @@ __global__ __launch_bounds__(NT) void k_sweep(Prob P, const double* E, int nE, d
         }
       }
       __syncthreads();
-      gj_inverse<R, M>(mat, S, sc);
+      gj_inverse<R, M>(mat, S, Ysc, sc);
       for (int tj = w; tj < 2 * MT; tj += NWAVE) {
         ctile<R> acc[MT];
 #pragma unroll
