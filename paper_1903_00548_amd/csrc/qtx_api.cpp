@@ -181,7 +181,7 @@ qtx_status stage_decimate(qtx_ctx* c, const double* E_dev, int nE, double eta) {
   QTX_HIP(c, c->wf.ensure((size_t)nE * 2 * MM * sizeof(double2)));
   QTX_HIP(c, c->sgn.ensure((size_t)nE * 2 * M * sizeof(double)));
   QTX_HIP(c, c->iters.ensure((size_t)nE * 2 * sizeof(int)));
-  QTX_HIP(c, c->dscr.ensure((size_t)grid * 11 * MM * sizeof(double2)));
+  QTX_HIP(c, c->dscr.ensure((size_t)grid * 13 * MM * sizeof(double2)));
   qtx::Prob P = make_prob(c);
   QTX_HIP(c, record(c, c->ev_dec, c->n_dec));
   QTX_HIP(c, qtx::run_decimate(M, P, E_dev, nE, eta, sides, c->dec_tol, c->dec_maxit, c->dscr.as<double2>(),

@@ -80,6 +80,15 @@ template <> struct mf<float> {
   static __device__ __forceinline__ int row(int r, int g) { return 4 * g + r; }
 };
 
+// The lane index laundered through an empty asm: per-lane offsets derived
+// from it are recomputed where they are used instead of being hoisted out
+// of the slab loop and kept live (in registers) across the whole sweep.
+__device__ __forceinline__ int lane_id() {
+  int l = threadIdx.x & 63;
+  asm volatile("" : "+v"(l));
+  return l;
+}
+
 template <typename R> struct ctile {
   typename mf<R>::acc re, im;
 };
@@ -154,6 +163,11 @@ template <typename R> struct BGlobD {          // FP64 source, cast to R
   }
 };
 
+template <class BF> struct BPerm {             // rows taken in the order piv[k]
+  BF b; const int* piv;
+  __device__ __forceinline__ auto get(int k, int col) const { return b.get(piv[k], col); }
+};
+
 // B[k][col] = zv * S[k][col] - H[k][col]
 template <typename R> struct BGen {
   const double2* S; const double2* H; cpx<double> zv; int M;
@@ -171,7 +185,7 @@ template <typename R> struct BGen {
 // no MFMA waits on the accumulator of the one before it.
 template <typename R, int MT, int KT, class AF, class BF>
 __device__ __forceinline__ void cgemm_col(ctile<R> (&acc)[MT], const AF& A, const BF& B, int tj) {
-  const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
+  const int lane = lane_id(), g = lane >> 4, c = lane & 15;
   const int col = 16 * tj + c;
   cpx<R> bq, aq[MT];
   {
@@ -204,6 +218,7 @@ __device__ __forceinline__ void cgemm_col(ctile<R> (&acc)[MT], const AF& A, cons
     bq = bn;
 #pragma unroll
     for (int ti = 0; ti < MT; ++ti) aq[ti] = an[ti];
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
@@ -211,11 +226,14 @@ __device__ __forceinline__ void cgemm_col(ctile<R> (&acc)[MT], const AF& A, cons
 // fn(row, col, re, im, ti, r).
 template <typename R, int MT, class F>
 __device__ __forceinline__ void tiles_foreach(ctile<R> (&acc)[MT], int tj, F fn) {
-  const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
+  const int lane = lane_id(), g = lane >> 4, c = lane & 15;
 #pragma unroll
-  for (int ti = 0; ti < MT; ++ti)
+  for (int ti = 0; ti < MT; ++ti) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) fn(16 * ti + mf<R>::row(r, g), 16 * tj + c, ti, r);
+    // one tile's loads in flight at a time (otherwise all are hoisted)
+    __builtin_amdgcn_sched_barrier(0);
+  }
 }
 
 // ------------------------------------------------------------ reductions

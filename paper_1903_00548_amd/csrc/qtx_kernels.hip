@@ -30,12 +30,15 @@ template <typename R, int M> struct BGJ {
 
 // Wave-level elimination of panel k (columns 16k..16k+15) of the LDS matrix.
 // The step loop is unrolled (static column index) with a scheduling barrier
-// after every step so that steps do not interleave; the pivot lane
-// publishes the already scaled pivot row, and the pivot row itself is
-// produced by the same fused multiply-subtract as the others (base 0,
-// factor -1).
+// after every step so that steps do not interleave.  Latency chain of one
+// step: pivot key -> DPP max -> the pivot lane writes its raw row to LDS
+// while every lane forms the reciprocal of the pivot -> every lane reads the
+// row back and scales it on the fly.  LDS operations of one wave complete in
+// issue order, so the write/read pair needs no wait beyond the compiler
+// barrier.  The pivot row is produced by the same fused multiply-subtract
+// as the others (base 0, factor -1).
 template <typename R, int M>
-__device__ void gj_panel(cpx<R>* mat, int S, int k, BGJ<R, M>& sc) {
+__device__ __forceinline__ void gj_panel(cpx<R>* mat, int S, int k, BGJ<R, M>& sc) {
   constexpr int RL = (M + 63) / 64;  // rows per lane
   const int lane = threadIdx.x & 63;
   cpx<R> pr[RL][16];
@@ -62,24 +65,21 @@ __device__ void gj_panel(cpx<R>* mat, int S, int k, BGJ<R, M>& sc) {
     const int pl = p & 63, pq = p >> 6;
     bool isp[RL];
     cpx<R> f[RL];
+    cpx<R> pvt = mk<R>(0, 0);
 #pragma unroll
     for (int q = 0; q < RL; ++q) {
       isp[q] = (q == pq) && (lane == pl);
+      if (isp[q])
+#pragma unroll
+        for (int c = 0; c < 16; ++c) sc.prow[c] = pr[q][c];
+      if (q == pq) pvt = mk<R>(readlane_d(pr[q][jj].re, pl), readlane_d(pr[q][jj].im, pl));
       f[q] = isp[q] ? mk<R>(-1, 0) : pr[q][jj];
     }
-#pragma unroll
-    for (int q = 0; q < RL; ++q)
-      if (isp[q]) {
-        const cpx<R> inv = cinv(pr[q][jj]);
-#pragma unroll
-        for (int c = 0; c < 16; ++c) sc.prow[c] = (c == jj) ? inv : cmul(pr[q][c], inv);
-      }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    const cpx<R> inv = cinv(pvt);
     __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
     for (int c = 0; c < 16; ++c) {
-      const cpx<R> pvc = sc.prow[c];
+      const cpx<R> pvc = (c == jj) ? inv : cmul(sc.prow[c], inv);
 #pragma unroll
       for (int q = 0; q < RL; ++q) {
         const cpx<R> base = (c == jj || isp[q]) ? mk<R>(0, 0) : pr[q][c];
@@ -93,9 +93,7 @@ __device__ void gj_panel(cpx<R>* mat, int S, int k, BGJ<R, M>& sc) {
       sc.piv[16 * k + jj] = p;
       sc.ppanel[p] = k;
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     __builtin_amdgcn_sched_barrier(0);
   }
 #pragma unroll
@@ -124,10 +122,13 @@ __device__ __forceinline__ void gj_update_tile(const cpx<R>* mat, int S, int k, 
   });
 }
 
-// In-place inverse of the M x M LDS matrix (row stride S); Y is LDS scratch
-// of 16 x M.  Ends with a barrier.
+// In-place Gauss-Jordan on the M x M LDS matrix (row stride S); Y is LDS
+// scratch of 16 x (M - 16).  The result is the inverse up to the pivot order:
+// A^-1[j][c] = mat[piv[j]][pinv[c]], so A^-1 B = P (mat (Q B)) with
+// (Q B)[k] = B[piv[k]] and row r of the product landing in row pinv[r].
+// Ends with a barrier.
 template <typename R, int M>
-__device__ void gj_inverse(cpx<R>* mat, int S, cpx<R>* Y, BGJ<R, M>& sc) {
+__device__ __forceinline__ void gj_inverse(cpx<R>* mat, int S, cpx<R>* Y, BGJ<R, M>& sc) {
   constexpr int NP = M / 16, MT = M / 16;
   const int t = threadIdx.x, w = t >> 6;
   if (t < M) sc.ppanel[t] = -1;
@@ -135,218 +136,24 @@ __device__ void gj_inverse(cpx<R>* mat, int S, cpx<R>* Y, BGJ<R, M>& sc) {
   for (int k = 0; k < NP; ++k) {
     if (w == 0) gj_panel<R, M>(mat, S, k, sc);
     __syncthreads();
-    for (int idx = t; idx < 16 * M; idx += NT) {
-      const int jj = idx / M, c = idx - jj * M;
-      if ((c >> 4) != k) Y[idx] = mat[sc.piv[16 * k + jj] * S + c];
+    // pivot rows of the columns outside the panel, compacted (16 x (M-16))
+    constexpr int WY = M - 16;
+    for (int idx = t; idx < 16 * WY; idx += NT) {
+      const int jj = idx / WY, cx = idx - jj * WY;
+      const int c = cx + (cx >= 16 * k ? 16 : 0);
+      Y[idx] = mat[sc.piv[16 * k + jj] * S + c];
     }
     __syncthreads();
     for (int tile = w; tile < MT * (NP - 1); tile += NWAVE) {
       const int ti = tile % MT, tcx = tile / MT, tc = tcx + (tcx >= k ? 1 : 0);
       gj_update_tile<R, M>(
-          mat, S, k, Y, M, 16 * tc, ti, sc,
+          mat, S, k, Y, WY, 16 * tcx, ti, sc,
           [&](int row, int col) { return mat[row * S + 16 * tc + col]; },
           [&](int row, int col, cpx<R> v) { mat[row * S + 16 * tc + col] = v; });
     }
     __syncthreads();
   }
   if (t < M) sc.pinv[sc.piv[t]] = t;
-  __syncthreads();
-  constexpr int b = M / 16;
-  const int gr = t >> 4, gc = t & 15;
-  cpx<R> a[b][b];
-#pragma unroll
-  for (int rr = 0; rr < b; ++rr)
-#pragma unroll
-    for (int cc = 0; cc < b; ++cc) a[rr][cc] = mat[(b * gr + rr) * S + b * gc + cc];
-  __syncthreads();
-#pragma unroll
-  for (int rr = 0; rr < b; ++rr)
-#pragma unroll
-    for (int cc = 0; cc < b; ++cc) mat[sc.pinv[b * gr + rr] * S + sc.piv[b * gc + cc]] = a[rr][cc];
-  __syncthreads();
-}
-
-// Blocked LU solve eps * X = B with partial pivoting (implicit row order).
-// eps (M x M) lives in LDS (row stride S), B (M x 2M, leading dimension 2M)
-// in global memory and is transformed in place; the solution rows are
-// written un-permuted to out (M x 2M).  Y is LDS scratch of 16 x 3M.
-// Panel factorisation on one wave (rows already chosen as pivots are
-// frozen), then per panel: gather the pivot rows of the live columns,
-// forward substitution with the unit lower 16x16 block, and the trailing
-// update of the remaining rows as masked MFMA tiles; finally the block
-// back substitution with the upper triangular factor.  Ends with a barrier.
-template <int M>
-__device__ void lu_panel(cpx<double>* eps, int S, int k, BGJ<double, M>& sc) {
-  const int lane = threadIdx.x & 63;
-  cpx<double> pr[16];
-  const bool ok = lane < M;
-  bool used = !ok || sc.ppanel[lane] >= 0;
-#pragma unroll
-  for (int c = 0; c < 16; ++c) pr[c] = ok ? eps[lane * S + 16 * k + c] : mk<double>(0, 0);
-#pragma unroll 1
-  for (int jj = 0; jj < 16; ++jj) {
-    cpx<double> f = pr[0];
-#pragma unroll
-    for (int c = 1; c < 16; ++c)
-      if (c == jj) f = pr[c];
-    const uint32_t key = used ? 0u : pivot_key32(f, lane);
-    const uint32_t kmax = wave_max_u32(key);
-    const int p = 255 - (int)(kmax & 0xff);
-    const cpx<double> pvt = mk<double>(readlane_d(f.re, p), readlane_d(f.im, p));
-    if (lane == p)
-#pragma unroll
-      for (int c = 0; c < 16; ++c) sc.prow[c] = pr[c];
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const bool elim = !used && lane != p;
-    const cpx<double> l = cmul(f, cinv(pvt));
-#pragma unroll
-    for (int c = 0; c < 16; ++c) {
-      if (c > jj && elim) pr[c] = cfms(pr[c], l, sc.prow[c]);
-      if (c == jj && elim) pr[c] = l;
-    }
-    if (lane == p) used = true;
-    if (lane == 0) {
-      sc.piv[16 * k + jj] = p;
-      sc.ppanel[p] = k;
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  }
-  if (ok)
-#pragma unroll
-    for (int c = 0; c < 16; ++c) eps[lane * S + 16 * k + c] = pr[c];
-}
-
-// A operand: rows of the LDS matrix restricted to columns [c0, c0+16); rows
-// whose ppanel is >= 0 and <= kmax read as zero (frozen rows).
-struct ALdsMask {
-  const cpx<double>* p; int S; int c0; const int* ppanel; int kmax; int kmin;
-  __device__ __forceinline__ cpx<double> get(int row, int k) const {
-    const int pp = ppanel[row];
-    const bool live = kmin < 0 ? !(pp >= 0 && pp <= kmax) : (pp >= 0 && pp < kmin);
-    return live ? p[row * S + c0 + k] : mk<double>(0, 0);
-  }
-};
-
-template <int M>
-__device__ void lu_solve(cpx<double>* eps, int S, double2* B, double2* out, cpx<double>* Y, BGJ<double, M>& sc) {
-  constexpr int NP = M / 16, MT = M / 16, W = 3 * M, LB = 2 * M;
-  static_assert(3 * M - 16 <= NT, "one live column per thread");
-  const int t = threadIdx.x, w = t >> 6;
-  if (t < M) sc.ppanel[t] = -1;
-  __syncthreads();
-  // ---- forward: P A = L U, B <- L^-1 P B
-  for (int k = 0; k < NP; ++k) {
-    if (w == 0) lu_panel<M>(eps, S, k, sc);
-    __syncthreads();
-    const int c0 = 16 * (k + 1);          // first live eps column
-    const int nl = M - c0 + LB;           // live columns: eps [c0, M), then B
-    for (int idx = t; idx < 16 * nl; idx += NT) {
-      const int jj = idx / nl, c = idx - jj * nl;
-      const int p = sc.piv[16 * k + jj];
-      Y[jj * W + c] = (c < M - c0) ? eps[p * S + c0 + c] : ldd(B + (size_t)p * LB + (c - (M - c0)));
-    }
-    __syncthreads();
-    // unit lower 16x16 forward substitution, one live column per thread
-    // (nl <= 3M - 16 <= NT; a loop here would let the compiler hoist all
-    // 120 loads of the triangular block out of it)
-    if (t < nl) {
-      const int c = t;
-      cpx<double> y[16];
-#pragma unroll
-      for (int a = 0; a < 16; ++a) y[a] = Y[a * W + c];
-      // column-oriented; the scheduling barriers keep the LDS loads of one
-      // column of L in flight at a time (otherwise all 120 are hoisted)
-#pragma unroll
-      for (int b = 0; b < 15; ++b) {
-#pragma unroll
-        for (int a = b + 1; a < 16; ++a) y[a] = cfms(y[a], eps[sc.piv[16 * k + a] * S + 16 * k + b], y[b]);
-        __builtin_amdgcn_sched_barrier(0);
-      }
-#pragma unroll
-      for (int a = 0; a < 16; ++a) Y[a * W + c] = y[a];
-      if (c < M - c0) {
-#pragma unroll
-        for (int a = 0; a < 16; ++a) eps[sc.piv[16 * k + a] * S + c0 + c] = y[a];
-      } else {
-#pragma unroll
-        for (int a = 0; a < 16; ++a)
-          B[(size_t)sc.piv[16 * k + a] * LB + (c - (M - c0))] = make_double2(y[a].re, y[a].im);
-      }
-    }
-    __syncthreads();
-    // trailing update of the rows that are not pivots yet
-    const int ncol = (M - c0) / 16 + 2 * NP;
-    for (int tile = w; tile < MT * ncol; tile += NWAVE) {
-      const int ti = tile % MT, tcx = tile / MT;
-      ctile<double> acc[1];
-      const bool is_eps = tcx < (M - c0) / 16;
-      const int xc = is_eps ? c0 + 16 * tcx : 16 * (tcx - (M - c0) / 16);
-      tiles_foreach<double, 1>(acc, 0, [&](int row, int col, int, int r) {
-        const int gr = 16 * ti + row;
-        cpx<double> v = is_eps ? eps[gr * S + xc + col] : ldd(B + (size_t)gr * LB + xc + col);
-        acc[0].re[r] = -v.re;
-        acc[0].im[r] = -v.im;
-      });
-      // acc = -x + L y  (then negated on store): x - L y
-      cgemm_col<double, 1, 1>(acc, ALdsMask{eps + 16 * ti * S, S, 16 * k, sc.ppanel + 16 * ti, k, -1},
-                              BLds<double>{Y + 16 * tcx, W}, 0);
-      tiles_foreach<double, 1>(acc, 0, [&](int row, int col, int, int r) {
-        const int gr = 16 * ti + row;
-        const cpx<double> v = mk<double>(-acc[0].re[r], -acc[0].im[r]);
-        if (is_eps) eps[gr * S + xc + col] = v;
-        else B[(size_t)gr * LB + xc + col] = make_double2(v.re, v.im);
-      });
-    }
-    __syncthreads();
-  }
-  // ---- backward: U X = B, panels from the last one
-  for (int k = NP - 1; k >= 0; --k) {
-    if (t < LB) {
-      const int c = t;
-      cpx<double> y[16];
-#pragma unroll
-      for (int a = 0; a < 16; ++a) y[a] = ldd(B + (size_t)sc.piv[16 * k + a] * LB + c);
-#pragma unroll
-      for (int b = 15; b >= 0; --b) {
-        y[b] = cmul(y[b], cinv(eps[sc.piv[16 * k + b] * S + 16 * k + b]));
-#pragma unroll
-        for (int a = 0; a < b; ++a) y[a] = cfms(y[a], eps[sc.piv[16 * k + a] * S + 16 * k + b], y[b]);
-        __builtin_amdgcn_sched_barrier(0);
-      }
-#pragma unroll
-      for (int a = 0; a < 16; ++a) {
-        Y[a * W + c] = y[a];
-        B[(size_t)sc.piv[16 * k + a] * LB + c] = make_double2(y[a].re, y[a].im);
-      }
-    }
-    __syncthreads();
-    if (k > 0) {
-      // rows that became pivots in earlier panels: x -= U[:, panel k] y
-      for (int tile = w; tile < MT * 2 * NP; tile += NWAVE) {
-        const int ti = tile % MT, tb = tile / MT;
-        ctile<double> acc[1];
-        tiles_foreach<double, 1>(acc, 0, [&](int row, int col, int, int r) {
-          cpx<double> v = ldd(B + (size_t)(16 * ti + row) * LB + 16 * tb + col);
-          acc[0].re[r] = -v.re;
-          acc[0].im[r] = -v.im;
-        });
-        cgemm_col<double, 1, 1>(acc, ALdsMask{eps + 16 * ti * S, S, 16 * k, sc.ppanel + 16 * ti, 0, k},
-                                BLds<double>{Y + 16 * tb, W}, 0);
-        tiles_foreach<double, 1>(acc, 0, [&](int row, int col, int, int r) {
-          B[(size_t)(16 * ti + row) * LB + 16 * tb + col] = make_double2(-acc[0].re[r], -acc[0].im[r]);
-        });
-      }
-      __syncthreads();
-    }
-  }
-  for (int idx = t; idx < M * LB; idx += NT) {
-    const int j = idx / LB, c = idx - j * LB;
-    out[idx] = B[(size_t)sc.piv[j] * LB + c];
-  }
   __syncthreads();
 }
 
@@ -363,7 +170,7 @@ template <int M> struct LDLScratch {
 };
 
 template <int M>
-__device__ void gamma_ldl(const double2* sig, double2* W, double* sg, LDLScratch<M>& sc) {
+__device__ __forceinline__ void gamma_ldl(const double2* sig, double2* W, double* sg, LDLScratch<M>& sc) {
   constexpr int b = M / 16;
   const int t = threadIdx.x, gr = t >> 4, gc = t & 15;
   cpx<double> a[b][b];
@@ -434,30 +241,31 @@ __device__ void gamma_ldl(const double2* sig, double2* W, double* sg, LDLScratch
 // couplings a (slab j -> j+1) and b (j+1 -> j), eliminating every other slab
 // gives e' = e - a g b - b g a, a' = -a g a, b' = -b g b with g = e^-1; the
 // surface of a right lead keeps only -a g b and that of a left lead only
-// -b g a.  Sigma = D0 - (converged surface block).  g [a | b] is obtained
-// by an LU solve with partial pivoting, not from an explicit inverse (nor a
-// blocked Gauss-Jordan, which inverts its 16x16 pivot blocks explicitly):
-// those lose up to two extra digits when D0 is ill-conditioned.
+// -b g a.  Sigma = D0 - (converged surface block).
+// g [a | b] comes from the blocked Gauss-Jordan inverse followed by one step
+// of iterative refinement, X <- X + e^-1 ([a | b] - e X): the explicit
+// inverse alone loses up to two digits when D0 is ill-conditioned, one
+// refinement step restores the accuracy of an LU solve.
 template <int M>
 __global__ __launch_bounds__(NT, 2) void k_decimate(Prob P, const double* E, int nE, double eta, int sides,
-                                                 double tol, int maxit, double2* scratch, double2* sig,
-                                                 double2* wf, double* sgn, int* iters) {
-  constexpr int MT = M / 16, MM = M * M;
-  constexpr int S = M + 1;
-  __shared__ cpx<double> epsL[M * S];
-  __shared__ cpx<double> Ysc[16 * 3 * M];
+                                                    double tol, int maxit, double2* scratch, double2* sig,
+                                                    double2* wf, double* sgn, int* iters) {
+  constexpr int MT = M / 16, MM = M * M, S = M + 1, LB = 2 * M;
+  __shared__ cpx<double> mat[M * S];
+  __shared__ union {
+    cpx<double> y[16 * (M - 16 > 0 ? M - 16 : 1)];
+    LDLScratch<M> ldl;
+  } u;
   __shared__ BGJ<double, M> sc;
-  __shared__ LDLScratch<M> lsc;
   __shared__ double red[2][NWAVE];
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
-  double2* ws = scratch + (size_t)blockIdx.x * 11 * MM;
+  double2* ws = scratch + (size_t)blockIdx.x * 13 * MM;
   double2* eps = ws;
   double2* esL = ws + MM;
   double2* esR = ws + 2 * MM;
-  double2* al[2] = {ws + 3 * MM, ws + 5 * MM};
-  double2* be[2] = {ws + 4 * MM, ws + 6 * MM};
-  double2* g = ws + 7 * MM;    // M x 2M: solution [g alpha | g beta]
-  double2* rhs = ws + 9 * MM;  // M x 2M: right-hand side being eliminated
+  double2* ab[2] = {ws + 3 * MM, ws + 5 * MM};   // [a | b], M x 2M, ping-pong
+  double2* X = ws + 7 * MM;                       // [g a | g b]
+  double2* Rr = ws + 9 * MM;                      // residual
   const int njobs = nE * sides;
   for (int job = blockIdx.x; job < njobs; job += gridDim.x) {
     const int e = job / sides;
@@ -472,10 +280,12 @@ __global__ __launch_bounds__(NT, 2) void k_decimate(Prob P, const double* E, int
       cpx<double> s = ldd(S00 + idx), h = ldd(H00 + idx);
       double2 d0 = make_double2(zx.re * s.re - zx.im * s.im - h.re, zx.re * s.im + zx.im * s.re - h.im);
       s = ldd(S01 + idx); h = ldd(H01 + idx);
-      double2 u = make_double2(zx.re * s.re - zx.im * s.im - h.re, zx.re * s.im + zx.im * s.re - h.im);
+      double2 uu = make_double2(zx.re * s.re - zx.im * s.im - h.re, zx.re * s.im + zx.im * s.re - h.im);
       s = ldd(S01 + c * M + r); h = ldd(H01 + c * M + r);
-      double2 l = make_double2(zx.re * s.re + zx.im * s.im - h.re, zx.im * s.re - zx.re * s.im + h.im);
-      eps[idx] = d0; esL[idx] = d0; esR[idx] = d0; al[0][idx] = u; be[0][idx] = l;
+      double2 ll = make_double2(zx.re * s.re + zx.im * s.im - h.re, zx.im * s.re - zx.re * s.im + h.im);
+      eps[idx] = d0; esL[idx] = d0; esR[idx] = d0;
+      ab[0][r * LB + c] = uu;
+      ab[0][r * LB + M + c] = ll;
       scl = fmax(scl, fabs(d0.x) + fabs(d0.y));
     }
     scl = wave_maxd(scl);
@@ -486,40 +296,78 @@ __global__ __launch_bounds__(NT, 2) void k_decimate(Prob P, const double* E, int
     int cur = 0, it = 0;
     bool conv = false;
     for (it = 1; it <= maxit; ++it) {
+      const double2* AB = ab[cur];
+      double2* ABn = ab[cur ^ 1];
       for (int idx = t; idx < MM; idx += NT) {
         const int r = idx / M, c = idx - r * M;
-        epsL[r * S + c] = ldd(eps + idx);
-        rhs[r * 2 * M + c] = al[cur][idx];
-        rhs[r * 2 * M + M + c] = be[cur][idx];
+        mat[r * S + c] = ldd(eps + idx);
       }
       __syncthreads();
-      lu_solve<M>(epsL, S, rhs, g, Ysc, sc);
+      gj_inverse<double, M>(mat, S, u.y, sc);
+      // X = e^-1 [a | b], then one refinement step; each wave owns whole
+      // column tiles of X, so the three products need no barrier
+#pragma unroll 1
+      for (int tj = w; tj < 2 * MT; tj += NWAVE) {
+        ctile<double> acc[MT];
+#pragma unroll
+        for (int ti = 0; ti < MT; ++ti) tzero(acc[ti]);
+        cgemm_col<double, MT, MT>(acc, ALds<double>{mat, S}, BPerm<BGlob<double>>{BGlob<double>{AB, LB}, sc.piv}, tj);
+        tiles_foreach<double, MT>(acc, tj, [&](int row, int col, int ti, int r) {
+          X[(unsigned)(sc.pinv[row] * LB + col)] = make_double2(acc[ti].re[r], acc[ti].im[r]);
+        });
+        __threadfence_block();
+        // residual R = [a | b] - e X
+        tiles_foreach<double, MT>(acc, tj, [&](int row, int col, int ti, int r) {
+          const double2 v = AB[(unsigned)(row * LB + col)];
+          acc[ti].re[r] = v.x;
+          acc[ti].im[r] = v.y;
+        });
+        cgemm_col<double, MT, MT>(acc, AGlob<double>{eps, M, -1.0}, BGlob<double>{X, LB}, tj);
+        tiles_foreach<double, MT>(acc, tj, [&](int row, int col, int ti, int r) {
+          Rr[(unsigned)(row * LB + col)] = make_double2(acc[ti].re[r], acc[ti].im[r]);
+        });
+        __threadfence_block();
+        // X += e^-1 R (rows through the pivot order)
+        tiles_foreach<double, MT>(acc, tj, [&](int row, int col, int ti, int r) {
+          const double2 v = X[(unsigned)(sc.pinv[row] * LB + col)];
+          acc[ti].re[r] = v.x;
+          acc[ti].im[r] = v.y;
+        });
+        cgemm_col<double, MT, MT>(acc, ALds<double>{mat, S}, BPerm<BGlob<double>>{BGlob<double>{Rr, LB}, sc.piv}, tj);
+        tiles_foreach<double, MT>(acc, tj, [&](int row, int col, int ti, int r) {
+          X[(unsigned)(sc.pinv[row] * LB + col)] = make_double2(acc[ti].re[r], acc[ti].im[r]);
+        });
+      }
+      // doubling update: output column tile tj reads column tiles tj (g a)
+      // and MT + tj (g b) of X, written by other waves unless M/16 == NWAVE
+      __syncthreads();
       double na = 0.0, nb = 0.0;
+#pragma unroll 1
       for (int tj = w; tj < MT; tj += NWAVE) {
-        ctile<double> a1[MT], a2[MT];
+        // one accumulator column live at a time: a g b, b g a, a g a, b g b
+#pragma unroll 1
+        for (int q = 0; q < 4; ++q) {
+          ctile<double> acc[MT];
 #pragma unroll
-        for (int ti = 0; ti < MT; ++ti) { tzero(a1[ti]); tzero(a2[ti]); }
-        cgemm_col<double, MT, MT>(a1, AGlob<double>{al[cur], M, 1.0}, BGlob<double>{g + M, 2 * M}, tj);
-        cgemm_col<double, MT, MT>(a2, AGlob<double>{be[cur], M, 1.0}, BGlob<double>{g, 2 * M}, tj);
-        tiles_foreach<double, MT>(a1, tj, [&](int row, int col, int ti, int r) {
-          const int idx = row * M + col;
-          const double r1 = a1[ti].re[r], i1 = a1[ti].im[r], r2 = a2[ti].re[r], i2 = a2[ti].im[r];
-          double2 v = eps[idx];
-          v.x -= r1 + r2; v.y -= i1 + i2; eps[idx] = v;
-          v = esR[idx]; v.x -= r1; v.y -= i1; esR[idx] = v;
-          v = esL[idx]; v.x -= r2; v.y -= i2; esL[idx] = v;
-        });
-#pragma unroll
-        for (int ti = 0; ti < MT; ++ti) { tzero(a1[ti]); tzero(a2[ti]); }
-        cgemm_col<double, MT, MT>(a1, AGlob<double>{al[cur], M, 1.0}, BGlob<double>{g, 2 * M}, tj);
-        cgemm_col<double, MT, MT>(a2, AGlob<double>{be[cur], M, 1.0}, BGlob<double>{g + M, 2 * M}, tj);
-        tiles_foreach<double, MT>(a1, tj, [&](int row, int col, int ti, int r) {
-          const int idx = row * M + col;
-          al[cur ^ 1][idx] = make_double2(-a1[ti].re[r], -a1[ti].im[r]);
-          be[cur ^ 1][idx] = make_double2(-a2[ti].re[r], -a2[ti].im[r]);
-          na = fmax(na, fabs(a1[ti].re[r]) + fabs(a1[ti].im[r]));
-          nb = fmax(nb, fabs(a2[ti].re[r]) + fabs(a2[ti].im[r]));
-        });
+          for (int ti = 0; ti < MT; ++ti) tzero(acc[ti]);
+          const double2* Aop = (q == 0 || q == 2) ? AB : AB + M;
+          const double2* Bop = (q == 0 || q == 3) ? X + M : X;
+          cgemm_col<double, MT, MT>(acc, AGlob<double>{Aop, LB, 1.0}, BGlob<double>{Bop, LB}, tj);
+          tiles_foreach<double, MT>(acc, tj, [&](int row, int col, int ti, int r) {
+            const unsigned idx = row * M + col;
+            const double re = acc[ti].re[r], im = acc[ti].im[r];
+            if (q < 2) {
+              double2 v = eps[idx];
+              v.x -= re; v.y -= im; eps[idx] = v;
+              double2* es = q == 0 ? esR : esL;
+              v = es[idx]; v.x -= re; v.y -= im; es[idx] = v;
+            } else {
+              ABn[(unsigned)(row * LB + col) + (q == 3 ? M : 0)] = make_double2(-re, -im);
+              if (q == 2) na = fmax(na, fabs(re) + fabs(im));
+              else nb = fmax(nb, fabs(re) + fabs(im));
+            }
+          });
+        }
       }
       na = wave_maxd(na);
       nb = wave_maxd(nb);
@@ -542,7 +390,7 @@ __global__ __launch_bounds__(NT, 2) void k_decimate(Prob P, const double* E, int
     __syncthreads();
     for (int s = 0; s < 2; ++s) {
       if ((side == 0 && s == 1) || (side == 1 && s == 0)) continue;
-      gamma_ldl<M>(sig + (size_t)(2 * e + s) * MM, wf + (size_t)(2 * e + s) * MM, sgn + (size_t)(2 * e + s) * M, lsc);
+      gamma_ldl<M>(sig + (size_t)(2 * e + s) * MM, wf + (size_t)(2 * e + s) * MM, sgn + (size_t)(2 * e + s) * M, u.ldl);
       if (t == 0) iters[2 * e + s] = it;
     }
     __syncthreads();
@@ -567,7 +415,7 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(Prob P, const double* E, int nE
   typedef typename vec2t<R>::type V2;
   constexpr int MT = M / 16, MM = M * M, S = M + 1, LD = 2 * M;
   __shared__ cpx<R> mat[M * S];
-  __shared__ cpx<R> Ysc[16 * M];
+  __shared__ cpx<R> Ysc[16 * (M - 16 > 0 ? M - 16 : 1)];
   __shared__ BGJ<R, M> sc;
   __shared__ double tred[NWAVE];
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
@@ -590,22 +438,31 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(Prob P, const double* E, int nE
       const double2* Sd = P.Sd(i);
       const double2* Hd = P.Hd(i);
       const cpx<double> zd = mk<double>(z.re - vd, z.im);
+#pragma unroll 1
       for (int tj = w; tj < 2 * MT; tj += NWAVE) {
         ctile<R> acc[MT];
         if (tj < MT) {
           tiles_foreach<R, MT>(acc, tj, [&](int row, int col, int ti, int r) {
-            const int idx = row * M + col;
+            const unsigned idx = row * M + col;
             cpx<double> s = ldd(Sd + idx), h = ldd(Hd + idx);
-            double re = zd.re * s.re - zd.im * s.im - h.re;
-            double im = zd.re * s.im + zd.im * s.re - h.im;
-            if (i == 0) { cpx<double> q = ldd(sL + idx); re -= q.re; im -= q.im; }
-            if (i == N - 1) { cpx<double> q = ldd(sR + idx); re -= q.re; im -= q.im; }
-            acc[ti].re[r] = (R)re;
-            acc[ti].im[r] = (R)im;
+            acc[ti].re[r] = (R)(zd.re * s.re - zd.im * s.im - h.re);
+            acc[ti].im[r] = (R)(zd.re * s.im + zd.im * s.re - h.im);
           });
+          if (i == 0)
+            tiles_foreach<R, MT>(acc, tj, [&](int row, int col, int ti, int r) {
+              cpx<double> q = ldd(sL + (unsigned)(row * M + col));
+              acc[ti].re[r] -= (R)q.re;
+              acc[ti].im[r] -= (R)q.im;
+            });
+          if (i == N - 1)
+            tiles_foreach<R, MT>(acc, tj, [&](int row, int col, int ti, int r) {
+              cpx<double> q = ldd(sR + (unsigned)(row * M + col));
+              acc[ti].re[r] -= (R)q.re;
+              acc[ti].im[r] -= (R)q.im;
+            });
         } else if (i == 0) {
           tiles_foreach<R, MT>(acc, tj, [&](int row, int col, int ti, int r) {
-            cpx<double> q = ldd(WL + row * M + col - M);
+            cpx<double> q = ldd(WL + (unsigned)(row * M + col - M));
             acc[ti].re[r] = (R)q.re;
             acc[ti].im[r] = (R)q.im;
           });
@@ -624,12 +481,13 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(Prob P, const double* E, int nE
           });
         } else {
           tiles_foreach<R, MT>(acc, tj, [&](int row, int col, int ti, int r) {
-            st2<R>(Xi + row * LD + col, mk<R>(acc[ti].re[r], acc[ti].im[r]));
+            st2<R>(Xi + (unsigned)(row * LD + col), mk<R>(acc[ti].re[r], acc[ti].im[r]));
           });
         }
       }
       __syncthreads();
       gj_inverse<R, M>(mat, S, Ysc, sc);
+#pragma unroll 1
       for (int tj = w; tj < 2 * MT; tj += NWAVE) {
         ctile<R> acc[MT];
 #pragma unroll
@@ -638,15 +496,18 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(Prob P, const double* E, int nE
         if (tj < MT) {
           if (i < N - 1) {
             const double vu = P.vu(i);
-            cgemm_col<R, MT, MT>(acc, A, BGen<R>{P.Su(i), P.Hu(i), mk<double>(z.re - vu, z.im), M}, tj);
+            cgemm_col<R, MT, MT>(
+                acc, A, BPerm<BGen<R>>{BGen<R>{P.Su(i), P.Hu(i), mk<double>(z.re - vu, z.im), M}, sc.piv}, tj);
           } else {
-            cgemm_col<R, MT, MT>(acc, A, BGlobD<R>{WR, M}, tj);
+            cgemm_col<R, MT, MT>(acc, A, BPerm<BGlobD<R>>{BGlobD<R>{WR, M}, sc.piv}, tj);
           }
         } else {
-          cgemm_col<R, MT, MT>(acc, A, BGlob<R>{Xi, LD}, tj);
+          cgemm_col<R, MT, MT>(acc, A, BPerm<BGlob<R>>{BGlob<R>{Xi, LD}, sc.piv}, tj);
         }
+        // rows land through the inverse pivot order; a column tile is read
+        // and written by one wave only, so the scatter needs no barrier
         tiles_foreach<R, MT>(acc, tj, [&](int row, int col, int ti, int r) {
-          st2<R>(Xi + row * LD + col, mk<R>(acc[ti].re[r], acc[ti].im[r]));
+          st2<R>(Xi + (unsigned)(sc.pinv[row] * LD + col), mk<R>(acc[ti].re[r], acc[ti].im[r]));
         });
       }
     }
@@ -655,15 +516,17 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(Prob P, const double* E, int nE
     {
       const V2* XN = XZ + (size_t)(N - 1) * M * LD;
       double tp = 0.0;
+#pragma unroll 1
       for (int tj = w; tj < 2 * MT; tj += NWAVE) {
         if (tj < MT) continue;
         ctile<R> acc[MT];
 #pragma unroll
         for (int ti = 0; ti < MT; ++ti) tzero(acc[ti]);
         cgemm_col<R, MT, MT>(acc, AGlobCT<R>{WR, M}, BGlob<R>{XN, LD}, tj);
+        const double sl = sgL[16 * tj + (lane & 15) - M];
         tiles_foreach<R, MT>(acc, tj, [&](int row, int col, int ti, int r) {
           const double re = acc[ti].re[r], im = acc[ti].im[r];
-          tp += sgR[row] * sgL[col - M] * (re * re + im * im);
+          tp += sgR[row] * sl * (re * re + im * im);
         });
       }
       tp = wave_sum(tp);
@@ -673,11 +536,12 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(Prob P, const double* E, int nE
     for (int i = N - 1; i >= 0; --i) {
       const V2* Xi = XZ + (size_t)i * M * LD;
       double pL = 0.0, pR = 0.0;
+#pragma unroll 1
       for (int tj = w; tj < 2 * MT; tj += NWAVE) {
         ctile<R> acc[MT];
         if (i == N - 1 || tj >= MT) {
           tiles_foreach<R, MT>(acc, tj, [&](int row, int col, int ti, int r) {
-            cpx<R> v = ld2<R>(Xi + row * LD + col);
+            cpx<R> v = ld2<R>(Xi + (unsigned)(row * LD + col));
             acc[ti].re[r] = v.re;
             acc[ti].im[r] = v.im;
           });
@@ -686,12 +550,16 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(Prob P, const double* E, int nE
           for (int ti = 0; ti < MT; ++ti) tzero(acc[ti]);
         }
         if (i < N - 1) cgemm_col<R, MT, MT>(acc, AGlob<R>{Xi, LD, (R)-1}, BGlob<R>{PSI, LD}, tj);
+        const int cl = 16 * tj + (lane & 15);
+        const double sg = cl < M ? sgR[cl] : sgL[cl - M];
+        double pp = 0.0;
         tiles_foreach<R, MT>(acc, tj, [&](int row, int col, int ti, int r) {
           const double re = acc[ti].re[r], im = acc[ti].im[r];
-          st2<R>(PSI + row * LD + col, mk<R>(acc[ti].re[r], acc[ti].im[r]));
-          if (col < M) pR += sgR[col] * (re * re + im * im);
-          else pL += sgL[col - M] * (re * re + im * im);
+          st2<R>(PSI + (unsigned)(row * LD + col), mk<R>(acc[ti].re[r], acc[ti].im[r]));
+          pp += re * re + im * im;
         });
+        if (tj < MT) pR += sg * pp;
+        else pL += sg * pp;
       }
       __threadfence_block();
       pL = wave_sum(pL);
