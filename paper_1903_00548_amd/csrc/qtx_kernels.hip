@@ -438,51 +438,92 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(Prob P, const double* E, int nE
       const double2* Sd = P.Sd(i);
       const double2* Hd = P.Hd(i);
       const cpx<double> zd = mk<double>(z.re - vd, z.im);
+      // Stage A = -L_i = -(A_{i,i-1}) once per slab in the LDS buffer (free
+      // until the new Schur complement is written): every wave reads the
+      // whole of it, which from L1/L2 would exceed the cache bandwidth.
+      if (i > 0) {
+        const double vu = P.vu(i - 1);
+        const cpx<double> zu = mk<double>(z.re - vu, z.im);
+        const double2* Su = P.Su(i - 1);
+        const double2* Hu = P.Hu(i - 1);
+        for (int idx = t; idx < MM; idx += NT) {
+          const int k = idx / M, r = idx - k * M;     // read S[k][r] along r
+          const cpx<double> sv = ldd(Su + idx), hv = ldd(Hu + idx);
+          const double re = zu.re * sv.re + zu.im * sv.im - hv.re;
+          const double im = zu.im * sv.re - zu.re * sv.im + hv.im;
+          mat[r * S + k] = mk<R>((R)-re, (R)-im);
+        }
+        __syncthreads();
+      }
+      // Column tiles of [Dt | y]: the y tiles go straight to the workspace,
+      // the (at most DT) Dt tile columns of this wave stay in registers until
+      // every wave has finished reading L_i from the LDS buffer.
+      constexpr int DT = (MT + NWAVE - 1) / NWAVE;
+      ctile<R> dacc[DT][MT];
 #pragma unroll 1
-      for (int tj = w; tj < 2 * MT; tj += NWAVE) {
-        ctile<R> acc[MT];
-        if (tj < MT) {
-          tiles_foreach<R, MT>(acc, tj, [&](int row, int col, int ti, int r) {
-            const unsigned idx = row * M + col;
-            cpx<double> s = ldd(Sd + idx), h = ldd(Hd + idx);
-            acc[ti].re[r] = (R)(zd.re * s.re - zd.im * s.im - h.re);
-            acc[ti].im[r] = (R)(zd.re * s.im + zd.im * s.re - h.im);
-          });
-          if (i == 0)
+      for (int pass = 0; pass < 2; ++pass) {
+        int nd = 0;
+#pragma unroll 1
+        for (int tj = w; tj < 2 * MT; tj += NWAVE) {
+          const bool is_d = tj < MT;
+          if (is_d != (pass == 1)) continue;
+          ctile<R> acc[MT];
+          if (is_d) {
             tiles_foreach<R, MT>(acc, tj, [&](int row, int col, int ti, int r) {
-              cpx<double> q = ldd(sL + (unsigned)(row * M + col));
-              acc[ti].re[r] -= (R)q.re;
-              acc[ti].im[r] -= (R)q.im;
+              const unsigned idx = row * M + col;
+              cpx<double> sv = ldd(Sd + idx), hv = ldd(Hd + idx);
+              acc[ti].re[r] = (R)(zd.re * sv.re - zd.im * sv.im - hv.re);
+              acc[ti].im[r] = (R)(zd.re * sv.im + zd.im * sv.re - hv.im);
             });
-          if (i == N - 1)
+            if (i == 0)
+              tiles_foreach<R, MT>(acc, tj, [&](int row, int col, int ti, int r) {
+                cpx<double> q = ldd(sL + (unsigned)(row * M + col));
+                acc[ti].re[r] -= (R)q.re;
+                acc[ti].im[r] -= (R)q.im;
+              });
+            if (i == N - 1)
+              tiles_foreach<R, MT>(acc, tj, [&](int row, int col, int ti, int r) {
+                cpx<double> q = ldd(sR + (unsigned)(row * M + col));
+                acc[ti].re[r] -= (R)q.re;
+                acc[ti].im[r] -= (R)q.im;
+              });
+          } else if (i == 0) {
             tiles_foreach<R, MT>(acc, tj, [&](int row, int col, int ti, int r) {
-              cpx<double> q = ldd(sR + (unsigned)(row * M + col));
-              acc[ti].re[r] -= (R)q.re;
-              acc[ti].im[r] -= (R)q.im;
+              cpx<double> q = ldd(WL + (unsigned)(row * M + col - M));
+              acc[ti].re[r] = (R)q.re;
+              acc[ti].im[r] = (R)q.im;
             });
-        } else if (i == 0) {
-          tiles_foreach<R, MT>(acc, tj, [&](int row, int col, int ti, int r) {
-            cpx<double> q = ldd(WL + (unsigned)(row * M + col - M));
-            acc[ti].re[r] = (R)q.re;
-            acc[ti].im[r] = (R)q.im;
-          });
-        } else {
+          } else {
 #pragma unroll
-          for (int ti = 0; ti < MT; ++ti) tzero(acc[ti]);
+            for (int ti = 0; ti < MT; ++ti) tzero(acc[ti]);
+          }
+          if (i > 0) cgemm_col<R, MT, MT>(acc, ALds<R>{mat, S}, BGlob<R>{Xi - (size_t)M * LD, LD}, tj);
+          if (is_d) {
+#pragma unroll
+            for (int q = 0; q < DT; ++q)
+              if (q == nd)
+#pragma unroll
+                for (int ti = 0; ti < MT; ++ti) dacc[q][ti] = acc[ti];
+            ++nd;
+          } else {
+            tiles_foreach<R, MT>(acc, tj, [&](int row, int col, int ti, int r) {
+              st2<R>(Xi + (unsigned)(row * LD + col), mk<R>(acc[ti].re[r], acc[ti].im[r]));
+            });
+          }
         }
-        if (i > 0) {
-          const double vu = P.vu(i - 1);
-          AGenCT<R> A{P.Su(i - 1), P.Hu(i - 1), mk<double>(z.re - vu, z.im), -1.0, M};
-          cgemm_col<R, MT, MT>(acc, A, BGlob<R>{Xi - (size_t)M * LD, LD}, tj);
-        }
-        if (tj < MT) {
-          tiles_foreach<R, MT>(acc, tj, [&](int row, int col, int ti, int r) {
-            mat[row * S + col] = mk<R>(acc[ti].re[r], acc[ti].im[r]);
-          });
-        } else {
-          tiles_foreach<R, MT>(acc, tj, [&](int row, int col, int ti, int r) {
-            st2<R>(Xi + (unsigned)(row * LD + col), mk<R>(acc[ti].re[r], acc[ti].im[r]));
-          });
+      }
+      __syncthreads();
+      {
+        int nd = 0;
+#pragma unroll 1
+        for (int tj = w; tj < MT; tj += NWAVE) {
+#pragma unroll
+          for (int q = 0; q < DT; ++q)
+            if (q == nd)
+              tiles_foreach<R, MT>(dacc[q], tj, [&](int row, int col, int ti, int r) {
+                mat[row * S + col] = mk<R>(dacc[q][ti].re[r], dacc[q][ti].im[r]);
+              });
+          ++nd;
         }
       }
       __syncthreads();
@@ -535,6 +576,16 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(Prob P, const double* E, int nE
     // back substitution with fused slab densities
     for (int i = N - 1; i >= 0; --i) {
       const V2* Xi = XZ + (size_t)i * M * LD;
+      if (i < N - 1) {
+        // stage -X_i in LDS once per slab (every wave reads all of it)
+        __syncthreads();
+        for (int idx = t; idx < MM; idx += NT) {
+          const int r = idx / M, c = idx - r * M;
+          const cpx<R> v = ld2<R>(Xi + (unsigned)(r * LD + c));
+          mat[r * S + c] = mk<R>(-v.re, -v.im);
+        }
+        __syncthreads();
+      }
       double pL = 0.0, pR = 0.0;
 #pragma unroll 1
       for (int tj = w; tj < 2 * MT; tj += NWAVE) {
@@ -549,7 +600,7 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(Prob P, const double* E, int nE
 #pragma unroll
           for (int ti = 0; ti < MT; ++ti) tzero(acc[ti]);
         }
-        if (i < N - 1) cgemm_col<R, MT, MT>(acc, AGlob<R>{Xi, LD, (R)-1}, BGlob<R>{PSI, LD}, tj);
+        if (i < N - 1) cgemm_col<R, MT, MT>(acc, ALds<R>{mat, S}, BGlob<R>{PSI, LD}, tj);
         const int cl = 16 * tj + (lane & 15);
         const double sg = cl < M ? sgR[cl] : sgL[cl - M];
         double pp = 0.0;
