@@ -14,6 +14,7 @@ energy of the grid (the FP64 path itself is held to 1e-10 of the CPU
 oracle by the parity tests).
 """
 import argparse
+import hashlib
 import json
 import multiprocessing as mp
 import os
@@ -34,6 +35,48 @@ def flops_per_energy(N, m, n_dec):
     """Algorithmic real flops: (152/3) m^3 per slab (factor 56/3 m^3, forward
     and backward right-hand-side sweeps 16 m^3 each) and per doubling."""
     return (N + n_dec) * (152.0 / 3.0) * m ** 3
+
+
+KERNEL_SOURCES = ("paper_1903_00548_amd/csrc/qtx_kernels.hip", "paper_1903_00548_amd/csrc/qtx_device.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_cfg1_fp64_hbm_traffic.md")
+
+
+def kernel_source_sha1():
+    h = hashlib.sha1()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per sweep launch from the committed rocprofv3 counter
+    summary, or None when it is missing or was taken on other kernel
+    sources."""
+    try:
+        txt = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    vals = dict(line.split(":", 1) for line in txt.splitlines() if ":" in line and not line.startswith("#"))
+    if vals.get("kernel_source_sha1", "").strip() != kernel_source_sha1():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration():
+    """A plain device-to-device copy of known size, for scaling the
+    FETCH_SIZE / WRITE_SIZE counters (run under rocprofv3 --pmc)."""
+    import torch
+    n = 1 << 27                       # 2^27 doubles = 1 GiB
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "dispatches": 3}))
 
 
 def _oracle_worker(args):
@@ -95,7 +138,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the energy "
               "grid shards across GPUs by design but no multi-GPU path is built.", file=sys.stderr)
@@ -162,7 +210,8 @@ def main():
         "config": {"workload": "cfg1_N200_m64_E2048", "N": dev.N, "m": dev.m, "energies_per_step": nE,
                    "eta": wl.eta, "path": best, "mean_decimation_doublings": n_dec},
         "roofline": {"bound": "mfma", "achieved": p["sweep_tflops"], "peak": PEAK[best], "unit": "TFLOP/s",
-                     "frac": p["sweep_tflops"] / PEAK[best], "traffic": None,
+                     "frac": p["sweep_tflops"] / PEAK[best],
+                     "traffic": measured_traffic() if best == "fp64" else None,
                      "kernel": "k_sweep (block forward/backward sweeps)"},
         "cpu_baseline": cpu,
         "paths": paths,
