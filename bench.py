@@ -112,23 +112,30 @@ def cpu_baseline(wl, seconds=15.0):
                       f"numpy/scipy FP64, {dt:.1f} s wall"}
 
 
-def time_path(ctx, torch, E_t, T_t, L_t, eta, prec, steps, warmup):
+def time_path(ctx, torch, E_t, T_t, L_t, I_t, eta, prec, steps, warmup):
+    from paper_1903_00548_amd import _lib
     nE = E_t.numel()
+
+    def solve():
+        ctx.solve_device(E_t.data_ptr(), nE, eta, prec, T_t.data_ptr(), L_t.data_ptr(), I_t.data_ptr())
+
     for _ in range(warmup):
-        ctx.solve_device(E_t.data_ptr(), nE, eta, prec, T_t.data_ptr(), L_t.data_ptr())
+        solve()
     torch.cuda.synchronize()
     ctx.kernel_times(enable=True)
     step_ms = []
     t_start = time.perf_counter()
     for _ in range(steps):
         a = time.perf_counter()
-        ctx.solve_device(E_t.data_ptr(), nE, eta, prec, T_t.data_ptr(), L_t.data_ptr())
+        solve()
         torch.cuda.synchronize()
         step_ms.append((time.perf_counter() - a) * 1e3)
     t_total = time.perf_counter() - t_start
     dec_ms, sw_ms, launches = ctx.kernel_times(enable=False)
+    info = np.frombuffer(I_t.cpu().numpy().tobytes(), dtype=_lib.INFO_DTYPE)
     return {"s": t_total, "step_ms": step_ms, "dec_ms": dec_ms / steps, "sweep_ms": sw_ms / steps,
-            "sweep_launches": launches / steps, "T": T_t.cpu().numpy().copy(), "ldos": L_t.cpu().numpy().copy()}
+            "sweep_launches": launches / steps, "T": T_t.cpu().numpy().copy(), "ldos": L_t.cpu().numpy().copy(),
+            "info": info}
 
 
 def main():
@@ -165,15 +172,17 @@ def main():
     E_t = torch.tensor(wl.E, dtype=torch.float64, device="cuda")
     T_t = torch.empty(nE, dtype=torch.float64, device="cuda")
     L_t = torch.empty((nE, 2, dev.N), dtype=torch.float64, device="cuda")
+    I_t = torch.empty(nE * _lib.INFO_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
 
     res = {}
     for name, prec in (("fp64", _lib.FP64), ("mixed", _lib.MIXED)):
-        res[name] = time_path(ctx, torch, E_t, T_t, L_t, wl.eta, prec, args.steps, args.warmup)
+        res[name] = time_path(ctx, torch, E_t, T_t, L_t, I_t, wl.eta, prec, args.steps, args.warmup)
     # decimation doublings actually used (for the algorithmic flop count)
-    _, _, info, _ = ctx.solve(wl.E, wl.eta, _lib.FP64, want_ldos=False)
-    n_dec = float(np.mean(info["dec_iters"]))
+    n_dec = float(np.mean(res["fp64"]["info"]["dec_iters"]))
     dT_mixed = float(np.abs(res["mixed"]["T"] - res["fp64"]["T"]).max())
     ok_mixed = dT_mixed <= 1e-8
+    scale = np.maximum(1.0, np.abs(res["fp64"]["ldos"]).max(axis=2))
+    dn_mixed = float((np.abs(res["mixed"]["ldos"] - res["fp64"]["ldos"]).max(axis=2) / scale).max())
 
     paths = {}
     for name in ("fp64", "mixed"):
@@ -190,7 +199,12 @@ def main():
             "sweep_tflops": ach,
             "whole_solve_frac_of_fp64_peak": rate * flops_per_energy(dev.N, dev.m, n_dec) / 78.6e12,
         }
-    paths["mixed"]["max_dT_vs_fp64"] = dT_mixed
+    mi = res["mixed"]["info"]
+    paths["mixed"].update({
+        "max_dT_vs_fp64": dT_mixed, "max_rel_dn_vs_fp64": dn_mixed,
+        "refine_steps_histogram": np.bincount(mi["refine_steps"], minlength=4).tolist(),
+        "fp64_fallbacks": int(mi["fell_back_fp64"].sum()),
+    })
     best = "mixed" if (ok_mixed and paths["mixed"]["energy_solves_per_s"] > paths["fp64"]["energy_solves_per_s"]) \
         else "fp64"
     p = paths[best]

@@ -153,6 +153,28 @@ qtx_status qtx_solve_device(qtx_ctx* ctx, const double* E_dev, int nE, double et
 qtx_status qtx_self_energy(qtx_ctx* ctx, const double* E, int nE, double eta,
                            qtx_c128* sigma, qtx_c128* wfac, double* sgn, int* iters);
 
+/* Tuning parameters of a context (problems created from it start with the
+ * same values).  name / accepted values / default:
+ *   "decimation_tol"        (0, 1)        1e-14  doubling stops when the
+ *                           couplings fall below this times |D0|;
+ *   "decimation_max_iters"  [1, 1000]     60     doublings before
+ *                           QTX_FLAG_DEC_NOTCONV;
+ *   "refine_tol"            (0, 1)        1e-12  QTX_MIXED: refinement stops
+ *                           when ||r||_F <= refine_tol ||b||_F over the
+ *                           refined columns;
+ *   "refine_max_steps"      [0, 20]       3      QTX_MIXED: corrections before
+ *                           the energy is re-solved in FP64;
+ *   "refine_weight_tol"     [0, 1]        1e-8   QTX_MIXED: columns of the
+ *                           broadening factor whose LDL^H pivot is at least
+ *                           this times the largest are refined (whole tiles
+ *                           of 16 columns, at least one tile per contact);
+ *                           0 refines every column;
+ *   "workgroups_per_cu"     1 or 2        2      resident energies per CU;
+ *   "energies_per_launch"   [1, 2^20]     4096   energies per launch chunk.
+ * Integer options take an integral value.  QTX_EINVAL for an unknown name
+ * or a value out of range (the setting is then unchanged). */
+qtx_status qtx_set_option(qtx_ctx* ctx, const char* name, double value);
+
 /* ---- batching and serving --------------------------------------------- */
 
 /* A problem is a context that shares the parent's device and stream and

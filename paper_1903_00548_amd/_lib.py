@@ -53,6 +53,7 @@ _SIGS = {
     "qtx_self_energy": (c_int, [c_void_p, c_void_p, c_int, c_double, c_void_p, c_void_p, c_void_p, c_void_p]),
     "qtx_problem_create": (c_int, [c_void_p, POINTER(c_void_p)]),
     "qtx_kernel_times": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p]),
+    "qtx_set_option": (c_int, [c_void_p, c_char_p, c_double]),
     "qtx_solve_batch": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_double, c_int,
                                 c_void_p, c_void_p]),
     "qtx_charge": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_double, c_double, c_double,
@@ -191,6 +192,9 @@ class Context:
         self._check(self.lib.qtx_kernel_times(self.h, int(enable), ctypes.byref(d), ctypes.byref(s_),
                                               ctypes.byref(n)))
         return d.value, s_.value, n.value
+
+    def set_option(self, name: str, value: float):
+        self._check(self.lib.qtx_set_option(self.h, name.encode(), float(value)))
 
     def problem(self):
         h = c_void_p()

@@ -65,7 +65,8 @@ struct qtx_ctx {
 
   // workspaces
   DevBuf wE, wT, wldos, winfo;
-  DevBuf sig, wf, sgn, iters, dscr, sws, part;
+  DevBuf sig, wf, sgn, iters, nheavy, dscr, sws, part;
+  DevBuf redo, elist, ecount;                  // mixed: energies re-solved in FP64
 
   // kernel timing: event pairs around decimation / sweep launches
   bool timing = false;
@@ -77,6 +78,9 @@ struct qtx_ctx {
   int dec_maxit = 60;
   int chunk = 4096;
   int wg_per_cu = 2;
+  double refine_tol = 1e-12;      // stop when ||r|| <= refine_tol ||b||
+  int refine_max = 3;             // corrections per energy before the FP64 fallback
+  double heavy_tol = 1e-8;        // refine columns with pivot >= heavy_tol * largest
 };
 
 namespace {
@@ -181,12 +185,13 @@ qtx_status stage_decimate(qtx_ctx* c, const double* E_dev, int nE, double eta) {
   QTX_HIP(c, c->wf.ensure((size_t)nE * 2 * MM * sizeof(double2)));
   QTX_HIP(c, c->sgn.ensure((size_t)nE * 2 * M * sizeof(double)));
   QTX_HIP(c, c->iters.ensure((size_t)nE * 2 * sizeof(int)));
+  QTX_HIP(c, c->nheavy.ensure((size_t)nE * 2 * sizeof(int)));
   QTX_HIP(c, c->dscr.ensure((size_t)grid * 13 * MM * sizeof(double2)));
   qtx::Prob P = make_prob(c);
   QTX_HIP(c, record(c, c->ev_dec, c->n_dec));
-  QTX_HIP(c, qtx::run_decimate(M, P, E_dev, nE, eta, sides, c->dec_tol, c->dec_maxit, c->dscr.as<double2>(),
-                               grid, c->sig.as<double2>(), c->wf.as<double2>(), c->sgn.as<double>(),
-                               c->iters.as<int>(), c->stream));
+  QTX_HIP(c, qtx::run_decimate(M, P, E_dev, nE, eta, sides, c->dec_tol, c->dec_maxit, c->heavy_tol,
+                               c->dscr.as<double2>(), grid, c->sig.as<double2>(), c->wf.as<double2>(),
+                               c->sgn.as<double>(), c->iters.as<int>(), c->nheavy.as<int>(), c->stream));
   QTX_HIP(c, record(c, c->ev_dec, c->n_dec));
   return QTX_OK;
 }
@@ -198,24 +203,54 @@ qtx_status solve_device_core(qtx_ctx* c, const double* E_dev, int nE, double eta
   if (nE < 0 || !(eta >= 0.0)) return fail(c, QTX_EINVAL, "nE must be >= 0 and eta >= 0");
   if (nE == 0) return QTX_OK;
   if (!E_dev || !T_dev) return fail(c, QTX_EINVAL, "E and T must not be NULL");
-  const bool fp32 = (prec == QTX_MIXED);
+  if (prec != QTX_FP64 && prec != QTX_MIXED) return fail(c, QTX_EINVAL, "precision must be QTX_FP64 or QTX_MIXED");
+  const bool mixed = (prec == QTX_MIXED);
   const int M = c->M, N = c->N;
   for (int e0 = 0; e0 < nE; e0 += c->chunk) {
     const int ne = std::min(c->chunk, nE - e0);
     s = stage_decimate(c, E_dev + e0, ne, eta);
     if (s != QTX_OK) return s;
     const int grid = std::max(1, std::min(ne, c->num_cu * c->wg_per_cu));
-    const size_t esz = fp32 ? sizeof(float2) : sizeof(double2);
-    const size_t ws_stride = (size_t)(N + 1) * M * 2 * M;
-    QTX_HIP(c, c->sws.ensure((size_t)grid * ws_stride * esz));
-    QTX_HIP(c, c->part.ensure((size_t)grid * 4 * 2 * N * sizeof(double)));
+    const size_t wsb = qtx::sweep_ws_bytes(N, M, mixed);
+    QTX_HIP(c, c->sws.ensure((size_t)grid * wsb));
+    QTX_HIP(c, c->part.ensure((size_t)grid * 4 * 2 * N * (mixed ? 2 : 1) * sizeof(double)));
+    if (mixed) {
+      QTX_HIP(c, c->redo.ensure((size_t)ne * sizeof(int)));
+      QTX_HIP(c, c->elist.ensure((size_t)ne * sizeof(int)));
+      QTX_HIP(c, c->ecount.ensure(sizeof(int)));
+    }
     qtx::Prob P = make_prob(c);
+    qtx::SweepArgs a;
+    a.E = E_dev + e0;
+    a.nE = ne;
+    a.eta = eta;
+    a.sig = c->sig.as<double2>();
+    a.wf = c->wf.as<double2>();
+    a.sgn = c->sgn.as<double>();
+    a.iters = c->iters.as<int>();
+    a.nheavy = c->nheavy.as<int>();
+    a.ws = c->sws.as<char>();
+    a.ws_bytes = wsb;
+    a.part = c->part.as<double>();
+    a.T = T_dev + e0;
+    a.ldos = ldos_dev ? ldos_dev + (size_t)e0 * 2 * N : nullptr;
+    a.info = info_dev ? info_dev + e0 : nullptr;
+    a.elist = nullptr;
+    a.ecount = nullptr;
+    a.redo = mixed ? c->redo.as<int>() : nullptr;
+    a.rtol = c->refine_tol;
+    a.maxstep = c->refine_max;
     QTX_HIP(c, record(c, c->ev_sw, c->n_sw));
-    QTX_HIP(c, qtx::run_sweep(M, fp32, P, E_dev + e0, ne, eta, c->sig.as<double2>(), c->wf.as<double2>(),
-                              c->sgn.as<double>(), c->iters.as<int>(), c->sws.p, ws_stride,
-                              c->part.as<double>(), grid, T_dev + e0,
-                              ldos_dev ? ldos_dev + (size_t)e0 * 2 * N : nullptr,
-                              info_dev ? info_dev + e0 : nullptr, c->stream));
+    QTX_HIP(c, qtx::run_sweep(M, mixed, P, a, grid, c->stream));
+    if (mixed) {
+      // energies whose refinement did not converge: FP64 sweep on the list
+      QTX_HIP(c, qtx::run_compact(c->redo.as<int>(), ne, c->elist.as<int>(), c->ecount.as<int>(), c->stream));
+      qtx::SweepArgs f = a;
+      f.elist = c->elist.as<int>();
+      f.ecount = c->ecount.as<int>();
+      f.redo = nullptr;
+      QTX_HIP(c, qtx::run_sweep(M, false, P, f, grid, c->stream));
+    }
     QTX_HIP(c, record(c, c->ev_sw, c->n_sw));
   }
   return QTX_OK;
@@ -254,7 +289,8 @@ void qtx_destroy(qtx_ctx* c) {
   for (hipEvent_t e : c->ev_dec) hipEventDestroy(e);
   for (hipEvent_t e : c->ev_sw) hipEventDestroy(e);
   DevBuf* bufs[] = {&c->dlead[0], &c->dlead[1], &c->ddev, &c->dV, &c->wE, &c->wT, &c->wldos, &c->winfo,
-                    &c->sig, &c->wf, &c->sgn, &c->iters, &c->dscr, &c->sws, &c->part};
+                    &c->sig, &c->wf, &c->sgn, &c->iters, &c->nheavy, &c->dscr, &c->sws, &c->part,
+                    &c->redo, &c->elist, &c->ecount};
   for (DevBuf* b : bufs) b->release();
   if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
   delete c;
@@ -486,12 +522,51 @@ qtx_status qtx_kernel_times(qtx_ctx* c, int enable, double* decimate_ms, double*
   return QTX_OK;
 }
 
+qtx_status qtx_set_option(qtx_ctx* c, const char* name, double value) {
+  if (!c) return QTX_EINVAL;
+  if (!name) return fail(c, QTX_EINVAL, "option name must not be NULL");
+  const std::string n(name);
+  const bool integral = std::isfinite(value) && value == std::floor(value);
+  if (n == "decimation_tol") {
+    if (!(value > 0.0 && value < 1.0)) return fail(c, QTX_EINVAL, "decimation_tol must be in (0, 1)");
+    c->dec_tol = value;
+  } else if (n == "decimation_max_iters") {
+    if (!integral || value < 1 || value > 1000) return fail(c, QTX_EINVAL, "decimation_max_iters must be in [1, 1000]");
+    c->dec_maxit = (int)value;
+  } else if (n == "refine_tol") {
+    if (!(value > 0.0 && value < 1.0)) return fail(c, QTX_EINVAL, "refine_tol must be in (0, 1)");
+    c->refine_tol = value;
+  } else if (n == "refine_max_steps") {
+    if (!integral || value < 0 || value > 20) return fail(c, QTX_EINVAL, "refine_max_steps must be in [0, 20]");
+    c->refine_max = (int)value;
+  } else if (n == "refine_weight_tol") {
+    if (!(value >= 0.0 && value <= 1.0)) return fail(c, QTX_EINVAL, "refine_weight_tol must be in [0, 1]");
+    c->heavy_tol = value;
+  } else if (n == "workgroups_per_cu") {
+    if (!integral || value < 1 || value > 2) return fail(c, QTX_EINVAL, "workgroups_per_cu must be 1 or 2");
+    c->wg_per_cu = (int)value;
+  } else if (n == "energies_per_launch") {
+    if (!integral || value < 1 || value > (1 << 20)) return fail(c, QTX_EINVAL, "energies_per_launch must be in [1, 2^20]");
+    c->chunk = (int)value;
+  } else {
+    return fail(c, QTX_EINVAL, "unknown option: " + n);
+  }
+  return QTX_OK;
+}
+
 qtx_status qtx_problem_create(qtx_ctx* parent, qtx_ctx** problem) {
   if (!parent || !problem) return QTX_EINVAL;
   *problem = nullptr;
   qtx_ctx* c = new qtx_ctx();
   c->device = parent->device;
   c->num_cu = parent->num_cu;
+  c->dec_tol = parent->dec_tol;
+  c->dec_maxit = parent->dec_maxit;
+  c->chunk = parent->chunk;
+  c->wg_per_cu = parent->wg_per_cu;
+  c->refine_tol = parent->refine_tol;
+  c->refine_max = parent->refine_max;
+  c->heavy_tol = parent->heavy_tol;
   c->stream = parent->stream;
   c->own_stream = false;
   c->parent = parent;

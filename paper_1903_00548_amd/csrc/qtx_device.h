@@ -145,6 +145,24 @@ template <typename R> struct AGenCT {
   }
 };
 
+// A[row][k] = sg * (zv * S[row][k] - H[row][k]): a block of zS - H
+// generated from the stored blocks (FP64 source).
+template <typename R> struct AGen {
+  const double2* S; const double2* H; cpx<double> zv; double sg; int M;
+  __device__ __forceinline__ cpx<R> get(int row, int k) const {
+    cpx<double> sv = ldd(S + (size_t)row * M + k);
+    cpx<double> hv = ldd(H + (size_t)row * M + k);
+    double re = zv.re * sv.re - zv.im * sv.im - hv.re;
+    double im = zv.re * sv.im + zv.im * sv.re - hv.im;
+    return mk<R>((R)(sg * re), (R)(sg * im));
+  }
+};
+
+template <class AF> struct ARows {             // rows r0, r0 + 1, ... of another A operand
+  AF a; int r0;
+  __device__ __forceinline__ auto get(int row, int k) const { return a.get(row + r0, k); }
+};
+
 template <typename R> struct BLds {            // row-major in LDS
   const cpx<R>* p; int ld;
   __device__ __forceinline__ cpx<R> get(int k, int col) const { return p[k * ld + col]; }
@@ -160,6 +178,14 @@ template <typename R> struct BGlobD {          // FP64 source, cast to R
   __device__ __forceinline__ cpx<R> get(int k, int col) const {
     cpx<double> v = ldd(p + (size_t)k * ld + col);
     return mk<R>((R)v.re, (R)v.im);
+  }
+};
+
+template <typename R> struct BGlobF {          // FP32 source, widened to R
+  const float2* p; int ld;
+  __device__ __forceinline__ cpx<R> get(int k, int col) const {
+    float2 v = p[(size_t)k * ld + col];
+    return mk<R>((R)v.x, (R)v.y);
   }
 };
 
@@ -260,6 +286,19 @@ __device__ __forceinline__ double wave_maxd(double v) {
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) v = fmax(v, __shfl_xor(v, m, 64));
   return v;
+}
+
+// Sum over the workgroup; every thread gets the same value (summed in the
+// same order).  red: NWAVE doubles of LDS.  Contains two barriers.
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int q = 0; q < NWAVE; ++q) s += red[q];
+  __syncthreads();
+  return s;
 }
 
 // Max over the 64 lanes of a wave with DPP row shifts and row broadcasts;

@@ -42,12 +42,54 @@ struct Prob {
   }
 };
 
-hipError_t run_decimate(int M, const Prob& P, const double* E, int nE, double eta, int sides, double tol,
-                        int maxit, double2* scratch, int grid, double2* sig, double2* wf, double* sgn,
-                        int* iters, hipStream_t st);
+// Arguments of one sweep launch.  Energy e uses sig/wf/sgn/iters/nheavy
+// at index e of the decimation outputs and writes T[e], ldos[e] and
+// info[e].  Workgroup b owns bytes [b ws_bytes, (b+1) ws_bytes) of ws and
+// its share of part.
+struct SweepArgs {
+  const double* E;
+  int nE;
+  double eta;
+  const double2* sig;      // Sigma_L, Sigma_R per energy (2 M^2)
+  const double2* wf;       // W_L, W_R per energy (2 M^2)
+  const double* sgn;       // signs of the broadening factors (2 M)
+  const int* iters;        // doublings per side (2), negative if capped
+  const int* nheavy;       // refined columns per side (2), mixed sweep only
+  char* ws;
+  size_t ws_bytes;
+  double* part;
+  double* T;
+  double* ldos;            // may be null
+  qtx_info* info;          // may be null
+  const int* elist;        // non-null: solve energies elist[0 .. *ecount) only
+  const int* ecount;
+  int* redo;               // mixed: 1 where the refinement did not converge
+  double rtol;             // mixed: stop when ||r|| <= rtol ||b||
+  int maxstep;             // mixed: at most this many corrections
+};
 
-hipError_t run_sweep(int M, bool fp32, const Prob& P, const double* E, int nE, double eta, const double2* sig,
-                     const double2* wf, const double* sgn, const int* iters, void* ws, size_t ws_stride,
-                     double* part, int grid, double* T, double* ldos, qtx_info* info, hipStream_t st);
+// Per-workgroup sweep workspace.  FP64 sweep: [X_i | z_i] for N slabs plus
+// the back-substitution buffer, (N + 1) M x 2M complex doubles.  Mixed
+// sweep, in this order: the same in complex floats; the N inverses of the
+// Schur complements (M x M floats); the correction columns (N M x 2M
+// floats); one slab of right-hand sides (M x 2M floats); the refined
+// solution (N M x 2M doubles).
+inline size_t sweep_ws_bytes(int N, int M, bool mixed) {
+  const size_t MM = (size_t)M * M;
+  if (!mixed) return (size_t)(N + 1) * 2 * MM * sizeof(double2);
+  return ((size_t)(N + 1) * 2 * MM + (size_t)N * MM + (size_t)N * 2 * MM + 2 * MM) * sizeof(float2) +
+         (size_t)N * 2 * MM * sizeof(double2);
+}
+
+hipError_t run_decimate(int M, const Prob& P, const double* E, int nE, double eta, int sides, double tol,
+                        int maxit, double heavy_tol, double2* scratch, int grid, double2* sig, double2* wf,
+                        double* sgn, int* iters, int* nheavy, hipStream_t st);
+
+// mixed = false: FP64 sweep (with a.elist: re-solve of the listed energies).
+// mixed = true: FP32 sweep plus refinement of the heavy columns.
+hipError_t run_sweep(int M, bool mixed, const Prob& P, const SweepArgs& a, int grid, hipStream_t st);
+
+// elist[0 .. *ecount) = the energies e < nE with redo[e] != 0 (one wave).
+hipError_t run_compact(const int* redo, int nE, int* elist, int* ecount, hipStream_t st);
 
 }  // namespace qtx

@@ -164,13 +164,17 @@ __device__ __forceinline__ void gj_inverse(cpx<R>* mat, int S, cpx<R>* Y, BGJ<R,
 // LDL^H: at each step the remaining diagonal entry of largest magnitude d
 // is eliminated, column k of W is the pivot column / sqrt|d| and s_k =
 // sign(d).  Exactly zero remaining diagonals (padding) end the factorisation.
+// The pivots come out in decreasing magnitude; *nh receives the number of
+// leading columns whose pivot is at least tau times the first one (the
+// columns that carry the weight of the injection).
 template <int M> struct LDLScratch {
   cpx<double> col[M];
   double dg[M];
 };
 
 template <int M>
-__device__ __forceinline__ void gamma_ldl(const double2* sig, double2* W, double* sg, LDLScratch<M>& sc) {
+__device__ __forceinline__ void gamma_ldl(const double2* sig, double2* W, double* sg, double tau, int* nh,
+                                          LDLScratch<M>& sc) {
   constexpr int b = M / 16;
   const int t = threadIdx.x, gr = t >> 4, gc = t & 15;
   cpx<double> a[b][b];
@@ -185,6 +189,8 @@ __device__ __forceinline__ void gamma_ldl(const double2* sig, double2* W, double
   for (int idx = t; idx < M * M; idx += NT) W[idx] = make_double2(0.0, 0.0);
   if (t < M) sg[t] = 0.0;
   bool used0 = false, used1 = false;
+  double d0 = 0.0;
+  int cnt = 0;
   for (int k = 0; k < M; ++k) {
     if (gr == gc)
 #pragma unroll
@@ -203,6 +209,8 @@ __device__ __forceinline__ void gamma_ldl(const double2* sig, double2* W, double
     if (lane + 64 == p) used1 = true;
     const double d = sc.dg[p];
     if (d == 0.0) break;                      // uniform: every thread reads the same d
+    if (k == 0) d0 = fabs(d);
+    if (fabs(d) >= tau * d0) cnt = k + 1;
     if (gc == p / b) {
       const int pc = p - b * gc;
 #pragma unroll
@@ -233,6 +241,7 @@ __device__ __forceinline__ void gamma_ldl(const double2* sig, double2* W, double
       }
     }
   }
+  if (t == 0) *nh = cnt;
   __syncthreads();
 }
 
@@ -248,8 +257,9 @@ __device__ __forceinline__ void gamma_ldl(const double2* sig, double2* W, double
 // refinement step restores the accuracy of an LU solve.
 template <int M>
 __global__ __launch_bounds__(NT, 2) void k_decimate(Prob P, const double* E, int nE, double eta, int sides,
-                                                    double tol, int maxit, double2* scratch, double2* sig,
-                                                    double2* wf, double* sgn, int* iters) {
+                                                    double tol, int maxit, double heavy_tol, double2* scratch,
+                                                    double2* sig, double2* wf, double* sgn, int* iters,
+                                                    int* nheavy) {
   constexpr int MT = M / 16, MM = M * M, S = M + 1, LB = 2 * M;
   __shared__ cpx<double> mat[M * S];
   __shared__ union {
@@ -390,11 +400,152 @@ __global__ __launch_bounds__(NT, 2) void k_decimate(Prob P, const double* E, int
     __syncthreads();
     for (int s = 0; s < 2; ++s) {
       if ((side == 0 && s == 1) || (side == 1 && s == 0)) continue;
-      gamma_ldl<M>(sig + (size_t)(2 * e + s) * MM, wf + (size_t)(2 * e + s) * MM, sgn + (size_t)(2 * e + s) * M, u.ldl);
+      gamma_ldl<M>(sig + (size_t)(2 * e + s) * MM, wf + (size_t)(2 * e + s) * MM, sgn + (size_t)(2 * e + s) * M,
+                   heavy_tol, nheavy + 2 * e + s, u.ldl);
       if (t == 0) iters[2 * e + s] = it;
     }
     __syncthreads();
   }
+}
+
+// ------------------------------------------------------------ refinement
+// Mixed-precision refinement of the heavy injected columns of one energy
+// (the single-precision sweep has left its factors X_i, Dt_i^-1 and its
+// solution, widened to FP64, in P64).  One step:
+//   forward:  r_i = b_i - (L_i psi_{i-1} + A_ii psi_i + U_i psi_{i+1})  (FP64)
+//             c_i = Dt_i^-1 (r_i - L_i c_{i-1})                          (FP32 factors)
+//   backward: d_i = c_i - X_i d_{i+1},   psi_i += d_i
+// repeated until ||r||_F <= rtol ||b||_F over the refined columns, with at
+// most maxstep corrections, stopping early when a correction fails to halve
+// the residual.  The refined columns are the first hR column
+// tiles of the right injection and the first hL of the left one (the
+// broadening factor orders its columns by decreasing weight).  The output
+// tiles (row tile, column tile) are dealt round-robin to the waves, so a
+// slab takes two barriers forward and one backward.  Returns the last
+// relative residual; *steps receives the corrections applied.
+template <int M>
+__device__ __forceinline__ double refine(const Prob& P, const SweepArgs& a, int e, cpx<double> z, int hR, int hL,
+                                         const float2* XZ, const float2* DI, float2* ZC, float2* YB, double2* P64,
+                                         double* red, int* steps) {
+  constexpr int MT = M / 16, MM = M * M, LD = 2 * M;
+  const int N = P.N, t = threadIdx.x, w = t >> 6;
+  const int npair = MT * (hR + hL);
+  const double2* sL = a.sig + (size_t)(2 * e) * MM;
+  const double2* sR = sL + MM;
+  const double2* WL = a.wf + (size_t)(2 * e) * MM;
+  const double2* WR = WL + MM;
+  // column tile of the q-th refined tile: right injection first
+  auto colt = [&](int q) { return q < hR ? q : MT + q - hR; };
+  double bb = 0.0;
+  for (int p = w; p < npair; p += NWAVE) {
+    const int ti = p % MT, tj = colt(p / MT);
+    ctile<double> acc[1];
+    tiles_foreach<double, 1>(acc, tj, [&](int row, int col, int, int) {
+      const int gr = 16 * ti + row;
+      const cpx<double> v = col < M ? ldd(WR + gr * M + col) : ldd(WL + gr * M + col - M);
+      bb += v.re * v.re + v.im * v.im;
+    });
+  }
+  bb = block_sum(bb, red);
+  double rel = 0.0, prev = 0.0;
+  int s = 0;
+  for (;; ++s) {
+    double rr = 0.0;
+    for (int i = 0; i < N; ++i) {
+      const double2* Pi = P64 + (size_t)i * M * LD;
+      const cpx<double> zd = mk<double>(z.re - P.vd(i), z.im);
+#pragma unroll 1
+      for (int p = w; p < npair; p += NWAVE) {
+        const int ti = p % MT, tj = colt(p / MT);
+        const bool bL = (i == 0 && tj >= MT), bR = (i == N - 1 && tj < MT);
+        ctile<double> acc[1];
+        tiles_foreach<double, 1>(acc, tj, [&](int row, int col, int, int r) {
+          const int gr = 16 * ti + row;
+          cpx<double> v = mk<double>(0.0, 0.0);
+          if (bL) v = ldd(WL + gr * M + col - M);
+          if (bR) v = ldd(WR + gr * M + col);
+          acc[0].re[r] = v.re;
+          acc[0].im[r] = v.im;
+        });
+        cgemm_col<double, 1, MT>(acc, ARows<AGen<double>>{{P.Sd(i), P.Hd(i), zd, -1.0, M}, 16 * ti},
+                                 BGlob<double>{Pi, LD}, tj);
+        if (i == 0) cgemm_col<double, 1, MT>(acc, ARows<AGlob<double>>{{sL, M, 1.0}, 16 * ti}, BGlob<double>{Pi, LD}, tj);
+        if (i == N - 1) cgemm_col<double, 1, MT>(acc, ARows<AGlob<double>>{{sR, M, 1.0}, 16 * ti}, BGlob<double>{Pi, LD}, tj);
+        if (i > 0) {
+          const cpx<double> zu = mk<double>(z.re - P.vu(i - 1), z.im);
+          cgemm_col<double, 1, MT>(acc, ARows<AGenCT<double>>{{P.Su(i - 1), P.Hu(i - 1), zu, -1.0, M}, 16 * ti},
+                                   BGlob<double>{Pi - (size_t)M * LD, LD}, tj);
+        }
+        if (i < N - 1) {
+          const cpx<double> zu = mk<double>(z.re - P.vu(i), z.im);
+          cgemm_col<double, 1, MT>(acc, ARows<AGen<double>>{{P.Su(i), P.Hu(i), zu, -1.0, M}, 16 * ti},
+                                   BGlob<double>{Pi + (size_t)M * LD, LD}, tj);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) rr += acc[0].re[r] * acc[0].re[r] + acc[0].im[r] * acc[0].im[r];
+        // right-hand side of the correction: r_i - L_i c_{i-1}
+        if (i > 0) {
+          const cpx<double> zu = mk<double>(z.re - P.vu(i - 1), z.im);
+          cgemm_col<double, 1, MT>(acc, ARows<AGenCT<double>>{{P.Su(i - 1), P.Hu(i - 1), zu, -1.0, M}, 16 * ti},
+                                   BGlobF<double>{ZC + (size_t)(i - 1) * M * LD, LD}, tj);
+        }
+        tiles_foreach<double, 1>(acc, tj, [&](int row, int col, int, int r) {
+          YB[(16 * ti + row) * LD + col] = make_float2((float)acc[0].re[r], (float)acc[0].im[r]);
+        });
+      }
+      __syncthreads();
+      float2* Ci = ZC + (size_t)i * M * LD;
+#pragma unroll 1
+      for (int p = w; p < npair; p += NWAVE) {
+        const int ti = p % MT, tj = colt(p / MT);
+        ctile<float> acc[1];
+        tzero(acc[0]);
+        cgemm_col<float, 1, MT>(acc, ARows<AGlob<float>>{{DI + (size_t)i * MM, M, 1.0f}, 16 * ti},
+                                BGlob<float>{YB, LD}, tj);
+        tiles_foreach<float, 1>(acc, tj, [&](int row, int col, int, int r) {
+          Ci[(16 * ti + row) * LD + col] = make_float2(acc[0].re[r], acc[0].im[r]);
+        });
+      }
+      __syncthreads();
+    }
+    rr = block_sum(rr, red);
+    prev = rel;
+    rel = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+    // uniform exits (NaN stops too): converged, out of steps, or a step
+    // that did not halve the residual (the single-precision factors are
+    // too inaccurate for this energy: the FP64 fallback takes over)
+    if (!(rel > a.rtol) || s == a.maxstep || (s > 0 && !(rel < 0.5 * prev))) break;
+    for (int i = N - 1; i >= 0; --i) {
+      float2* Ci = ZC + (size_t)i * M * LD;
+      double2* Pi = P64 + (size_t)i * M * LD;
+#pragma unroll 1
+      for (int p = w; p < npair; p += NWAVE) {
+        const int ti = p % MT, tj = colt(p / MT);
+        ctile<float> acc[1];
+        tiles_foreach<float, 1>(acc, tj, [&](int row, int col, int, int r) {
+          const float2 v = Ci[(16 * ti + row) * LD + col];
+          acc[0].re[r] = v.x;
+          acc[0].im[r] = v.y;
+        });
+        if (i < N - 1)
+          cgemm_col<float, 1, MT>(acc, ARows<AGlob<float>>{{XZ + (size_t)i * M * LD, LD, -1.0f}, 16 * ti},
+                                  BGlob<float>{Ci + (size_t)M * LD, LD}, tj);
+        // d_i replaces c_i: this tile of c_i is read by this wave only, and
+        // c_{i+1} is complete since the previous barrier
+        tiles_foreach<float, 1>(acc, tj, [&](int row, int col, int, int r) {
+          const unsigned idx = (16 * ti + row) * LD + col;
+          Ci[idx] = make_float2(acc[0].re[r], acc[0].im[r]);
+          double2 v = Pi[idx];
+          v.x += (double)acc[0].re[r];
+          v.y += (double)acc[0].im[r];
+          Pi[idx] = v;
+        });
+      }
+      __syncthreads();
+    }
+  }
+  *steps = s;
+  return rel;
 }
 
 // ------------------------------------------------------------ block sweeps
@@ -407,11 +558,17 @@ __global__ __launch_bounds__(NT, 2) void k_decimate(Prob P, const double* E, int
 // T = sum_{j,k} s^R_j s^L_k |(W_R^H psiL_{N-1})_{jk}|^2.
 // D_i, U_i and L_i = A_{i,i-1} are generated from the stored H/S blocks and
 // the potential weights while they are loaded as MFMA operands.
-template <typename R, int M>
-__global__ __launch_bounds__(NT, 2) void k_sweep(Prob P, const double* E, int nE, double eta,
-                                              const double2* sig, const double2* wf, const double* sgn,
-                                              const int* iters, typename vec2t<R>::type* ws, size_t ws_stride,
-                                              double* part, double* T, double* ldos, qtx_info* info) {
+//
+// MIX (R = float): the sweep also keeps Dt_i^-1 (in natural row/column
+// order) and writes the heavy column tiles of psi, plus the whole left
+// injection on the last slab, to the FP64 solution buffer; the densities of
+// the light columns are reduced here, those of the heavy columns and T after
+// the refinement.
+//
+// With a.elist (FP64 sweep only) the launch re-solves the listed energies,
+// keeping the refinement diagnostics in info and marking the fallback.
+template <typename R, int M, bool MIX>
+__global__ __launch_bounds__(NT, 2) void k_sweep(Prob P, SweepArgs a) {
   typedef typename vec2t<R>::type V2;
   constexpr int MT = M / 16, MM = M * M, S = M + 1, LD = 2 * M;
   __shared__ cpx<R> mat[M * S];
@@ -420,17 +577,38 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(Prob P, const double* E, int nE
   __shared__ double tred[NWAVE];
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   const int N = P.N;
-  V2* XZ = ws + (size_t)blockIdx.x * ws_stride;
+  char* wsb = a.ws + (size_t)blockIdx.x * a.ws_bytes;
+  V2* XZ = (V2*)wsb;
   V2* PSI = XZ + (size_t)N * M * LD;
-  double* prt = part + (size_t)blockIdx.x * NWAVE * 2 * N;
-  for (int e = blockIdx.x; e < nE; e += gridDim.x) {
-    const cpx<double> z = mk<double>(E[e], eta);
-    const double2* sL = sig + (size_t)(2 * e) * MM;
+  float2* DI = nullptr;
+  float2* ZC = nullptr;
+  float2* YB = nullptr;
+  double2* P64 = nullptr;
+  if constexpr (MIX) {
+    DI = (float2*)(XZ + (size_t)(N + 1) * M * LD);
+    ZC = DI + (size_t)N * MM;
+    YB = ZC + (size_t)N * M * LD;
+    P64 = (double2*)(YB + (size_t)M * LD);
+  }
+  double* prt = a.part + (size_t)blockIdx.x * NWAVE * 2 * N * (MIX ? 2 : 1);
+  double* prt2 = prt + (size_t)NWAVE * 2 * N;
+  // values loaded from memory are made wave-uniform explicitly, so that
+  // everything addressed through them stays in scalar registers
+  const int ne = a.elist ? __builtin_amdgcn_readfirstlane(*a.ecount) : a.nE;
+  for (int q = blockIdx.x; q < ne; q += gridDim.x) {
+    const int e = a.elist ? __builtin_amdgcn_readfirstlane(a.elist[q]) : q;
+    const cpx<double> z = mk<double>(a.E[e], a.eta);
+    const double2* sL = a.sig + (size_t)(2 * e) * MM;
     const double2* sR = sL + MM;
-    const double2* WL = wf + (size_t)(2 * e) * MM;
+    const double2* WL = a.wf + (size_t)(2 * e) * MM;
     const double2* WR = WL + MM;
-    const double* sgL = sgn + (size_t)(2 * e) * M;
+    const double* sgL = a.sgn + (size_t)(2 * e) * M;
     const double* sgR = sgL + M;
+    int hL = MT, hR = MT;                      // heavy column tiles (MIX)
+    if constexpr (MIX) {
+      hL = __builtin_amdgcn_readfirstlane(min(max((a.nheavy[2 * e] + 15) / 16, 1), MT));
+      hR = __builtin_amdgcn_readfirstlane(min(max((a.nheavy[2 * e + 1] + 15) / 16, 1), MT));
+    }
     for (int i = 0; i < N; ++i) {
       __syncthreads();
       V2* Xi = XZ + (size_t)i * M * LD;
@@ -477,21 +655,21 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(Prob P, const double* E, int nE
             });
             if (i == 0)
               tiles_foreach<R, MT>(acc, tj, [&](int row, int col, int ti, int r) {
-                cpx<double> q = ldd(sL + (unsigned)(row * M + col));
-                acc[ti].re[r] -= (R)q.re;
-                acc[ti].im[r] -= (R)q.im;
+                cpx<double> v = ldd(sL + (unsigned)(row * M + col));
+                acc[ti].re[r] -= (R)v.re;
+                acc[ti].im[r] -= (R)v.im;
               });
             if (i == N - 1)
               tiles_foreach<R, MT>(acc, tj, [&](int row, int col, int ti, int r) {
-                cpx<double> q = ldd(sR + (unsigned)(row * M + col));
-                acc[ti].re[r] -= (R)q.re;
-                acc[ti].im[r] -= (R)q.im;
+                cpx<double> v = ldd(sR + (unsigned)(row * M + col));
+                acc[ti].re[r] -= (R)v.re;
+                acc[ti].im[r] -= (R)v.im;
               });
           } else if (i == 0) {
             tiles_foreach<R, MT>(acc, tj, [&](int row, int col, int ti, int r) {
-              cpx<double> q = ldd(WL + (unsigned)(row * M + col - M));
-              acc[ti].re[r] = (R)q.re;
-              acc[ti].im[r] = (R)q.im;
+              cpx<double> v = ldd(WL + (unsigned)(row * M + col - M));
+              acc[ti].re[r] = (R)v.re;
+              acc[ti].im[r] = (R)v.im;
             });
           } else {
 #pragma unroll
@@ -500,10 +678,10 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(Prob P, const double* E, int nE
           if (i > 0) cgemm_col<R, MT, MT>(acc, ALds<R>{mat, S}, BGlob<R>{Xi - (size_t)M * LD, LD}, tj);
           if (is_d) {
 #pragma unroll
-            for (int q = 0; q < DT; ++q)
-              if (q == nd)
+            for (int q2 = 0; q2 < DT; ++q2)
+              if (q2 == nd)
 #pragma unroll
-                for (int ti = 0; ti < MT; ++ti) dacc[q][ti] = acc[ti];
+                for (int ti = 0; ti < MT; ++ti) dacc[q2][ti] = acc[ti];
             ++nd;
           } else {
             tiles_foreach<R, MT>(acc, tj, [&](int row, int col, int ti, int r) {
@@ -518,16 +696,25 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(Prob P, const double* E, int nE
 #pragma unroll 1
         for (int tj = w; tj < MT; tj += NWAVE) {
 #pragma unroll
-          for (int q = 0; q < DT; ++q)
-            if (q == nd)
-              tiles_foreach<R, MT>(dacc[q], tj, [&](int row, int col, int ti, int r) {
-                mat[row * S + col] = mk<R>(dacc[q][ti].re[r], dacc[q][ti].im[r]);
+          for (int q2 = 0; q2 < DT; ++q2)
+            if (q2 == nd)
+              tiles_foreach<R, MT>(dacc[q2], tj, [&](int row, int col, int ti, int r) {
+                mat[row * S + col] = mk<R>(dacc[q2][ti].re[r], dacc[q2][ti].im[r]);
               });
           ++nd;
         }
       }
       __syncthreads();
       gj_inverse<R, M>(mat, S, Ysc, sc);
+      if constexpr (MIX) {
+        // Dt_i^-1[j][c] = mat[piv[j]][pinv[c]]
+        float2* Di = DI + (size_t)i * MM;
+        for (int idx = t; idx < MM; idx += NT) {
+          const int j = idx / M, c = idx - j * M;
+          const cpx<R> v = mat[sc.piv[j] * S + sc.pinv[c]];
+          Di[idx] = make_float2(v.re, v.im);
+        }
+      }
 #pragma unroll 1
       for (int tj = w; tj < 2 * MT; tj += NWAVE) {
         ctile<R> acc[MT];
@@ -554,7 +741,7 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(Prob P, const double* E, int nE
     }
     __syncthreads();
     // transmission from the left-injected solution on the last slab
-    {
+    if constexpr (!MIX) {
       const V2* XN = XZ + (size_t)(N - 1) * M * LD;
       double tp = 0.0;
 #pragma unroll 1
@@ -603,14 +790,23 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(Prob P, const double* E, int nE
         if (i < N - 1) cgemm_col<R, MT, MT>(acc, ALds<R>{mat, S}, BGlob<R>{PSI, LD}, tj);
         const int cl = 16 * tj + (lane & 15);
         const double sg = cl < M ? sgR[cl] : sgL[cl - M];
+        bool heavy = false, keep = false;
+        if constexpr (MIX) {
+          heavy = tj < MT ? tj < hR : tj - MT < hL;
+          keep = heavy || (i == N - 1 && tj >= MT);
+        }
         double pp = 0.0;
         tiles_foreach<R, MT>(acc, tj, [&](int row, int col, int ti, int r) {
           const double re = acc[ti].re[r], im = acc[ti].im[r];
           st2<R>(PSI + (unsigned)(row * LD + col), mk<R>(acc[ti].re[r], acc[ti].im[r]));
+          if constexpr (MIX)
+            if (keep) P64[(size_t)i * M * LD + (unsigned)(row * LD + col)] = make_double2(re, im);
           pp += re * re + im * im;
         });
-        if (tj < MT) pR += sg * pp;
-        else pL += sg * pp;
+        if (!heavy) {
+          if (tj < MT) pR += sg * pp;
+          else pL += sg * pp;
+        }
       }
       __threadfence_block();
       pL = wave_sum(pL);
@@ -621,86 +817,154 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(Prob P, const double* E, int nE
       }
     }
     __syncthreads();
+    int steps = 0;
+    double rel = 0.0;
+    if constexpr (MIX) {
+      rel = refine<M>(P, a, e, z, hR, hL, (const float2*)XZ, DI, ZC, YB, P64, tred, &steps);
+      // transmission and the heavy columns' densities from the refined solution
+      {
+        const double2* PN = P64 + (size_t)(N - 1) * M * LD;
+        double tp = 0.0;
+#pragma unroll 1
+        for (int tj = MT + w; tj < 2 * MT; tj += NWAVE) {
+          ctile<double> acc[MT];
+#pragma unroll
+          for (int ti = 0; ti < MT; ++ti) tzero(acc[ti]);
+          cgemm_col<double, MT, MT>(acc, AGlobCT<double>{WR, M}, BGlob<double>{PN, LD}, tj);
+          const double sl = sgL[16 * tj + (lane & 15) - M];
+          tiles_foreach<double, MT>(acc, tj, [&](int row, int col, int ti, int r) {
+            const double re = acc[ti].re[r], im = acc[ti].im[r];
+            tp += sgR[row] * sl * (re * re + im * im);
+          });
+        }
+        tp = wave_sum(tp);
+        if (lane == 0) tred[w] = tp;
+      }
+      const int npair = MT * (hR + hL);
+      for (int i = 0; i < N; ++i) {
+        const double2* Pi = P64 + (size_t)i * M * LD;
+        double pL = 0.0, pR = 0.0;
+        for (int p = w; p < npair; p += NWAVE) {
+          const int ti = p % MT, qq = p / MT, tj = qq < hR ? qq : MT + qq - hR;
+          const int cl = 16 * tj + (lane & 15);
+          const double sg = cl < M ? sgR[cl] : sgL[cl - M];
+          double pp = 0.0;
+          ctile<double> acc[1];
+          tiles_foreach<double, 1>(acc, tj, [&](int row, int col, int, int) {
+            const double2 v = Pi[(16 * ti + row) * LD + col];
+            pp += v.x * v.x + v.y * v.y;
+          });
+          if (tj < MT) pR += sg * pp;
+          else pL += sg * pp;
+        }
+        pL = wave_sum(pL);
+        pR = wave_sum(pR);
+        if (lane == 0) {
+          prt2[(w * 2 + 0) * N + i] = pL;
+          prt2[(w * 2 + 1) * N + i] = pR;
+        }
+      }
+      __threadfence_block();
+      __syncthreads();
+    }
     const double ipi = 0.31830988618379067154;
     double Te = 0.0;
-    for (int q = 0; q < NWAVE; ++q) Te += tred[q];
+    for (int q2 = 0; q2 < NWAVE; ++q2) Te += tred[q2];
     bool bad = !isfinite(Te);
     for (int idx = t; idx < 2 * N; idx += NT) {
       const int s = idx / N, i = idx - s * N;
       double v = 0.0;
-      for (int q = 0; q < NWAVE; ++q) v += prt[(q * 2 + s) * N + i];
-      if (ldos) ldos[((size_t)e * 2 + s) * N + i] = v * ipi;
+      for (int q2 = 0; q2 < NWAVE; ++q2) v += prt[(q2 * 2 + s) * N + i];
+      if constexpr (MIX)
+        for (int q2 = 0; q2 < NWAVE; ++q2) v += prt2[(q2 * 2 + s) * N + i];
+      if (a.ldos) a.ldos[((size_t)e * 2 + s) * N + i] = v * ipi;
     }
     if (t == 0) {
-      T[e] = Te;
-      if (info) {
-        const int i0 = iters[2 * e], i1 = iters[2 * e + 1];
+      a.T[e] = Te;
+      const int i0 = a.iters[2 * e], i1 = a.iters[2 * e + 1];
+      const bool rbad = MIX && !(rel <= a.rtol);
+      if constexpr (MIX) a.redo[e] = (rbad || bad) ? 1 : 0;
+      if (a.info) {
         qtx_info inf;
+        if (a.elist) {
+          inf = a.info[e];             // keep the refinement record, mark the fallback
+          inf.fell_back_fp64 = 1;
+        } else {
+          inf.refine_steps = steps;
+          inf.resid = rel;
+          inf.fell_back_fp64 = 0;
+        }
         inf.dec_iters = (i0 < 0 || i1 < 0) ? -1 : (i0 > i1 ? i0 : i1);
-        inf.refine_steps = 0;
-        inf.resid = 0.0;
-        inf.fell_back_fp64 = 0;
-        inf.flags = ((i0 < 0 || i1 < 0) ? QTX_FLAG_DEC_NOTCONV : 0) | (bad ? QTX_FLAG_NONFINITE : 0);
-        info[e] = inf;
+        inf.flags = ((i0 < 0 || i1 < 0) ? QTX_FLAG_DEC_NOTCONV : 0) | (bad ? QTX_FLAG_NONFINITE : 0) |
+                    (rbad ? QTX_FLAG_REFINE_NOTCONV : 0);
+        a.info[e] = inf;
       }
     }
   }
 }
 
+// Energies whose refinement failed, compacted into a list (one wave).
+__global__ __launch_bounds__(64) void k_compact(const int* redo, int nE, int* elist, int* ecount) {
+  const int lane = threadIdx.x;
+  int base = 0;
+  for (int e0 = 0; e0 < nE; e0 += 64) {
+    const int e = e0 + lane;
+    const bool f = e < nE && redo[e] != 0;
+    const unsigned long long m = __ballot(f);
+    const int pre = __popcll(m & ((1ull << lane) - 1ull));
+    if (f) elist[base + pre] = e;
+    base += __popcll(m);
+  }
+  if (lane == 0) *ecount = base;
+}
+
 // ------------------------------------------------------------- launchers
 template <int M>
 hipError_t launch_decimate(const Prob& P, const double* E, int nE, double eta, int sides, double tol,
-                           int maxit, double2* scratch, int grid, double2* sig, double2* wf, double* sgn,
-                           int* iters, hipStream_t st) {
-  hipLaunchKernelGGL((k_decimate<M>), dim3(grid), dim3(NT), 0, st, P, E, nE, eta, sides, tol, maxit,
-                     scratch, sig, wf, sgn, iters);
+                           int maxit, double heavy_tol, double2* scratch, int grid, double2* sig, double2* wf,
+                           double* sgn, int* iters, int* nheavy, hipStream_t st) {
+  hipLaunchKernelGGL((k_decimate<M>), dim3(grid), dim3(NT), 0, st, P, E, nE, eta, sides, tol, maxit, heavy_tol,
+                     scratch, sig, wf, sgn, iters, nheavy);
   return hipGetLastError();
 }
 
-template <typename R, int M>
-hipError_t launch_sweep(const Prob& P, const double* E, int nE, double eta, const double2* sig,
-                        const double2* wf, const double* sgn, const int* iters, void* ws, size_t ws_stride,
-                        double* part, int grid, double* T, double* ldos, qtx_info* info, hipStream_t st) {
-  hipLaunchKernelGGL((k_sweep<R, M>), dim3(grid), dim3(NT), 0, st, P, E, nE, eta, sig, wf, sgn, iters,
-                     (typename vec2t<R>::type*)ws, ws_stride, part, T, ldos, info);
+template <typename R, int M, bool MIX>
+hipError_t launch_sweep(const Prob& P, const SweepArgs& a, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((k_sweep<R, M, MIX>), dim3(grid), dim3(NT), 0, st, P, a);
   return hipGetLastError();
 }
 
 hipError_t run_decimate(int M, const Prob& P, const double* E, int nE, double eta, int sides, double tol,
-                        int maxit, double2* scratch, int grid, double2* sig, double2* wf, double* sgn,
-                        int* iters, hipStream_t st) {
+                        int maxit, double heavy_tol, double2* scratch, int grid, double2* sig, double2* wf,
+                        double* sgn, int* iters, int* nheavy, hipStream_t st) {
+#define QTX_DEC(MM) \
+  return launch_decimate<MM>(P, E, nE, eta, sides, tol, maxit, heavy_tol, scratch, grid, sig, wf, sgn, iters, nheavy, st)
   switch (M) {
-    case 16: return launch_decimate<16>(P, E, nE, eta, sides, tol, maxit, scratch, grid, sig, wf, sgn, iters, st);
-    case 32: return launch_decimate<32>(P, E, nE, eta, sides, tol, maxit, scratch, grid, sig, wf, sgn, iters, st);
-    case 48: return launch_decimate<48>(P, E, nE, eta, sides, tol, maxit, scratch, grid, sig, wf, sgn, iters, st);
-    case 64: return launch_decimate<64>(P, E, nE, eta, sides, tol, maxit, scratch, grid, sig, wf, sgn, iters, st);
+    case 16: QTX_DEC(16);
+    case 32: QTX_DEC(32);
+    case 48: QTX_DEC(48);
+    case 64: QTX_DEC(64);
     default: return hipErrorInvalidValue;
   }
+#undef QTX_DEC
 }
 
-hipError_t run_sweep(int M, bool fp32, const Prob& P, const double* E, int nE, double eta, const double2* sig,
-                     const double2* wf, const double* sgn, const int* iters, void* ws, size_t ws_stride,
-                     double* part, int grid, double* T, double* ldos, qtx_info* info, hipStream_t st) {
-#define QTX_SWEEP(RR, MM) \
-  return launch_sweep<RR, MM>(P, E, nE, eta, sig, wf, sgn, iters, ws, ws_stride, part, grid, T, ldos, info, st)
-  if (!fp32) {
-    switch (M) {
-      case 16: QTX_SWEEP(double, 16);
-      case 32: QTX_SWEEP(double, 32);
-      case 48: QTX_SWEEP(double, 48);
-      case 64: QTX_SWEEP(double, 64);
-      default: return hipErrorInvalidValue;
-    }
-  } else {
-    switch (M) {
-      case 16: QTX_SWEEP(float, 16);
-      case 32: QTX_SWEEP(float, 32);
-      case 48: QTX_SWEEP(float, 48);
-      case 64: QTX_SWEEP(float, 64);
-      default: return hipErrorInvalidValue;
-    }
+hipError_t run_sweep(int M, bool mixed, const Prob& P, const SweepArgs& a, int grid, hipStream_t st) {
+#define QTX_SWEEP(MM) \
+  return mixed ? launch_sweep<float, MM, true>(P, a, grid, st) : launch_sweep<double, MM, false>(P, a, grid, st)
+  switch (M) {
+    case 16: QTX_SWEEP(16);
+    case 32: QTX_SWEEP(32);
+    case 48: QTX_SWEEP(48);
+    case 64: QTX_SWEEP(64);
+    default: return hipErrorInvalidValue;
   }
 #undef QTX_SWEEP
+}
+
+hipError_t run_compact(const int* redo, int nE, int* elist, int* ecount, hipStream_t st) {
+  hipLaunchKernelGGL(k_compact, dim3(1), dim3(64), 0, st, redo, nE, elist, ecount);
+  return hipGetLastError();
 }
 
 }  // namespace qtx

@@ -1,0 +1,142 @@
+"""GPU parity of the mixed-precision path (QTX_MIXED) against the FP64 oracle
+and against the FP64 GPU path.
+
+The bulk of the sweep runs in single precision; the heavy columns of the
+broadening factors are refined against an FP64 residual and the energies
+whose refinement does not converge are re-solved in FP64.
+
+Tolerances: |dT| <= 1e-8 absolute per energy; slab densities
+|dn| <= 1e-8 * max(1, max_i |n_i|) per energy and contact.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1903_00548_amd import _lib
+from paper_1903_00548_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL_T = 1e-8
+TOL_N = 1e-8
+
+
+def _errors(T, L, Tref, Lref):
+    dT = np.abs(T - Tref)
+    scale = np.maximum(1.0, np.abs(Lref).max(axis=2))
+    dn = np.abs(L - Lref).max(axis=2) / scale
+    return dT.max(), dn.max()
+
+
+def _check(T, L, Tref, Lref, label="", tolT=TOL_T, tolN=TOL_N):
+    assert np.all(np.isfinite(T)) and np.all(np.isfinite(L)), label
+    dT, dn = _errors(T, L, Tref, Lref)
+    print(f"{label}: max|dT| = {dT:.3e}, max rel|dn| = {dn:.3e}")
+    assert dT <= tolT, f"{label} max|dT|={dT:.3e}"
+    assert dn <= tolN, f"{label} max rel|dn|={dn:.3e}"
+
+
+def test_mixed_cfg0(gpu_lib):
+    wl = W.config0()
+    ctx = _lib.context_for(wl.device, 0)
+    T, L, info, st = ctx.solve(wl.E, wl.eta, _lib.MIXED)
+    assert st == _lib.OK
+    Tref, Lref = oracle.solve_device(wl.device, wl.E, wl.eta)
+    _check(T, L, Tref, Lref, "cfg0 mixed")
+    assert np.all(info["refine_steps"] <= 3)
+    assert np.all(info["resid"] <= 1e-12) or np.any(info["fell_back_fp64"] == 1)
+
+
+@pytest.mark.parametrize("seed,N,m,uniform,same,mode", [
+    (1, 5, 4, True, True, W.POT_LINEAR_FE),
+    (2, 9, 6, False, False, W.POT_LINEAR_FE),
+    (3, 1, 16, False, False, W.POT_DIAG),
+    (4, 2, 16, True, False, W.POT_LINEAR_FE),
+    (5, 33, 20, False, True, W.POT_DIAG),
+    (6, 17, 48, True, True, W.POT_LINEAR_FE),
+    (7, 12, 64, False, False, W.POT_LINEAR_FE),
+    (8, 3, 1, True, True, W.POT_DIAG),
+])
+def test_mixed_small_devices(gpu_lib, seed, N, m, uniform, same, mode):
+    dev = W.small_random_device(seed, N, m, uniform=uniform, same_leads=same, pot_mode=mode,
+                                VL=0.04 * (seed % 3), VR=-0.03 * (seed % 2))
+    E = np.linspace(-2.0, 2.0, 23)
+    ctx = _lib.context_for(dev, 0)
+    T, L, info, st = ctx.solve(E, 1e-6, _lib.MIXED)
+    Tref, Lref = oracle.solve_device(dev, E, 1e-6)
+    _check(T, L, Tref, Lref, f"seed{seed} mixed")
+
+
+def test_mixed_cfg1_full_size(gpu_lib):
+    """Headline workload, 2048 energies in one call: every energy against the
+    FP64 GPU path (held to 1e-10 of the oracle by the FP64 parity tests),
+    12 sampled energies against the oracle directly."""
+    wl = W.config1()
+    dev = wl.device
+    ctx = _lib.context_for(dev, 0)
+    T64, L64, _, _ = ctx.solve(wl.E, wl.eta, _lib.FP64)
+    T, L, info, st = ctx.solve(wl.E, wl.eta, _lib.MIXED)
+    assert st == _lib.OK
+    _check(T, L, T64, L64, "cfg1 mixed vs fp64 (all 2048)", tolT=TOL_T - 1e-10, tolN=TOL_N)
+    rng = np.random.default_rng(4321)
+    idx = np.sort(np.concatenate([[0, len(wl.E) - 1], rng.choice(len(wl.E), 10, replace=False)]))
+    Tref, Lref = oracle.solve_device(dev, wl.E[idx], wl.eta)
+    _check(T[idx], L[idx], Tref, Lref, "cfg1 mixed vs oracle (sampled)")
+    steps = info["refine_steps"]
+    print("refinement steps histogram:", np.bincount(steps, minlength=4).tolist(),
+          "fallbacks:", int(info["fell_back_fp64"].sum()))
+    assert steps.max() <= 3
+
+
+def test_mixed_forced_fallback_is_the_fp64_result(gpu_lib):
+    """No correction allowed and an unreachable tolerance: every energy is
+    re-solved by the FP64 sweep, whose result must be bitwise the FP64
+    path's, with the fallback recorded and no flag left set."""
+    wl = W.config0()
+    ctx = _lib.context_for(wl.device, 0)
+    T64, L64, _, _ = ctx.solve(wl.E, wl.eta, _lib.FP64)
+    ctx.set_option("refine_max_steps", 0)
+    ctx.set_option("refine_tol", 1e-300)
+    T, L, info, st = ctx.solve(wl.E, wl.eta, _lib.MIXED)
+    assert st == _lib.OK
+    assert np.array_equal(T, T64) and np.array_equal(L, L64)
+    assert np.all(info["fell_back_fp64"] == 1)
+    assert np.all(info["flags"] == 0)
+    assert np.all(info["refine_steps"] == 0)
+
+
+def test_mixed_refine_every_column(gpu_lib):
+    """refine_weight_tol = 0 refines every column of both injections: the
+    densities then carry no single-precision error either."""
+    wl = W.config0()
+    ctx = _lib.context_for(wl.device, 0)
+    ctx.set_option("refine_weight_tol", 0.0)
+    T, L, info, st = ctx.solve(wl.E, wl.eta, _lib.MIXED)
+    Tref, Lref = oracle.solve_device(wl.device, wl.E, wl.eta)
+    _check(T, L, Tref, Lref, "cfg0 mixed, all columns refined", tolT=1e-9, tolN=1e-9)
+
+
+def test_set_option_validation(gpu_lib):
+    ctx = _lib.Context(0)
+    for name, bad in (("refine_tol", 0.0), ("refine_tol", 2.0), ("refine_max_steps", 1.5),
+                      ("refine_max_steps", -1), ("refine_weight_tol", -0.1), ("workgroups_per_cu", 3),
+                      ("energies_per_launch", 0), ("decimation_max_iters", 0), ("no_such_option", 1.0)):
+        with pytest.raises(_lib.QtxError) as ei:
+            ctx.set_option(name, bad)
+        assert ei.value.status == _lib.EINVAL, name
+    for name, ok in (("refine_tol", 1e-10), ("refine_max_steps", 2), ("refine_weight_tol", 0.0),
+                     ("workgroups_per_cu", 1), ("energies_per_launch", 100), ("decimation_tol", 1e-13),
+                     ("decimation_max_iters", 80)):
+        ctx.set_option(name, ok)
+
+
+def test_mixed_chunked_launches_match_single_launch(gpu_lib):
+    """Energies split over several launches (and one workgroup per CU) give
+    the same results as one launch."""
+    wl = W.config0()
+    ctx = _lib.context_for(wl.device, 0)
+    T1, L1, _, _ = ctx.solve(wl.E, wl.eta, _lib.MIXED)
+    ctx.set_option("energies_per_launch", 7)
+    ctx.set_option("workgroups_per_cu", 1)
+    T2, L2, _, _ = ctx.solve(wl.E, wl.eta, _lib.MIXED)
+    assert np.array_equal(T1, T2) and np.array_equal(L1, L2)
