@@ -42,10 +42,24 @@ __device__ __forceinline__ cpx<R> cfms(cpx<R> a, cpx<R> f, cpx<R> p) {
 }
 template <typename R>
 __device__ __forceinline__ cpx<R> cconj(cpx<R> a) { return mk<R>(a.re, -a.im); }
+// 1/d from the hardware reciprocal estimate refined by Newton steps
+// r <- r + r (1 - d r) (each step doubles the number of correct bits).
+__device__ __forceinline__ double recip(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-d, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ float recip(float d) {
+  float r = __builtin_amdgcn_rcpf(d);
+  float e = fmaf(-d, r, 1.0f);
+  return fmaf(r, e, r);
+}
 template <typename R>
 __device__ __forceinline__ cpx<R> cinv(cpx<R> a) {
-  R d = a.re * a.re + a.im * a.im;
-  return mk<R>(a.re / d, -a.im / d);
+  const R r = recip(a.re * a.re + a.im * a.im);
+  return mk<R>(a.re * r, -a.im * r);
 }
 template <typename R>
 __device__ __forceinline__ R cabs1(cpx<R> a) { return fabs(a.re) + fabs(a.im); }

@@ -13,11 +13,11 @@ namespace qtx {
 
 // ------------------------------------------------------------ Gauss-Jordan
 // Blocked Gauss-Jordan elimination with partial pivoting (no physical row
-// exchanges; the permutation is undone on the way out).  For each panel of
-// 16 columns one wave eliminates the panel in registers (one matrix row per
-// lane, pivot search by a DPP max reduction, no workgroup barrier), leaving
-// in the panel G = E e_p, the panel transform applied to the unit vectors of
-// its pivot rows.  Every other column x is then updated by
+// exchanges; the permutation is undone on the way out).  Each panel of 16
+// columns is eliminated in registers by the four waves together (one
+// matrix row per lane, four panel columns per wave), leaving in the panel
+// G = E e_p, the panel transform applied to the unit vectors of its pivot
+// rows.  Every other column x is then updated by
 //   x' = x (pivot rows of the panel zeroed) + G y,   y_jj = x[p_jj],
 // as 16x16 complex MFMA tiles shared by all waves.
 
@@ -25,84 +25,71 @@ template <typename R, int M> struct BGJ {
   int piv[M];        // pivot row chosen for column j
   int pinv[M];
   int ppanel[M];     // panel in which row r became a pivot, -1 before
-  cpx<R> prow[16];   // pivot row of the current step (panel part)
 };
 
-// Wave-level elimination of panel k (columns 16k..16k+15) of the LDS matrix.
-// The step loop is unrolled (static column index) with a scheduling barrier
-// after every step so that steps do not interleave.  Latency chain of one
-// step: pivot key -> DPP max -> the pivot lane writes its raw row to LDS
-// while every lane forms the reciprocal of the pivot -> every lane reads the
-// row back and scales it on the fly.  LDS operations of one wave complete in
-// issue order, so the write/read pair needs no wait beyond the compiler
-// barrier.  The pivot row is produced by the same fused multiply-subtract
-// as the others (base 0, factor -1).
+// LDS scratch (complex elements) that gj_inverse needs beside the matrix:
+// the compacted pivot rows of the panel update, and during the panel the
+// double-buffered row multipliers.
+template <int M> constexpr int gj_scratch() { return 16 * (M - 16) > 128 ? 16 * (M - 16) : 128; }
+
+// Elimination of panel k (columns 16k..16k+15) of the LDS matrix; wave w
+// holds columns 16k+4w .. 16k+4w+3 of every row.  Step jj: the wave owning
+// column jj finds the pivot row p (DPP max over the unused rows), forms the
+// row multipliers m_r = x_rj / x_pj (the pivot row takes -1 / x_pj) and
+// publishes them and p through LDS; after one barrier every wave reads the
+// pivot row's entries of its own columns from lane p and updates
+//   x_rc <- x_rc - m_r x_pc  (c != j, with x_pc read as 0 in row p),
+//   x_rj <- -m_r.
+// The multipliers alternate between two LDS buffers, so that one barrier
+// per step orders both the publication and the reuse.
 template <typename R, int M>
-__device__ __forceinline__ void gj_panel(cpx<R>* mat, int S, int k, BGJ<R, M>& sc) {
-  constexpr int RL = (M + 63) / 64;  // rows per lane
-  const int lane = threadIdx.x & 63;
-  cpx<R> pr[RL][16];
-  bool used[RL];
+__device__ __forceinline__ void gj_panel(cpx<R>* mat, int S, int k, BGJ<R, M>& sc, cpx<R>* mb) {
+  static_assert(M <= 64, "one matrix row per lane");
+  const int lane = lane_id(), w = threadIdx.x >> 6;
+  const bool ok = lane < M;
+  const int c0 = 16 * k + 4 * w;
+  cpx<R> pr[4];
 #pragma unroll
-  for (int q = 0; q < RL; ++q) {
-    const int r = lane + 64 * q;
-    const bool ok = r < M;
-#pragma unroll
-    for (int c = 0; c < 16; ++c) pr[q][c] = ok ? mat[r * S + 16 * k + c] : mk<R>(0, 0);
-    used[q] = !ok || sc.ppanel[r] >= 0;
-  }
+  for (int c = 0; c < 4; ++c) pr[c] = ok ? mat[lane * S + c0 + c] : mk<R>(0, 0);
+  bool used = true;
+  if (ok) used = sc.ppanel[lane] >= 0;
 #pragma unroll
   for (int jj = 0; jj < 16; ++jj) {
-    uint32_t key = 0;
-#pragma unroll
-    for (int q = 0; q < RL; ++q)
-      if (!used[q]) {
-        const uint32_t kq = pivot_key32(pr[q][jj], lane + 64 * q);
-        key = kq > key ? kq : key;
-      }
-    key = wave_max_u32(key);
-    const int p = 255 - (int)(key & 0xff);
-    const int pl = p & 63, pq = p >> 6;
-    bool isp[RL];
-    cpx<R> f[RL];
-    cpx<R> pvt = mk<R>(0, 0);
-#pragma unroll
-    for (int q = 0; q < RL; ++q) {
-      isp[q] = (q == pq) && (lane == pl);
-      if (isp[q])
-#pragma unroll
-        for (int c = 0; c < 16; ++c) sc.prow[c] = pr[q][c];
-      if (q == pq) pvt = mk<R>(readlane_d(pr[q][jj].re, pl), readlane_d(pr[q][jj].im, pl));
-      f[q] = isp[q] ? mk<R>(-1, 0) : pr[q][jj];
-    }
-    const cpx<R> inv = cinv(pvt);
-    __builtin_amdgcn_wave_barrier();
-#pragma unroll
-    for (int c = 0; c < 16; ++c) {
-      const cpx<R> pvc = (c == jj) ? inv : cmul(sc.prow[c], inv);
-#pragma unroll
-      for (int q = 0; q < RL; ++q) {
-        const cpx<R> base = (c == jj || isp[q]) ? mk<R>(0, 0) : pr[q][c];
-        pr[q][c] = cfms(base, f[q], pvc);
+    const int owner = jj >> 2, cj = jj & 3;
+    cpx<R>* mbj = mb + (jj & 1) * 64;
+    if (w == owner) {
+      uint32_t key = used ? 0u : pivot_key32(pr[cj], lane);
+      key = wave_max_u32(key);
+      const int p = 255 - (int)(key & 0xff);
+      const cpx<R> pvt = mk<R>(readlane_d(pr[cj].re, p), readlane_d(pr[cj].im, p));
+      const cpx<R> inv = cinv(pvt);
+      mbj[lane] = lane == p ? mk<R>(-inv.re, -inv.im) : cmul(pr[cj], inv);
+      if (lane == 0) {
+        sc.piv[16 * k + jj] = p;
+        sc.ppanel[p] = k;
       }
     }
+    __syncthreads();
+    const int p = __builtin_amdgcn_readfirstlane(sc.piv[16 * k + jj]);
+    const cpx<R> m = mbj[lane];
+    const bool isp = lane == p;
+    cpx<R> prow[4];
 #pragma unroll
-    for (int q = 0; q < RL; ++q)
-      if (isp[q]) used[q] = true;
-    if (lane == 0) {
-      sc.piv[16 * k + jj] = p;
-      sc.ppanel[p] = k;
+    for (int c = 0; c < 4; ++c) prow[c] = mk<R>(readlane_d(pr[c].re, p), readlane_d(pr[c].im, p));
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      if (c == cj && w == owner) {
+        pr[c] = mk<R>(-m.re, -m.im);
+      } else {
+        const cpx<R> base = isp ? mk<R>(0, 0) : pr[c];
+        pr[c] = cfms(base, m, prow[c]);
+      }
     }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_sched_barrier(0);
+    if (isp) used = true;
   }
+  if (ok)
 #pragma unroll
-  for (int q = 0; q < RL; ++q) {
-    const int r = lane + 64 * q;
-    if (r < M)
-#pragma unroll
-      for (int c = 0; c < 16; ++c) mat[r * S + 16 * k + c] = pr[q][c];
-  }
+    for (int c = 0; c < 4; ++c) mat[lane * S + c0 + c] = pr[c];
 }
 
 // One 16x16 output tile of the panel update: X[ti, tc] <- masked X + G Y.
@@ -123,7 +110,7 @@ __device__ __forceinline__ void gj_update_tile(const cpx<R>* mat, int S, int k, 
 }
 
 // In-place Gauss-Jordan on the M x M LDS matrix (row stride S); Y is LDS
-// scratch of 16 x (M - 16).  The result is the inverse up to the pivot order:
+// scratch of gj_scratch<M>() elements.  The result is the inverse up to the pivot order:
 // A^-1[j][c] = mat[piv[j]][pinv[c]], so A^-1 B = P (mat (Q B)) with
 // (Q B)[k] = B[piv[k]] and row r of the product landing in row pinv[r].
 // Ends with a barrier.
@@ -134,7 +121,7 @@ __device__ __forceinline__ void gj_inverse(cpx<R>* mat, int S, cpx<R>* Y, BGJ<R,
   if (t < M) sc.ppanel[t] = -1;
   __syncthreads();
   for (int k = 0; k < NP; ++k) {
-    if (w == 0) gj_panel<R, M>(mat, S, k, sc);
+    gj_panel<R, M>(mat, S, k, sc, Y);
     __syncthreads();
     // pivot rows of the columns outside the panel, compacted (16 x (M-16))
     constexpr int WY = M - 16;
@@ -263,7 +250,7 @@ __global__ __launch_bounds__(NT, 2) void k_decimate(Prob P, const double* E, int
   constexpr int MT = M / 16, MM = M * M, S = M + 1, LB = 2 * M;
   __shared__ cpx<double> mat[M * S];
   __shared__ union {
-    cpx<double> y[16 * (M - 16 > 0 ? M - 16 : 1)];
+    cpx<double> y[gj_scratch<M>()];
     LDLScratch<M> ldl;
   } u;
   __shared__ BGJ<double, M> sc;
@@ -572,7 +559,7 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(Prob P, SweepArgs a) {
   typedef typename vec2t<R>::type V2;
   constexpr int MT = M / 16, MM = M * M, S = M + 1, LD = 2 * M;
   __shared__ cpx<R> mat[M * S];
-  __shared__ cpx<R> Ysc[16 * (M - 16 > 0 ? M - 16 : 1)];
+  __shared__ cpx<R> Ysc[gj_scratch<M>()];
   __shared__ BGJ<R, M> sc;
   __shared__ double tred[NWAVE];
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
