@@ -92,21 +92,64 @@ __device__ __forceinline__ void gj_panel(cpx<R>* mat, int S, int k, BGJ<R, M>& s
     for (int c = 0; c < 4; ++c) mat[lane * S + c0 + c] = pr[c];
 }
 
-// One 16x16 output tile of the panel update: X[ti, tc] <- masked X + G Y.
-template <typename R, int M, class XLoad, class XStore>
-__device__ __forceinline__ void gj_update_tile(const cpx<R>* mat, int S, int k, const cpx<R>* Y, int ldy, int ycol,
-                                               int ti, const BGJ<R, M>& sc, XLoad xl, XStore xs) {
-  ctile<R> acc[1];
-  tiles_foreach<R, 1>(acc, 0, [&](int row, int col, int, int r) {
-    const int gr = 16 * ti + row;
-    cpx<R> v = sc.ppanel[gr] == k ? mk<R>(0, 0) : xl(gr, col);
-    acc[0].re[r] = v.re;
-    acc[0].im[r] = v.im;
-  });
-  cgemm_col<R, 1, 1>(acc, ALds<R>{mat + 16 * ti * S + 16 * k, S}, BLds<R>{Y + ycol, ldy}, 0);
-  tiles_foreach<R, 1>(acc, 0, [&](int row, int col, int, int r) {
-    xs(16 * ti + row, col, mk<R>(acc[0].re[r], acc[0].im[r]));
-  });
+// Panel update x' = (x with the panel's pivot rows zeroed) + G y for every
+// 16x16 tile outside panel k (G: the panel columns, y: the compacted pivot
+// rows in Y, row stride M - 16).  The tiles are dealt round-robin to the
+// waves; each wave runs its (at most TPW) tiles through one interleaved
+// MFMA loop, so that 2 TPW accumulator chains are in flight.  A wave's
+// surplus slots recompute a valid tile and do not store it.
+template <typename R, int M>
+__device__ __forceinline__ void gj_update(cpx<R>* mat, int S, int k, const cpx<R>* Y, const BGJ<R, M>& sc) {
+  constexpr int MT = M / 16, NTILE = MT * (MT - 1), TPW = (NTILE + NWAVE - 1) / NWAVE, WY = M - 16;
+  if constexpr (NTILE > 0) {
+    const int w = threadIdx.x >> 6, lane = lane_id(), g = lane >> 4, c = lane & 15;
+    int arow[TPW], bcol[TPW], xcol[TPW];
+    bool keep[TPW];
+    ctile<R> acc[TPW];
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) {
+      int tile = w + NWAVE * q;
+      keep[q] = tile < NTILE;
+      tile = keep[q] ? tile : 0;
+      const int ti = tile % MT, tcx = tile / MT, tc = tcx + (tcx >= k ? 1 : 0);
+      arow[q] = 16 * ti;
+      bcol[q] = 16 * tcx + c;
+      xcol[q] = 16 * tc + c;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = arow[q] + mf<R>::row(r, g);
+        const cpx<R> v = sc.ppanel[row] == k ? mk<R>(0, 0) : mat[row * S + xcol[q]];
+        acc[q].re[r] = v.re;
+        acc[q].im[r] = v.im;
+      }
+    }
+#pragma unroll
+    for (int sl = 0; sl < 4; ++sl) {
+      const int kk = 4 * g + sl;
+      cpx<R> av[TPW], bv[TPW];
+#pragma unroll
+      for (int q = 0; q < TPW; ++q) {
+        av[q] = mat[(arow[q] + c) * S + 16 * k + kk];
+        bv[q] = Y[kk * WY + bcol[q]];
+      }
+#pragma unroll
+      for (int q = 0; q < TPW; ++q) {
+        acc[q].re = mf<R>::op(av[q].re, bv[q].re, acc[q].re);
+        acc[q].im = mf<R>::op(av[q].re, bv[q].im, acc[q].im);
+      }
+#pragma unroll
+      for (int q = 0; q < TPW; ++q) {
+        acc[q].re = mf<R>::op(-av[q].im, bv[q].im, acc[q].re);
+        acc[q].im = mf<R>::op(av[q].im, bv[q].re, acc[q].im);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < TPW; ++q)
+      if (keep[q])
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          mat[(arow[q] + mf<R>::row(r, g)) * S + xcol[q]] = mk<R>(acc[q].re[r], acc[q].im[r]);
+  }
 }
 
 // In-place Gauss-Jordan on the M x M LDS matrix (row stride S); Y is LDS
@@ -131,13 +174,7 @@ __device__ __forceinline__ void gj_inverse(cpx<R>* mat, int S, cpx<R>* Y, BGJ<R,
       Y[idx] = mat[sc.piv[16 * k + jj] * S + c];
     }
     __syncthreads();
-    for (int tile = w; tile < MT * (NP - 1); tile += NWAVE) {
-      const int ti = tile % MT, tcx = tile / MT, tc = tcx + (tcx >= k ? 1 : 0);
-      gj_update_tile<R, M>(
-          mat, S, k, Y, WY, 16 * tcx, ti, sc,
-          [&](int row, int col) { return mat[row * S + 16 * tc + col]; },
-          [&](int row, int col, cpx<R> v) { mat[row * S + 16 * tc + col] = v; });
-    }
+    gj_update<R, M>(mat, S, k, Y, sc);
     __syncthreads();
   }
   if (t < M) sc.pinv[sc.piv[t]] = t;
@@ -336,35 +373,47 @@ __global__ __launch_bounds__(NT, 2) void k_decimate(Prob P, const double* E, int
         });
       }
       // doubling update: output column tile tj reads column tiles tj (g a)
-      // and MT + tj (g b) of X, written by other waves unless M/16 == NWAVE
+      // and MT + tj (g b) of X, written by other waves unless M/16 == NWAVE.
+      // g is dead from here on: a, then b, is staged in its LDS buffer as
+      // the shared A operand of the two products that use it.
       __syncthreads();
       double na = 0.0, nb = 0.0;
 #pragma unroll 1
-      for (int tj = w; tj < MT; tj += NWAVE) {
-        // one accumulator column live at a time: a g b, b g a, a g a, b g b
-#pragma unroll 1
-        for (int q = 0; q < 4; ++q) {
-          ctile<double> acc[MT];
-#pragma unroll
-          for (int ti = 0; ti < MT; ++ti) tzero(acc[ti]);
-          const double2* Aop = (q == 0 || q == 2) ? AB : AB + M;
-          const double2* Bop = (q == 0 || q == 3) ? X + M : X;
-          cgemm_col<double, MT, MT>(acc, AGlob<double>{Aop, LB, 1.0}, BGlob<double>{Bop, LB}, tj);
-          tiles_foreach<double, MT>(acc, tj, [&](int row, int col, int ti, int r) {
-            const unsigned idx = row * M + col;
-            const double re = acc[ti].re[r], im = acc[ti].im[r];
-            if (q < 2) {
-              double2 v = eps[idx];
-              v.x -= re; v.y -= im; eps[idx] = v;
-              double2* es = q == 0 ? esR : esL;
-              v = es[idx]; v.x -= re; v.y -= im; es[idx] = v;
-            } else {
-              ABn[(unsigned)(row * LB + col) + (q == 3 ? M : 0)] = make_double2(-re, -im);
-              if (q == 2) na = fmax(na, fabs(re) + fabs(im));
-              else nb = fmax(nb, fabs(re) + fabs(im));
-            }
-          });
+      for (int half = 0; half < 2; ++half) {
+        const double2* Aop = AB + half * M;
+        for (int idx = t; idx < MM; idx += NT) {
+          const int r = idx / M, c = idx - r * M;
+          mat[r * S + c] = ldd(Aop + r * LB + c);
         }
+        __syncthreads();
+#pragma unroll 1
+        for (int tj = w; tj < MT; tj += NWAVE) {
+          // one accumulator column live at a time: a g b, a g a | b g a, b g b
+#pragma unroll 1
+          for (int qq = 0; qq < 2; ++qq) {
+            const int q = half == 0 ? 2 * qq : 1 + 2 * qq;
+            ctile<double> acc[MT];
+#pragma unroll
+            for (int ti = 0; ti < MT; ++ti) tzero(acc[ti]);
+            const double2* Bop = (q == 0 || q == 3) ? X + M : X;
+            cgemm_col<double, MT, MT>(acc, ALds<double>{mat, S}, BGlob<double>{Bop, LB}, tj);
+            tiles_foreach<double, MT>(acc, tj, [&](int row, int col, int ti, int r) {
+              const unsigned idx = row * M + col;
+              const double re = acc[ti].re[r], im = acc[ti].im[r];
+              if (q < 2) {
+                double2 v = eps[idx];
+                v.x -= re; v.y -= im; eps[idx] = v;
+                double2* es = q == 0 ? esR : esL;
+                v = es[idx]; v.x -= re; v.y -= im; es[idx] = v;
+              } else {
+                ABn[(unsigned)(row * LB + col) + (q == 3 ? M : 0)] = make_double2(-re, -im);
+                if (q == 2) na = fmax(na, fabs(re) + fabs(im));
+                else nb = fmax(nb, fabs(re) + fabs(im));
+              }
+            });
+          }
+        }
+        __syncthreads();
       }
       na = wave_maxd(na);
       nb = wave_maxd(nb);
