@@ -38,7 +38,6 @@ struct DevBuf {
   template <typename T> T* as() const { return static_cast<T*>(p); }
 };
 
-int pad16(int m) { return ((m + 15) / 16) * 16; }
 
 }  // namespace
 
@@ -148,9 +147,11 @@ bool leads_identical(const qtx_ctx* c) {
 qtx_status check_ready(qtx_ctx* c) {
   if (!c->lead_set[0] || !c->lead_set[1]) return fail(c, QTX_ESTATE, "both leads must be set before solving");
   if (!c->dev_set) return fail(c, QTX_ESTATE, "device must be set before solving");
-  if (c->M > 64) return fail(c, QTX_EINVAL, "block size above 64 is not supported by this build");
   return QTX_OK;
 }
+
+// Resident workgroups per CU: blocks above 64 take a whole CU.
+int wgs_per_cu(const qtx_ctx* c) { return c->M > 64 ? 1 : c->wg_per_cu; }
 
 qtx::Prob make_prob(const qtx_ctx* c) {
   qtx::Prob P;
@@ -180,13 +181,13 @@ qtx_status stage_decimate(qtx_ctx* c, const double* E_dev, int nE, double eta) {
   const int M = c->M;
   const size_t MM = (size_t)M * M;
   const int sides = leads_identical(c) ? 1 : 2;
-  const int grid = std::max(1, std::min(nE * sides, c->num_cu * c->wg_per_cu));
+  const int grid = std::max(1, std::min(nE * sides, c->num_cu * wgs_per_cu(c)));
   QTX_HIP(c, c->sig.ensure((size_t)nE * 2 * MM * sizeof(double2)));
   QTX_HIP(c, c->wf.ensure((size_t)nE * 2 * MM * sizeof(double2)));
   QTX_HIP(c, c->sgn.ensure((size_t)nE * 2 * M * sizeof(double)));
   QTX_HIP(c, c->iters.ensure((size_t)nE * 2 * sizeof(int)));
   QTX_HIP(c, c->nheavy.ensure((size_t)nE * 2 * sizeof(int)));
-  QTX_HIP(c, c->dscr.ensure((size_t)grid * 13 * MM * sizeof(double2)));
+  QTX_HIP(c, c->dscr.ensure((size_t)grid * qtx::dec_ws_elems(M) * sizeof(double2)));
   qtx::Prob P = make_prob(c);
   QTX_HIP(c, record(c, c->ev_dec, c->n_dec));
   QTX_HIP(c, qtx::run_decimate(M, P, E_dev, nE, eta, sides, c->dec_tol, c->dec_maxit, c->heavy_tol,
@@ -210,7 +211,7 @@ qtx_status solve_device_core(qtx_ctx* c, const double* E_dev, int nE, double eta
     const int ne = std::min(c->chunk, nE - e0);
     s = stage_decimate(c, E_dev + e0, ne, eta);
     if (s != QTX_OK) return s;
-    const int grid = std::max(1, std::min(ne, c->num_cu * c->wg_per_cu));
+    const int grid = std::max(1, std::min(ne, c->num_cu * wgs_per_cu(c)));
     const size_t wsb = qtx::sweep_ws_bytes(N, M, mixed);
     QTX_HIP(c, c->sws.ensure((size_t)grid * wsb));
     QTX_HIP(c, c->part.ensure((size_t)grid * 4 * 2 * N * (mixed ? 2 : 1) * sizeof(double)));
@@ -329,7 +330,7 @@ qtx_status qtx_set_lead(qtx_ctx* c, qtx_side side, int m, const qtx_c128* H00, c
     return fail(c, QTX_EINVAL, "H00 and S00 must be Hermitian");
   hipSetDevice(c->device);
   c->m = m;
-  c->M = pad16(m);
+  c->M = qtx::padded_block(m);
   const int M = c->M;
   const size_t MM = (size_t)M * M;
   std::vector<double2> h(4 * MM);
@@ -360,7 +361,7 @@ qtx_status qtx_set_device(qtx_ctx* c, int N, int m, const qtx_c128* Hd, const qt
   if (!none && given != 4) return fail(c, QTX_EINVAL, "give all four device block arrays or none");
   hipSetDevice(c->device);
   c->m = m;
-  c->M = pad16(m);
+  c->M = qtx::padded_block(m);
   if (none) {
     if (!c->lead_set[0]) return fail(c, QTX_ESTATE, "a uniform device copies the left lead: set it first");
     c->uniform = true;
@@ -454,7 +455,6 @@ qtx_status qtx_self_energy(qtx_ctx* c, const double* E, int nE, double eta, qtx_
   if (nE == 0) return QTX_OK;
   if (!E || !sigma) return fail(c, QTX_EINVAL, "E and sigma must not be NULL");
   if (!c->lead_set[0] || !c->lead_set[1]) return fail(c, QTX_ESTATE, "both leads must be set");
-  if (c->M > 64) return fail(c, QTX_EINVAL, "block size above 64 is not supported by this build");
   hipSetDevice(c->device);
   const int m = c->m, M = c->M;
   const size_t MM = (size_t)M * M;

@@ -74,12 +74,26 @@ struct SweepArgs {
 // Schur complements (M x M floats); the correction columns (N M x 2M
 // floats); one slab of right-hand sides (M x 2M floats); the refined
 // solution (N M x 2M doubles).
+// Blocks above 64 (96, 128) keep two more M x (M + 1) complex matrices of
+// the sweep precision at the end: the working matrix and the staged
+// coupling block.
 inline size_t sweep_ws_bytes(int N, int M, bool mixed) {
   const size_t MM = (size_t)M * M;
-  if (!mixed) return (size_t)(N + 1) * 2 * MM * sizeof(double2);
+  const size_t big = M > 64 ? 2 * (size_t)M * (M + 1) * (mixed ? sizeof(float2) : sizeof(double2)) : 0;
+  if (!mixed) return (size_t)(N + 1) * 2 * MM * sizeof(double2) + big;
   return ((size_t)(N + 1) * 2 * MM + (size_t)N * MM + (size_t)N * 2 * MM + 2 * MM) * sizeof(float2) +
-         (size_t)N * 2 * MM * sizeof(double2);
+         (size_t)N * 2 * MM * sizeof(double2) + big;
 }
+
+// Per-workgroup decimation workspace (complex doubles): e, the two surface
+// blocks, [a | b] twice, g [a | b], the residual, and for M > 64 the working
+// matrix M x (M + 1).
+__host__ __device__ constexpr size_t dec_ws_elems(int M) {
+  return 13 * (size_t)M * M + (M > 64 ? (size_t)M * (M + 1) : 0);
+}
+
+// Padded block size for a physical block size m (1 <= m <= 128).
+inline int padded_block(int m) { return m <= 64 ? ((m + 15) / 16) * 16 : (m <= 96 ? 96 : 128); }
 
 hipError_t run_decimate(int M, const Prob& P, const double* E, int nE, double eta, int sides, double tol,
                         int maxit, double heavy_tol, double2* scratch, int grid, double2* sig, double2* wf,

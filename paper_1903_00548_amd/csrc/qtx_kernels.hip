@@ -30,40 +30,60 @@ template <typename R, int M> struct BGJ {
 // LDS scratch (complex elements) that gj_inverse needs beside the matrix:
 // the compacted pivot rows of the panel update, and during the panel the
 // double-buffered row multipliers.
-template <int M> constexpr int gj_scratch() { return 16 * (M - 16) > 128 ? 16 * (M - 16) : 128; }
+template <int M> constexpr int gj_scratch() {
+  return 16 * (M - 16) > 2 * 64 * ((M + 63) / 64) ? 16 * (M - 16) : 2 * 64 * ((M + 63) / 64);
+}
 
-// Elimination of panel k (columns 16k..16k+15) of the LDS matrix; wave w
-// holds columns 16k+4w .. 16k+4w+3 of every row.  Step jj: the wave owning
-// column jj finds the pivot row p (DPP max over the unused rows), forms the
-// row multipliers m_r = x_rj / x_pj (the pivot row takes -1 / x_pj) and
-// publishes them and p through LDS; after one barrier every wave reads the
-// pivot row's entries of its own columns from lane p and updates
+// Elimination of panel k (columns 16k..16k+15) of the matrix; wave w holds
+// columns 16k+4w .. 16k+4w+3 of every row (rows lane, lane + 64, ...).
+// Step jj: the wave owning column jj finds the pivot row p (DPP max over
+// the unused rows), forms the row multipliers m_r = x_rj / x_pj (the pivot
+// row takes -1 / x_pj) and publishes them and p through LDS; after one
+// barrier every wave reads the pivot row's entries of its own columns from
+// the lane that holds row p and updates
 //   x_rc <- x_rc - m_r x_pc  (c != j, with x_pc read as 0 in row p),
 //   x_rj <- -m_r.
 // The multipliers alternate between two LDS buffers, so that one barrier
 // per step orders both the publication and the reuse.
 template <typename R, int M>
 __device__ __forceinline__ void gj_panel(cpx<R>* mat, int S, int k, BGJ<R, M>& sc, cpx<R>* mb) {
-  static_assert(M <= 64, "one matrix row per lane");
+  constexpr int RL = (M + 63) / 64;             // rows per lane
+  static_assert(M <= 128, "pivot keys carry 8-bit row indices");
   const int lane = lane_id(), w = threadIdx.x >> 6;
-  const bool ok = lane < M;
   const int c0 = 16 * k + 4 * w;
-  cpx<R> pr[4];
+  cpx<R> pr[RL][4];
+  bool used[RL];
 #pragma unroll
-  for (int c = 0; c < 4; ++c) pr[c] = ok ? mat[lane * S + c0 + c] : mk<R>(0, 0);
-  bool used = true;
-  if (ok) used = sc.ppanel[lane] >= 0;
+  for (int q = 0; q < RL; ++q) {
+    const int r = lane + 64 * q;
+    const bool ok = r < M;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) pr[q][c] = ok ? mat[r * S + c0 + c] : mk<R>(0, 0);
+    used[q] = true;
+    if (ok) used[q] = sc.ppanel[r] >= 0;
+  }
 #pragma unroll
   for (int jj = 0; jj < 16; ++jj) {
     const int owner = jj >> 2, cj = jj & 3;
-    cpx<R>* mbj = mb + (jj & 1) * 64;
+    cpx<R>* mbj = mb + (jj & 1) * 64 * RL;
     if (w == owner) {
-      uint32_t key = used ? 0u : pivot_key32(pr[cj], lane);
+      uint32_t key = 0;
+#pragma unroll
+      for (int q = 0; q < RL; ++q)
+        if (!used[q]) {
+          const uint32_t kq = pivot_key32(pr[q][cj], lane + 64 * q);
+          key = kq > key ? kq : key;
+        }
       key = wave_max_u32(key);
-      const int p = 255 - (int)(key & 0xff);
-      const cpx<R> pvt = mk<R>(readlane_d(pr[cj].re, p), readlane_d(pr[cj].im, p));
+      const int p = 255 - (int)(key & 0xff), pl = RL == 1 ? p : p & 63, pq = RL == 1 ? 0 : p >> 6;
+      cpx<R> pvt = mk<R>(0, 0);
+#pragma unroll
+      for (int q = 0; q < RL; ++q)
+        if (q == pq) pvt = mk<R>(readlane_d(pr[q][cj].re, pl), readlane_d(pr[q][cj].im, pl));
       const cpx<R> inv = cinv(pvt);
-      mbj[lane] = lane == p ? mk<R>(-inv.re, -inv.im) : cmul(pr[cj], inv);
+#pragma unroll
+      for (int q = 0; q < RL; ++q)
+        mbj[lane + 64 * q] = (q == pq && lane == pl) ? mk<R>(-inv.re, -inv.im) : cmul(pr[q][cj], inv);
       if (lane == 0) {
         sc.piv[16 * k + jj] = p;
         sc.ppanel[p] = k;
@@ -71,89 +91,109 @@ __device__ __forceinline__ void gj_panel(cpx<R>* mat, int S, int k, BGJ<R, M>& s
     }
     __syncthreads();
     const int p = __builtin_amdgcn_readfirstlane(sc.piv[16 * k + jj]);
-    const cpx<R> m = mbj[lane];
-    const bool isp = lane == p;
+    const int pl = RL == 1 ? p : p & 63, pq = RL == 1 ? 0 : p >> 6;
+    cpx<R> m[RL];
+#pragma unroll
+    for (int q = 0; q < RL; ++q) m[q] = mbj[lane + 64 * q];
     cpx<R> prow[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) prow[c] = mk<R>(readlane_d(pr[c].re, p), readlane_d(pr[c].im, p));
-#pragma unroll
     for (int c = 0; c < 4; ++c) {
-      if (c == cj && w == owner) {
-        pr[c] = mk<R>(-m.re, -m.im);
-      } else {
-        const cpx<R> base = isp ? mk<R>(0, 0) : pr[c];
-        pr[c] = cfms(base, m, prow[c]);
-      }
-    }
-    if (isp) used = true;
-  }
-  if (ok)
+      prow[c] = mk<R>(0, 0);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) mat[lane * S + c0 + c] = pr[c];
+      for (int q = 0; q < RL; ++q)
+        if (q == pq) prow[c] = mk<R>(readlane_d(pr[q][c].re, pl), readlane_d(pr[q][c].im, pl));
+    }
+#pragma unroll
+    for (int q = 0; q < RL; ++q) {
+      const bool isp = (q == pq) && (lane == pl);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        if (c == cj && w == owner) {
+          pr[q][c] = mk<R>(-m[q].re, -m[q].im);
+        } else {
+          const cpx<R> base = isp ? mk<R>(0, 0) : pr[q][c];
+          pr[q][c] = cfms(base, m[q], prow[c]);
+        }
+      }
+      if (isp) used[q] = true;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < RL; ++q) {
+    const int r = lane + 64 * q;
+    if (r < M)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) mat[r * S + c0 + c] = pr[q][c];
+  }
 }
 
 // Panel update x' = (x with the panel's pivot rows zeroed) + G y for every
 // 16x16 tile outside panel k (G: the panel columns, y: the compacted pivot
 // rows in Y, row stride M - 16).  The tiles are dealt round-robin to the
-// waves; each wave runs its (at most TPW) tiles through one interleaved
-// MFMA loop, so that 2 TPW accumulator chains are in flight.  A wave's
-// surplus slots recompute a valid tile and do not store it.
+// waves; each wave runs its tiles in groups of at most four through one
+// interleaved MFMA loop, so that up to eight accumulator chains are in
+// flight.  A group's surplus slots recompute a valid tile and do not store.
 template <typename R, int M>
 __device__ __forceinline__ void gj_update(cpx<R>* mat, int S, int k, const cpx<R>* Y, const BGJ<R, M>& sc) {
   constexpr int MT = M / 16, NTILE = MT * (MT - 1), TPW = (NTILE + NWAVE - 1) / NWAVE, WY = M - 16;
+  constexpr int GRP = TPW < 4 ? TPW : 4;
   if constexpr (NTILE > 0) {
     const int w = threadIdx.x >> 6, lane = lane_id(), g = lane >> 4, c = lane & 15;
-    int arow[TPW], bcol[TPW], xcol[TPW];
-    bool keep[TPW];
-    ctile<R> acc[TPW];
+#pragma unroll 1
+    for (int q0 = 0; q0 < TPW; q0 += GRP) {
+      int arow[GRP], bcol[GRP], xcol[GRP];
+      bool keep[GRP];
+      ctile<R> acc[GRP];
 #pragma unroll
-    for (int q = 0; q < TPW; ++q) {
-      int tile = w + NWAVE * q;
-      keep[q] = tile < NTILE;
-      tile = keep[q] ? tile : 0;
-      const int ti = tile % MT, tcx = tile / MT, tc = tcx + (tcx >= k ? 1 : 0);
-      arow[q] = 16 * ti;
-      bcol[q] = 16 * tcx + c;
-      xcol[q] = 16 * tc + c;
+      for (int q = 0; q < GRP; ++q) {
+        int tile = w + NWAVE * (q0 + q);
+        keep[q] = (q0 + q < TPW) && tile < NTILE;
+        tile = keep[q] ? tile : 0;
+        const int ti = tile % MT, tcx = tile / MT, tc = tcx + (tcx >= k ? 1 : 0);
+        arow[q] = 16 * ti;
+        bcol[q] = 16 * tcx + c;
+        xcol[q] = 16 * tc + c;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = arow[q] + mf<R>::row(r, g);
-        const cpx<R> v = sc.ppanel[row] == k ? mk<R>(0, 0) : mat[row * S + xcol[q]];
-        acc[q].re[r] = v.re;
-        acc[q].im[r] = v.im;
+        for (int r = 0; r < 4; ++r) {
+          const int row = arow[q] + mf<R>::row(r, g);
+          const cpx<R> v = sc.ppanel[row] == k ? mk<R>(0, 0) : mat[row * S + xcol[q]];
+          acc[q].re[r] = v.re;
+          acc[q].im[r] = v.im;
+        }
       }
+#pragma unroll
+      for (int sl = 0; sl < 4; ++sl) {
+        const int kk = 4 * g + sl;
+        cpx<R> av[GRP], bv[GRP];
+#pragma unroll
+        for (int q = 0; q < GRP; ++q) {
+          av[q] = mat[(arow[q] + c) * S + 16 * k + kk];
+          bv[q] = Y[kk * WY + bcol[q]];
+        }
+#pragma unroll
+        for (int q = 0; q < GRP; ++q) {
+          acc[q].re = mf<R>::op(av[q].re, bv[q].re, acc[q].re);
+          acc[q].im = mf<R>::op(av[q].re, bv[q].im, acc[q].im);
+        }
+#pragma unroll
+        for (int q = 0; q < GRP; ++q) {
+          acc[q].re = mf<R>::op(-av[q].im, bv[q].im, acc[q].re);
+          acc[q].im = mf<R>::op(av[q].im, bv[q].re, acc[q].im);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < GRP; ++q)
+        if (keep[q])
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            mat[(arow[q] + mf<R>::row(r, g)) * S + xcol[q]] = mk<R>(acc[q].re[r], acc[q].im[r]);
     }
-#pragma unroll
-    for (int sl = 0; sl < 4; ++sl) {
-      const int kk = 4 * g + sl;
-      cpx<R> av[TPW], bv[TPW];
-#pragma unroll
-      for (int q = 0; q < TPW; ++q) {
-        av[q] = mat[(arow[q] + c) * S + 16 * k + kk];
-        bv[q] = Y[kk * WY + bcol[q]];
-      }
-#pragma unroll
-      for (int q = 0; q < TPW; ++q) {
-        acc[q].re = mf<R>::op(av[q].re, bv[q].re, acc[q].re);
-        acc[q].im = mf<R>::op(av[q].re, bv[q].im, acc[q].im);
-      }
-#pragma unroll
-      for (int q = 0; q < TPW; ++q) {
-        acc[q].re = mf<R>::op(-av[q].im, bv[q].im, acc[q].re);
-        acc[q].im = mf<R>::op(av[q].im, bv[q].re, acc[q].im);
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < TPW; ++q)
-      if (keep[q])
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          mat[(arow[q] + mf<R>::row(r, g)) * S + xcol[q]] = mk<R>(acc[q].re[r], acc[q].im[r]);
   }
 }
 
-// In-place Gauss-Jordan on the M x M LDS matrix (row stride S); Y is LDS
-// scratch of gj_scratch<M>() elements.  The result is the inverse up to the pivot order:
+// In-place Gauss-Jordan on the M x M matrix (row stride S; in LDS, or for
+// M > 64 in the workgroup's global workspace); Y is LDS scratch of
+// gj_scratch<M>() elements.  The result is the inverse up to the pivot order:
 // A^-1[j][c] = mat[piv[j]][pinv[c]], so A^-1 B = P (mat (Q B)) with
 // (Q B)[k] = B[piv[k]] and row r of the product landing in row pinv[r].
 // Ends with a barrier.
@@ -280,12 +320,13 @@ __device__ __forceinline__ void gamma_ldl(const double2* sig, double2* W, double
 // inverse alone loses up to two digits when D0 is ill-conditioned, one
 // refinement step restores the accuracy of an LU solve.
 template <int M>
-__global__ __launch_bounds__(NT, 2) void k_decimate(Prob P, const double* E, int nE, double eta, int sides,
-                                                    double tol, int maxit, double heavy_tol, double2* scratch,
-                                                    double2* sig, double2* wf, double* sgn, int* iters,
-                                                    int* nheavy) {
+__global__ __launch_bounds__(NT, M > 64 ? 1 : 2) void k_decimate(Prob P, const double* E, int nE, double eta,
+                                                                 int sides, double tol, int maxit, double heavy_tol,
+                                                                 double2* scratch, double2* sig, double2* wf,
+                                                                 double* sgn, int* iters, int* nheavy) {
   constexpr int MT = M / 16, MM = M * M, S = M + 1, LB = 2 * M;
-  __shared__ cpx<double> mat[M * S];
+  constexpr bool BIG = M > 64;                    // working matrix in the global workspace
+  __shared__ cpx<double> mat_l[BIG ? 1 : M * S];
   __shared__ union {
     cpx<double> y[gj_scratch<M>()];
     LDLScratch<M> ldl;
@@ -293,7 +334,10 @@ __global__ __launch_bounds__(NT, 2) void k_decimate(Prob P, const double* E, int
   __shared__ BGJ<double, M> sc;
   __shared__ double red[2][NWAVE];
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
-  double2* ws = scratch + (size_t)blockIdx.x * 13 * MM;
+  double2* ws = scratch + (size_t)blockIdx.x * dec_ws_elems(M);
+  cpx<double>* mat;
+  if constexpr (BIG) mat = (cpx<double>*)(ws + 13 * MM);
+  else mat = mat_l;
   double2* eps = ws;
   double2* esL = ws + MM;
   double2* esR = ws + 2 * MM;
@@ -604,16 +648,28 @@ __device__ __forceinline__ double refine(const Prob& P, const SweepArgs& a, int 
 // With a.elist (FP64 sweep only) the launch re-solves the listed energies,
 // keeping the refinement diagnostics in info and marking the fallback.
 template <typename R, int M, bool MIX>
-__global__ __launch_bounds__(NT, 2) void k_sweep(Prob P, SweepArgs a) {
+__global__ __launch_bounds__(NT, M > 64 ? 1 : 2) void k_sweep(Prob P, SweepArgs a) {
   typedef typename vec2t<R>::type V2;
   constexpr int MT = M / 16, MM = M * M, S = M + 1, LD = 2 * M;
-  __shared__ cpx<R> mat[M * S];
+  // M > 64: the working matrix and the staged coupling block live at the
+  // end of the workgroup's global workspace (they do not fit in LDS)
+  constexpr bool BIG = M > 64;
+  __shared__ cpx<R> mat_l[BIG ? 1 : M * S];
   __shared__ cpx<R> Ysc[gj_scratch<M>()];
   __shared__ BGJ<R, M> sc;
   __shared__ double tred[NWAVE];
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   const int N = P.N;
   char* wsb = a.ws + (size_t)blockIdx.x * a.ws_bytes;
+  cpx<R>* mat;
+  cpx<R>* Lst;                                  // -L_i, staged once per slab
+  if constexpr (BIG) {
+    mat = (cpx<R>*)(wsb + a.ws_bytes - 2 * (size_t)M * S * sizeof(cpx<R>));
+    Lst = mat + M * S;
+  } else {
+    mat = mat_l;
+    Lst = mat_l;
+  }
   V2* XZ = (V2*)wsb;
   V2* PSI = XZ + (size_t)N * M * LD;
   float2* DI = nullptr;
@@ -655,6 +711,7 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(Prob P, SweepArgs a) {
       // Stage A = -L_i = -(A_{i,i-1}) once per slab in the LDS buffer (free
       // until the new Schur complement is written): every wave reads the
       // whole of it, which from L1/L2 would exceed the cache bandwidth.
+      // (M > 64: a separate global buffer, in the layout the products read.)
       if (i > 0) {
         const double vu = P.vu(i - 1);
         const cpx<double> zu = mk<double>(z.re - vu, z.im);
@@ -665,14 +722,14 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(Prob P, SweepArgs a) {
           const cpx<double> sv = ldd(Su + idx), hv = ldd(Hu + idx);
           const double re = zu.re * sv.re + zu.im * sv.im - hv.re;
           const double im = zu.im * sv.re - zu.re * sv.im + hv.im;
-          mat[r * S + k] = mk<R>((R)-re, (R)-im);
+          Lst[r * S + k] = mk<R>((R)-re, (R)-im);
         }
         __syncthreads();
       }
       // Column tiles of [Dt | y]: the y tiles go straight to the workspace,
       // the (at most DT) Dt tile columns of this wave stay in registers until
       // every wave has finished reading L_i from the LDS buffer.
-      constexpr int DT = (MT + NWAVE - 1) / NWAVE;
+      constexpr int DT = BIG ? 1 : (MT + NWAVE - 1) / NWAVE;
       ctile<R> dacc[DT][MT];
 #pragma unroll 1
       for (int pass = 0; pass < 2; ++pass) {
@@ -711,8 +768,13 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(Prob P, SweepArgs a) {
 #pragma unroll
             for (int ti = 0; ti < MT; ++ti) tzero(acc[ti]);
           }
-          if (i > 0) cgemm_col<R, MT, MT>(acc, ALds<R>{mat, S}, BGlob<R>{Xi - (size_t)M * LD, LD}, tj);
-          if (is_d) {
+          if (i > 0) cgemm_col<R, MT, MT>(acc, ALds<R>{Lst, S}, BGlob<R>{Xi - (size_t)M * LD, LD}, tj);
+          if (is_d && BIG) {
+            // the Schur complement goes straight to its own buffer
+            tiles_foreach<R, MT>(acc, tj, [&](int row, int col, int ti, int r) {
+              mat[row * S + col] = mk<R>(acc[ti].re[r], acc[ti].im[r]);
+            });
+          } else if (is_d) {
 #pragma unroll
             for (int q2 = 0; q2 < DT; ++q2)
               if (q2 == nd)
@@ -727,7 +789,7 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(Prob P, SweepArgs a) {
         }
       }
       __syncthreads();
-      {
+      if constexpr (!BIG) {
         int nd = 0;
 #pragma unroll 1
         for (int tj = w; tj < MT; tj += NWAVE) {
@@ -800,14 +862,17 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(Prob P, SweepArgs a) {
     for (int i = N - 1; i >= 0; --i) {
       const V2* Xi = XZ + (size_t)i * M * LD;
       if (i < N - 1) {
-        // stage -X_i in LDS once per slab (every wave reads all of it)
-        __syncthreads();
-        for (int idx = t; idx < MM; idx += NT) {
-          const int r = idx / M, c = idx - r * M;
-          const cpx<R> v = ld2<R>(Xi + (unsigned)(r * LD + c));
-          mat[r * S + c] = mk<R>(-v.re, -v.im);
+        // stage -X_i in LDS once per slab (every wave reads all of it);
+        // M > 64 reads X_i where it is
+        if constexpr (!BIG) {
+          __syncthreads();
+          for (int idx = t; idx < MM; idx += NT) {
+            const int r = idx / M, c = idx - r * M;
+            const cpx<R> v = ld2<R>(Xi + (unsigned)(r * LD + c));
+            mat[r * S + c] = mk<R>(-v.re, -v.im);
+          }
+          __syncthreads();
         }
-        __syncthreads();
       }
       double pL = 0.0, pR = 0.0;
 #pragma unroll 1
@@ -823,7 +888,10 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(Prob P, SweepArgs a) {
 #pragma unroll
           for (int ti = 0; ti < MT; ++ti) tzero(acc[ti]);
         }
-        if (i < N - 1) cgemm_col<R, MT, MT>(acc, ALds<R>{mat, S}, BGlob<R>{PSI, LD}, tj);
+        if (i < N - 1) {
+          if constexpr (BIG) cgemm_col<R, MT, MT>(acc, AGlob<R>{Xi, LD, (R)-1}, BGlob<R>{PSI, LD}, tj);
+          else cgemm_col<R, MT, MT>(acc, ALds<R>{mat, S}, BGlob<R>{PSI, LD}, tj);
+        }
         const int cl = 16 * tj + (lane & 15);
         const double sg = cl < M ? sgR[cl] : sgL[cl - M];
         bool heavy = false, keep = false;
@@ -980,6 +1048,8 @@ hipError_t run_decimate(int M, const Prob& P, const double* E, int nE, double et
     case 32: QTX_DEC(32);
     case 48: QTX_DEC(48);
     case 64: QTX_DEC(64);
+    case 96: QTX_DEC(96);
+    case 128: QTX_DEC(128);
     default: return hipErrorInvalidValue;
   }
 #undef QTX_DEC
@@ -993,6 +1063,8 @@ hipError_t run_sweep(int M, bool mixed, const Prob& P, const SweepArgs& a, int g
     case 32: QTX_SWEEP(32);
     case 48: QTX_SWEEP(48);
     case 64: QTX_SWEEP(64);
+    case 96: QTX_SWEEP(96);
+    case 128: QTX_SWEEP(128);
     default: return hipErrorInvalidValue;
   }
 #undef QTX_SWEEP

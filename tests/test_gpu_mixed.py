@@ -15,6 +15,8 @@ import oracle
 from paper_1903_00548_amd import _lib
 from paper_1903_00548_amd import workloads as W
 
+import small_cases
+
 pytestmark = pytest.mark.gpu
 
 TOL_T = 1e-8
@@ -47,24 +49,14 @@ def test_mixed_cfg0(gpu_lib):
     assert np.all(info["resid"] <= 1e-12) or np.any(info["fell_back_fp64"] == 1)
 
 
-@pytest.mark.parametrize("seed,N,m,uniform,same,mode", [
-    (1, 5, 4, True, True, W.POT_LINEAR_FE),
-    (2, 9, 6, False, False, W.POT_LINEAR_FE),
-    (3, 1, 16, False, False, W.POT_DIAG),
-    (4, 2, 16, True, False, W.POT_LINEAR_FE),
-    (5, 33, 20, False, True, W.POT_DIAG),
-    (6, 17, 48, True, True, W.POT_LINEAR_FE),
-    (7, 12, 64, False, False, W.POT_LINEAR_FE),
-    (8, 3, 1, True, True, W.POT_DIAG),
-])
-def test_mixed_small_devices(gpu_lib, seed, N, m, uniform, same, mode):
-    dev = W.small_random_device(seed, N, m, uniform=uniform, same_leads=same, pot_mode=mode,
-                                VL=0.04 * (seed % 3), VR=-0.03 * (seed % 2))
-    E = np.linspace(-2.0, 2.0, 23)
+@pytest.mark.parametrize("case", small_cases.CASES, ids=lambda c: f"seed{c[0]}-N{c[1]}-m{c[2]}")
+def test_mixed_small_devices(gpu_lib, case):
+    dev = small_cases.device(*case)
+    E = small_cases.energies()
     ctx = _lib.context_for(dev, 0)
-    T, L, info, st = ctx.solve(E, 1e-6, _lib.MIXED)
-    Tref, Lref = oracle.solve_device(dev, E, 1e-6)
-    _check(T, L, Tref, Lref, f"seed{seed} mixed")
+    T, L, info, st = ctx.solve(E, small_cases.ETA, _lib.MIXED)
+    Tref, Lref = small_cases.reference(*case)
+    _check(T, L, Tref, Lref, label=f"seed{case[0]} mixed")
 
 
 def test_mixed_cfg1_full_size(gpu_lib):
