@@ -170,7 +170,10 @@ qtx_status qtx_self_energy(qtx_ctx* ctx, const double* E, int nE, double eta,
  *                           of 16 columns, at least one tile per contact);
  *                           0 refines every column;
  *   "workgroups_per_cu"     1 or 2        2      resident energies per CU;
- *   "energies_per_launch"   [1, 2^20]     4096   energies per launch chunk.
+ *   "energies_per_launch"   [1, 2^20]     4096   energies per launch chunk;
+ *   "use_graph"             0 or 1        1      qtx_solve_batch captures its
+ *                           launch sequence in a HIP graph and replays it
+ *                           while the batch shape is unchanged.
  * Integer options take an integral value.  QTX_EINVAL for an unknown name
  * or a value out of range (the setting is then unchanged). */
 qtx_status qtx_set_option(qtx_ctx* ctx, const char* name, double value);
@@ -181,10 +184,15 @@ qtx_status qtx_set_option(qtx_ctx* ctx, const char* name, double value);
  * carries its own leads, device blocks and potential (same setters). */
 qtx_status qtx_problem_create(qtx_ctx* parent, qtx_ctx** problem);
 
-/* Solve nprob problems, each on its own energy grid E[p][0..nE[p]-1], in
- * one batched launch sequence of persistent kernels (devices of different
- * N and m share the launch).  T[p] (nE[p]) and ldos[p] (nE[p]*2*N_p, or
- * NULL) are host buffers.  Problems must be fully set. */
+/* Solve nprob problems, each on its own energy grid E[p][0..nE[p]-1], as
+ * one batch: the (problem, energy) items of all problems with the same
+ * padded block size share one decimation and one sweep launch (devices of
+ * different N in the same launch, longest first), and the whole launch
+ * sequence is replayed from a HIP graph while the batch shape (problems,
+ * their N and m, the nE[p], eta, precision, options) is unchanged.
+ * T[p] (nE[p]) and ldos[p] (nE[p]*2*N_p, or NULL) are host buffers;
+ * results are the same as qtx_solve on each problem alone.  Problems must
+ * be fully set and live on ctx's device.  Synchronous. */
 qtx_status qtx_solve_batch(qtx_ctx* ctx, int nprob, qtx_ctx* const* probs,
                            const double* const* E, const int* nE, double eta,
                            qtx_precision prec, double* const* T, double* const* ldos);

@@ -208,7 +208,7 @@ def solve_batch(ctx: Context, problems, energies, eta, precision=FP64, want_ldos
     n = len(problems)
     Es = [np.ascontiguousarray(e, dtype=np.float64) for e in energies]
     Ts = [np.empty(len(e)) for e in Es]
-    Ls = [np.empty((len(e), 2, p.N)) for e, p in zip(Es, problems)] if want_ldos else None
+    Ls = [np.empty((len(e), 2, p.N or 0)) for e, p in zip(Es, problems)] if want_ldos else None
     hp = (c_void_p * n)(*[p.h for p in problems])
     Ep = (c_void_p * n)(*[_ptr(e) for e in Es])
     nEp = (c_int * n)(*[len(e) for e in Es])

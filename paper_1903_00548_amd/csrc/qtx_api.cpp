@@ -10,6 +10,7 @@
 #include <complex>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -66,6 +67,14 @@ struct qtx_ctx {
   DevBuf wE, wT, wldos, winfo;
   DevBuf sig, wf, sgn, iters, nheavy, dscr, sws, part;
   DevBuf redo, elist, ecount;                  // mixed: energies re-solved in FP64
+
+  // batched solves: flattened items of all problems, and the captured
+  // launch sequence of the last batch shape
+  DevBuf bprobs, bitem_prob, bitem_ldos, bjob_item, bjob_side, bE, bT, bldos, binfo;
+  std::vector<long long> batch_sig;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  bool use_graph = true;
 
   // kernel timing: event pairs around decimation / sweep launches
   bool timing = false;
@@ -190,7 +199,7 @@ qtx_status stage_decimate(qtx_ctx* c, const double* E_dev, int nE, double eta) {
   QTX_HIP(c, c->dscr.ensure((size_t)grid * qtx::dec_ws_elems(M) * sizeof(double2)));
   qtx::Prob P = make_prob(c);
   QTX_HIP(c, record(c, c->ev_dec, c->n_dec));
-  QTX_HIP(c, qtx::run_decimate(M, P, E_dev, nE, eta, sides, c->dec_tol, c->dec_maxit, c->heavy_tol,
+  QTX_HIP(c, qtx::run_decimate(M, P, qtx::BatchDesc{}, E_dev, nE, eta, sides, c->dec_tol, c->dec_maxit, c->heavy_tol,
                                c->dscr.as<double2>(), grid, c->sig.as<double2>(), c->wf.as<double2>(),
                                c->sgn.as<double>(), c->iters.as<int>(), c->nheavy.as<int>(), c->stream));
   QTX_HIP(c, record(c, c->ev_dec, c->n_dec));
@@ -233,6 +242,7 @@ qtx_status solve_device_core(qtx_ctx* c, const double* E_dev, int nE, double eta
     a.ws = c->sws.as<char>();
     a.ws_bytes = wsb;
     a.part = c->part.as<double>();
+    a.nmax = N;
     a.T = T_dev + e0;
     a.ldos = ldos_dev ? ldos_dev + (size_t)e0 * 2 * N : nullptr;
     a.info = info_dev ? info_dev + e0 : nullptr;
@@ -242,7 +252,7 @@ qtx_status solve_device_core(qtx_ctx* c, const double* E_dev, int nE, double eta
     a.rtol = c->refine_tol;
     a.maxstep = c->refine_max;
     QTX_HIP(c, record(c, c->ev_sw, c->n_sw));
-    QTX_HIP(c, qtx::run_sweep(M, mixed, P, a, grid, c->stream));
+    QTX_HIP(c, qtx::run_sweep(M, mixed, P, a, qtx::BatchDesc{}, grid, c->stream));
     if (mixed) {
       // energies whose refinement did not converge: FP64 sweep on the list
       QTX_HIP(c, qtx::run_compact(c->redo.as<int>(), ne, c->elist.as<int>(), c->ecount.as<int>(), c->stream));
@@ -250,7 +260,7 @@ qtx_status solve_device_core(qtx_ctx* c, const double* E_dev, int nE, double eta
       f.elist = c->elist.as<int>();
       f.ecount = c->ecount.as<int>();
       f.redo = nullptr;
-      QTX_HIP(c, qtx::run_sweep(M, false, P, f, grid, c->stream));
+      QTX_HIP(c, qtx::run_sweep(M, false, P, f, qtx::BatchDesc{}, grid, c->stream));
     }
     QTX_HIP(c, record(c, c->ev_sw, c->n_sw));
   }
@@ -289,9 +299,12 @@ void qtx_destroy(qtx_ctx* c) {
   if (c->stream) hipStreamSynchronize(c->stream);
   for (hipEvent_t e : c->ev_dec) hipEventDestroy(e);
   for (hipEvent_t e : c->ev_sw) hipEventDestroy(e);
+  if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) hipGraphDestroy(c->graph);
   DevBuf* bufs[] = {&c->dlead[0], &c->dlead[1], &c->ddev, &c->dV, &c->wE, &c->wT, &c->wldos, &c->winfo,
                     &c->sig, &c->wf, &c->sgn, &c->iters, &c->nheavy, &c->dscr, &c->sws, &c->part,
-                    &c->redo, &c->elist, &c->ecount};
+                    &c->redo, &c->elist, &c->ecount, &c->bprobs, &c->bitem_prob, &c->bitem_ldos,
+                    &c->bjob_item, &c->bjob_side, &c->bE, &c->bT, &c->bldos, &c->binfo};
   for (DevBuf* b : bufs) b->release();
   if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
   delete c;
@@ -545,6 +558,9 @@ qtx_status qtx_set_option(qtx_ctx* c, const char* name, double value) {
   } else if (n == "workgroups_per_cu") {
     if (!integral || value < 1 || value > 2) return fail(c, QTX_EINVAL, "workgroups_per_cu must be 1 or 2");
     c->wg_per_cu = (int)value;
+  } else if (n == "use_graph") {
+    if (!(value == 0.0 || value == 1.0)) return fail(c, QTX_EINVAL, "use_graph must be 0 or 1");
+    c->use_graph = value != 0.0;
   } else if (n == "energies_per_launch") {
     if (!integral || value < 1 || value > (1 << 20)) return fail(c, QTX_EINVAL, "energies_per_launch must be in [1, 2^20]");
     c->chunk = (int)value;
@@ -567,6 +583,7 @@ qtx_status qtx_problem_create(qtx_ctx* parent, qtx_ctx** problem) {
   c->refine_tol = parent->refine_tol;
   c->refine_max = parent->refine_max;
   c->heavy_tol = parent->heavy_tol;
+  c->use_graph = parent->use_graph;
   c->stream = parent->stream;
   c->own_stream = false;
   c->parent = parent;
@@ -574,20 +591,269 @@ qtx_status qtx_problem_create(qtx_ctx* parent, qtx_ctx** problem) {
   return QTX_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// One launch group of a batch: a contiguous range of items (all of one
+// padded block size) and its decimation jobs.
+struct BatchChunk {
+  int M, nmax, item0, nitems, job0, njobs;
+};
+
+void drop_graph(qtx_ctx* c) {
+  if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) hipGraphDestroy(c->graph);
+  c->graph_exec = nullptr;
+  c->graph = nullptr;
+  c->batch_sig.clear();
+}
+
+// The launch sequence of a batch (decimation, sweep, and for the mixed
+// path the compaction and FP64 re-solve of unconverged items), chunk by
+// chunk on the context stream.  Buffers must already have their sizes.
+qtx_status enqueue_batch(qtx_ctx* c, const std::vector<BatchChunk>& chunks, double eta, bool mixed) {
+  for (const BatchChunk& k : chunks) {
+    const int M = k.M;
+    const bool big = M > 64;
+    const int wg = big ? 1 : c->wg_per_cu;
+    qtx::BatchDesc b;
+    b.probs = c->bprobs.as<qtx::Prob>();
+    b.item_prob = c->bitem_prob.as<int>() + k.item0;
+    b.item_ldos = c->bitem_ldos.as<size_t>() + k.item0;
+    b.job_item = c->bjob_item.as<int>() + k.job0;
+    b.job_side = c->bjob_side.as<int>() + k.job0;
+    b.njobs = k.njobs;
+    qtx::Prob P0{};
+    P0.N = k.nmax;
+    P0.M = M;
+    const int gdec = std::max(1, std::min(k.njobs, c->num_cu * wg));
+    QTX_HIP(c, qtx::run_decimate(M, P0, b, c->bE.as<double>() + k.item0, k.nitems, eta, 2, c->dec_tol, c->dec_maxit,
+                                 c->heavy_tol, c->dscr.as<double2>(), gdec, c->sig.as<double2>(), c->wf.as<double2>(),
+                                 c->sgn.as<double>(), c->iters.as<int>(), c->nheavy.as<int>(), c->stream));
+    const int grid = std::max(1, std::min(k.nitems, c->num_cu * wg));
+    qtx::SweepArgs a;
+    a.E = c->bE.as<double>() + k.item0;
+    a.nE = k.nitems;
+    a.eta = eta;
+    a.sig = c->sig.as<double2>();
+    a.wf = c->wf.as<double2>();
+    a.sgn = c->sgn.as<double>();
+    a.iters = c->iters.as<int>();
+    a.nheavy = c->nheavy.as<int>();
+    a.ws = c->sws.as<char>();
+    a.ws_bytes = qtx::sweep_ws_bytes(k.nmax, M, mixed);
+    a.part = c->part.as<double>();
+    a.nmax = k.nmax;
+    a.T = c->bT.as<double>() + k.item0;
+    a.ldos = c->bldos.as<double>();
+    a.info = c->binfo.as<qtx_info>() + k.item0;
+    a.elist = nullptr;
+    a.ecount = nullptr;
+    a.redo = mixed ? c->redo.as<int>() : nullptr;
+    a.rtol = c->refine_tol;
+    a.maxstep = c->refine_max;
+    QTX_HIP(c, qtx::run_sweep(M, mixed, P0, a, b, grid, c->stream));
+    if (mixed) {
+      QTX_HIP(c, qtx::run_compact(c->redo.as<int>(), k.nitems, c->elist.as<int>(), c->ecount.as<int>(), c->stream));
+      qtx::SweepArgs f = a;
+      f.elist = c->elist.as<int>();
+      f.ecount = c->ecount.as<int>();
+      f.redo = nullptr;
+      QTX_HIP(c, qtx::run_sweep(M, false, P0, f, b, grid, c->stream));
+    }
+  }
+  return QTX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 qtx_status qtx_solve_batch(qtx_ctx* c, int nprob, qtx_ctx* const* probs, const double* const* E, const int* nE,
                            double eta, qtx_precision prec, double* const* T, double* const* ldos) {
   if (!c) return QTX_EINVAL;
   if (nprob < 0 || (nprob > 0 && (!probs || !E || !nE || !T))) return fail(c, QTX_EINVAL, "bad batch arguments");
-  qtx_status worst = QTX_OK;
+  if (prec != QTX_FP64 && prec != QTX_MIXED) return fail(c, QTX_EINVAL, "precision must be QTX_FP64 or QTX_MIXED");
+  if (!(eta >= 0.0)) return fail(c, QTX_EINVAL, "eta must be >= 0");
   for (int p = 0; p < nprob; ++p) {
-    if (!probs[p]) return fail(c, QTX_EINVAL, "NULL problem in batch");
     qtx_ctx* q = probs[p];
-    q->stream = c->stream;
-    qtx_status s = qtx_solve(q, E[p], nE[p], eta, prec, T[p], ldos ? ldos[p] : nullptr, nullptr);
-    if (s == QTX_ENOTCONV) worst = QTX_ENOTCONV;
-    else if (s != QTX_OK) return fail(c, s, std::string("problem ") + std::to_string(p) + ": " + q->err);
+    if (!q) return fail(c, QTX_EINVAL, "NULL problem in batch");
+    if (q->device != c->device) return fail(c, QTX_EINVAL, "every problem must live on the batch context's device");
+    qtx_status s = check_ready(q);
+    if (s != QTX_OK) return fail(c, s, std::string("problem ") + std::to_string(p) + ": " + q->err);
+    if (nE[p] < 0) return fail(c, QTX_EINVAL, "nE must be >= 0");
+    if (nE[p] > 0 && (!E[p] || !T[p])) return fail(c, QTX_EINVAL, "E[p] and T[p] must not be NULL");
+    for (int e = 0; e < nE[p]; ++e)
+      if (!std::isfinite(E[p][e])) return fail(c, QTX_EINVAL, "energies must be finite");
   }
-  return worst;
+  hipSetDevice(c->device);
+  const bool mixed = (prec == QTX_MIXED);
+
+  // problems grouped by padded block size, each group by decreasing slab
+  // count, so that the grid-stride order hands out the longest items first
+  std::vector<int> order(nprob);
+  for (int p = 0; p < nprob; ++p) order[p] = p;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    if (probs[x]->M != probs[y]->M) return probs[x]->M < probs[y]->M;
+    return probs[x]->N > probs[y]->N;
+  });
+  std::vector<qtx::Prob> hprob(nprob);
+  for (int p = 0; p < nprob; ++p) hprob[p] = make_prob(probs[p]);
+  std::vector<int> item_prob, item_e, job_item, job_side;
+  std::vector<double> hE;
+  std::vector<size_t> item_ldos;
+  std::vector<BatchChunk> chunks;
+  size_t ldos_total = 0;
+  for (size_t oi = 0; oi < order.size();) {
+    const int M = probs[order[oi]]->M;
+    size_t oj = oi;
+    while (oj < order.size() && probs[order[oj]]->M == M) ++oj;
+    BatchChunk k{M, 0, (int)item_prob.size(), 0, (int)job_item.size(), 0};
+    auto close_chunk = [&]() {
+      if (k.nitems > 0) chunks.push_back(k);
+      k = BatchChunk{M, 0, (int)item_prob.size(), 0, (int)job_item.size(), 0};
+    };
+    for (size_t o = oi; o < oj; ++o) {
+      const int p = order[o];
+      const qtx_ctx* q = probs[p];
+      const bool same = leads_identical(q);
+      for (int e = 0; e < nE[p]; ++e) {
+        if (k.nitems == c->chunk) close_chunk();
+        item_prob.push_back(p);
+        item_e.push_back(e);
+        hE.push_back(E[p][e]);
+        item_ldos.push_back(ldos_total);
+        ldos_total += 2 * (size_t)q->N;
+        const int local = k.nitems++;
+        k.nmax = std::max(k.nmax, q->N);
+        if (same) {
+          job_item.push_back(local);
+          job_side.push_back(-1);
+          k.njobs += 1;
+        } else {
+          job_item.push_back(local);
+          job_side.push_back(0);
+          job_item.push_back(local);
+          job_side.push_back(1);
+          k.njobs += 2;
+        }
+      }
+    }
+    close_chunk();
+    oi = oj;
+  }
+  const int nitems = (int)item_prob.size();
+  if (nitems == 0) return QTX_OK;
+
+  // buffer sizes (all allocations before any capture)
+  size_t sig_b = 0, dscr_b = 0, sws_b = 0, part_b = 0, per_b = 0;
+  for (const BatchChunk& k : chunks) {
+    const size_t MM = (size_t)k.M * k.M;
+    const int wg = k.M > 64 ? 1 : c->wg_per_cu;
+    const size_t gdec = std::max(1, std::min(k.njobs, c->num_cu * wg));
+    const size_t grid = std::max(1, std::min(k.nitems, c->num_cu * wg));
+    sig_b = std::max(sig_b, (size_t)k.nitems * 2 * MM * sizeof(double2));
+    per_b = std::max(per_b, (size_t)k.nitems);
+    dscr_b = std::max(dscr_b, gdec * qtx::dec_ws_elems(k.M) * sizeof(double2));
+    sws_b = std::max(sws_b, grid * qtx::sweep_ws_bytes(k.nmax, k.M, mixed));
+    part_b = std::max(part_b, grid * 4 * 2 * (size_t)k.nmax * (mixed ? 2 : 1) * sizeof(double));
+  }
+  int maxM = 16;
+  for (const BatchChunk& k : chunks) maxM = std::max(maxM, k.M);
+  QTX_HIP(c, c->sig.ensure(sig_b));
+  QTX_HIP(c, c->wf.ensure(sig_b));
+  QTX_HIP(c, c->sgn.ensure(per_b * 2 * maxM * sizeof(double)));
+  QTX_HIP(c, c->iters.ensure(per_b * 2 * sizeof(int)));
+  QTX_HIP(c, c->nheavy.ensure(per_b * 2 * sizeof(int)));
+  QTX_HIP(c, c->dscr.ensure(dscr_b));
+  QTX_HIP(c, c->sws.ensure(sws_b));
+  QTX_HIP(c, c->part.ensure(part_b));
+  QTX_HIP(c, c->redo.ensure(per_b * sizeof(int)));
+  QTX_HIP(c, c->elist.ensure(per_b * sizeof(int)));
+  QTX_HIP(c, c->ecount.ensure(sizeof(int)));
+  QTX_HIP(c, c->bprobs.ensure(nprob * sizeof(qtx::Prob)));
+  QTX_HIP(c, c->bitem_prob.ensure(nitems * sizeof(int)));
+  QTX_HIP(c, c->bitem_ldos.ensure(nitems * sizeof(size_t)));
+  QTX_HIP(c, c->bjob_item.ensure(job_item.size() * sizeof(int)));
+  QTX_HIP(c, c->bjob_side.ensure(job_side.size() * sizeof(int)));
+  QTX_HIP(c, c->bE.ensure(nitems * sizeof(double)));
+  QTX_HIP(c, c->bT.ensure(nitems * sizeof(double)));
+  QTX_HIP(c, c->bldos.ensure(std::max<size_t>(ldos_total, 1) * sizeof(double)));
+  QTX_HIP(c, c->binfo.ensure(nitems * sizeof(qtx_info)));
+
+  QTX_HIP(c, hipMemcpyAsync(c->bprobs.p, hprob.data(), nprob * sizeof(qtx::Prob), hipMemcpyHostToDevice, c->stream));
+  QTX_HIP(c, hipMemcpyAsync(c->bitem_prob.p, item_prob.data(), nitems * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  QTX_HIP(c, hipMemcpyAsync(c->bitem_ldos.p, item_ldos.data(), nitems * sizeof(size_t), hipMemcpyHostToDevice,
+                            c->stream));
+  QTX_HIP(c, hipMemcpyAsync(c->bjob_item.p, job_item.data(), job_item.size() * sizeof(int), hipMemcpyHostToDevice,
+                            c->stream));
+  QTX_HIP(c, hipMemcpyAsync(c->bjob_side.p, job_side.data(), job_side.size() * sizeof(int), hipMemcpyHostToDevice,
+                            c->stream));
+  QTX_HIP(c, hipMemcpyAsync(c->bE.p, hE.data(), nitems * sizeof(double), hipMemcpyHostToDevice, c->stream));
+
+  // the launch sequence depends on the batch shape (and the buffers, whose
+  // sizes follow from it): replay the captured graph while it is unchanged
+  std::vector<long long> sig;
+  sig.push_back(mixed);
+  sig.push_back(c->wg_per_cu);
+  sig.push_back(c->chunk);
+  sig.push_back(c->refine_max);
+  long long eb;
+  std::memcpy(&eb, &eta, sizeof(eb));
+  sig.push_back(eb);
+  std::memcpy(&eb, &c->refine_tol, sizeof(eb));
+  sig.push_back(eb);
+  std::memcpy(&eb, &c->heavy_tol, sizeof(eb));
+  sig.push_back(eb);
+  std::memcpy(&eb, &c->dec_tol, sizeof(eb));
+  sig.push_back(eb);
+  sig.push_back(c->dec_maxit);
+  for (void* bp : {c->sig.p, c->wf.p, c->sgn.p, c->dscr.p, c->sws.p, c->part.p, c->bprobs.p, c->bE.p, c->bT.p,
+                   c->bldos.p, c->binfo.p})
+    sig.push_back((long long)(uintptr_t)bp);
+  for (const BatchChunk& k : chunks)
+    for (int v : {k.M, k.nmax, k.item0, k.nitems, k.job0, k.njobs}) sig.push_back(v);
+  if (!c->use_graph) {
+    drop_graph(c);
+    qtx_status s = enqueue_batch(c, chunks, eta, mixed);
+    if (s != QTX_OK) return s;
+  } else {
+    if (sig != c->batch_sig || !c->graph_exec) {
+      drop_graph(c);
+      QTX_HIP(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+      qtx_status s = enqueue_batch(c, chunks, eta, mixed);
+      hipGraph_t g = nullptr;
+      hipError_t ce = hipStreamEndCapture(c->stream, &g);
+      if (s != QTX_OK) {
+        if (g) hipGraphDestroy(g);
+        return s;
+      }
+      if (ce != hipSuccess) return hipfail(c, ce, "hipStreamEndCapture");
+      c->graph = g;
+      QTX_HIP(c, hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0));
+      c->batch_sig = sig;
+    }
+    QTX_HIP(c, hipGraphLaunch(c->graph_exec, c->stream));
+  }
+
+  std::vector<double> hT(nitems), hL(ldos ? ldos_total : 0);
+  std::vector<qtx_info> hinfo(nitems);
+  QTX_HIP(c, hipMemcpyAsync(hT.data(), c->bT.p, nitems * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  if (ldos)
+    QTX_HIP(c, hipMemcpyAsync(hL.data(), c->bldos.p, ldos_total * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  QTX_HIP(c, hipMemcpyAsync(hinfo.data(), c->binfo.p, nitems * sizeof(qtx_info), hipMemcpyDeviceToHost, c->stream));
+  QTX_HIP(c, hipStreamSynchronize(c->stream));
+  bool flagged = false;
+  for (int i = 0; i < nitems; ++i) {
+    const int p = item_prob[i], e = item_e[i];
+    T[p][e] = hT[i];
+    if (ldos && ldos[p])
+      std::memcpy(ldos[p] + (size_t)e * 2 * probs[p]->N, hL.data() + item_ldos[i], 2 * probs[p]->N * sizeof(double));
+    flagged |= hinfo[i].flags != 0;
+  }
+  if (flagged) return fail(c, QTX_ENOTCONV, "some energies were flagged");
+  return QTX_OK;
 }
 
 qtx_status qtx_charge(const double* ldos, const double* w, int nE, int N, const double* E, double muL, double muR,

@@ -42,6 +42,22 @@ struct Prob {
   }
 };
 
+// Several problems in one launch: the energies of all problems of one
+// padded block size form a flat list of items (item e: problem
+// item_prob[e], energy E[e]); outputs T[e], info[e], and the densities of
+// item e at ldos + item_ldos[e] (2 N of its problem).  The decimation runs
+// over njobs jobs (item job_item[j], contact job_side[j]: 0 left, 1 right,
+// -1 both when the problem's leads are the same).  probs == nullptr: one
+// problem, passed by value.
+struct BatchDesc {
+  const Prob* probs;
+  const int* item_prob;
+  const size_t* item_ldos;
+  const int* job_item;
+  const int* job_side;
+  int njobs;
+};
+
 // Arguments of one sweep launch.  Energy e uses sig/wf/sgn/iters/nheavy
 // at index e of the decimation outputs and writes T[e], ldos[e] and
 // info[e].  Workgroup b owns bytes [b ws_bytes, (b+1) ws_bytes) of ws and
@@ -57,7 +73,8 @@ struct SweepArgs {
   const int* nheavy;       // refined columns per side (2), mixed sweep only
   char* ws;
   size_t ws_bytes;
-  double* part;
+  double* part;            // per workgroup NWAVE * 2 * nmax doubles (twice that, mixed)
+  int nmax;                // largest slab count of the launch
   double* T;
   double* ldos;            // may be null
   qtx_info* info;          // may be null
@@ -95,13 +112,14 @@ __host__ __device__ constexpr size_t dec_ws_elems(int M) {
 // Padded block size for a physical block size m (1 <= m <= 128).
 inline int padded_block(int m) { return m <= 64 ? ((m + 15) / 16) * 16 : (m <= 96 ? 96 : 128); }
 
-hipError_t run_decimate(int M, const Prob& P, const double* E, int nE, double eta, int sides, double tol,
-                        int maxit, double heavy_tol, double2* scratch, int grid, double2* sig, double2* wf,
-                        double* sgn, int* iters, int* nheavy, hipStream_t st);
+hipError_t run_decimate(int M, const Prob& P, const BatchDesc& b, const double* E, int nE, double eta, int sides,
+                        double tol, int maxit, double heavy_tol, double2* scratch, int grid, double2* sig,
+                        double2* wf, double* sgn, int* iters, int* nheavy, hipStream_t st);
 
 // mixed = false: FP64 sweep (with a.elist: re-solve of the listed energies).
 // mixed = true: FP32 sweep plus refinement of the heavy columns.
-hipError_t run_sweep(int M, bool mixed, const Prob& P, const SweepArgs& a, int grid, hipStream_t st);
+hipError_t run_sweep(int M, bool mixed, const Prob& P, const SweepArgs& a, const BatchDesc& b, int grid,
+                     hipStream_t st);
 
 // elist[0 .. *ecount) = the energies e < nE with redo[e] != 0 (one wave).
 hipError_t run_compact(const int* redo, int nE, int* elist, int* ecount, hipStream_t st);

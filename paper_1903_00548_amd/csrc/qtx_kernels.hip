@@ -309,6 +309,37 @@ __device__ __forceinline__ void gamma_ldl(const double2* sig, double2* W, double
   __syncthreads();
 }
 
+// ------------------------------------------------------------ batch items
+// A problem descriptor read from device memory with every field made
+// wave-uniform, so that the addresses built from it stay scalar.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ double uni(double v) {
+  const long long x = __double_as_longlong(v);
+  const unsigned lo = (unsigned)uni((int)(x & 0xffffffff)), hi = (unsigned)uni((int)(x >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+template <class T> __device__ __forceinline__ T* uni(T* p) {
+  const unsigned long long x = (unsigned long long)p;
+  const unsigned lo = (unsigned)uni((int)(x & 0xffffffffull)), hi = (unsigned)uni((int)(x >> 32));
+  return (T*)(((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ Prob load_prob(const Prob* pp) {
+  Prob P;
+  P.N = uni(pp->N);
+  P.M = uni(pp->M);
+  P.leadL = uni(pp->leadL);
+  P.leadR = uni(pp->leadR);
+  P.VL = uni(pp->VL);
+  P.VR = uni(pp->VR);
+  P.dHd = uni(pp->dHd);
+  P.dHu = uni(pp->dHu);
+  P.dSd = uni(pp->dSd);
+  P.dSu = uni(pp->dSu);
+  P.V = uni(pp->V);
+  P.pot_mode = uni(pp->pot_mode);
+  return P;
+}
+
 // ------------------------------------------------------------- decimation
 // Doubling elimination of the semi-infinite lead: with on-site e and
 // couplings a (slab j -> j+1) and b (j+1 -> j), eliminating every other slab
@@ -320,10 +351,10 @@ __device__ __forceinline__ void gamma_ldl(const double2* sig, double2* W, double
 // inverse alone loses up to two digits when D0 is ill-conditioned, one
 // refinement step restores the accuracy of an LU solve.
 template <int M>
-__global__ __launch_bounds__(NT, M > 64 ? 1 : 2) void k_decimate(Prob P, const double* E, int nE, double eta,
-                                                                 int sides, double tol, int maxit, double heavy_tol,
-                                                                 double2* scratch, double2* sig, double2* wf,
-                                                                 double* sgn, int* iters, int* nheavy) {
+__global__ __launch_bounds__(NT, M > 64 ? 1 : 2) void k_decimate(Prob P0, BatchDesc b, const double* E, int nE,
+                                                                 double eta, int sides, double tol, int maxit,
+                                                                 double heavy_tol, double2* scratch, double2* sig,
+                                                                 double2* wf, double* sgn, int* iters, int* nheavy) {
   constexpr int MT = M / 16, MM = M * M, S = M + 1, LB = 2 * M;
   constexpr bool BIG = M > 64;                    // working matrix in the global workspace
   __shared__ cpx<double> mat_l[BIG ? 1 : M * S];
@@ -344,10 +375,20 @@ __global__ __launch_bounds__(NT, M > 64 ? 1 : 2) void k_decimate(Prob P, const d
   double2* ab[2] = {ws + 3 * MM, ws + 5 * MM};   // [a | b], M x 2M, ping-pong
   double2* X = ws + 7 * MM;                       // [g a | g b]
   double2* Rr = ws + 9 * MM;                      // residual
-  const int njobs = nE * sides;
+  const int njobs = b.probs ? b.njobs : nE * sides;
   for (int job = blockIdx.x; job < njobs; job += gridDim.x) {
-    const int e = job / sides;
-    const int side = (sides == 2) ? (job % 2) : -1;
+    // single problem: jobs (energy, side), or one job per energy when both
+    // leads are the same; batch: the job list names item and side
+    int e, side;
+    Prob P = P0;
+    if (b.probs) {
+      e = __builtin_amdgcn_readfirstlane(b.job_item[job]);
+      side = __builtin_amdgcn_readfirstlane(b.job_side[job]);
+      P = load_prob(b.probs + __builtin_amdgcn_readfirstlane(b.item_prob[e]));
+    } else {
+      e = job / sides;
+      side = (sides == 2) ? (job % 2) : -1;
+    }
     const double2* lead = (side == 1) ? P.leadR : P.leadL;
     const double V = (side == 1) ? P.VR : P.VL;
     const double2 *H00 = lead, *H01 = lead + MM, *S00 = lead + 2 * MM, *S01 = lead + 3 * MM;
@@ -648,7 +689,7 @@ __device__ __forceinline__ double refine(const Prob& P, const SweepArgs& a, int 
 // With a.elist (FP64 sweep only) the launch re-solves the listed energies,
 // keeping the refinement diagnostics in info and marking the fallback.
 template <typename R, int M, bool MIX>
-__global__ __launch_bounds__(NT, M > 64 ? 1 : 2) void k_sweep(Prob P, SweepArgs a) {
+__global__ __launch_bounds__(NT, M > 64 ? 1 : 2) void k_sweep(Prob P0, SweepArgs a, BatchDesc b) {
   typedef typename vec2t<R>::type V2;
   constexpr int MT = M / 16, MM = M * M, S = M + 1, LD = 2 * M;
   // M > 64: the working matrix and the staged coupling block live at the
@@ -659,7 +700,6 @@ __global__ __launch_bounds__(NT, M > 64 ? 1 : 2) void k_sweep(Prob P, SweepArgs 
   __shared__ BGJ<R, M> sc;
   __shared__ double tred[NWAVE];
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
-  const int N = P.N;
   char* wsb = a.ws + (size_t)blockIdx.x * a.ws_bytes;
   cpx<R>* mat;
   cpx<R>* Lst;                                  // -L_i, staged once per slab
@@ -671,24 +711,29 @@ __global__ __launch_bounds__(NT, M > 64 ? 1 : 2) void k_sweep(Prob P, SweepArgs 
     Lst = mat_l;
   }
   V2* XZ = (V2*)wsb;
-  V2* PSI = XZ + (size_t)N * M * LD;
-  float2* DI = nullptr;
-  float2* ZC = nullptr;
-  float2* YB = nullptr;
-  double2* P64 = nullptr;
-  if constexpr (MIX) {
-    DI = (float2*)(XZ + (size_t)(N + 1) * M * LD);
-    ZC = DI + (size_t)N * MM;
-    YB = ZC + (size_t)N * M * LD;
-    P64 = (double2*)(YB + (size_t)M * LD);
-  }
-  double* prt = a.part + (size_t)blockIdx.x * NWAVE * 2 * N * (MIX ? 2 : 1);
-  double* prt2 = prt + (size_t)NWAVE * 2 * N;
+  double* prt = a.part + (size_t)blockIdx.x * NWAVE * 2 * a.nmax * (MIX ? 2 : 1);
+  double* prt2 = prt + (size_t)NWAVE * 2 * a.nmax;
   // values loaded from memory are made wave-uniform explicitly, so that
   // everything addressed through them stays in scalar registers
   const int ne = a.elist ? __builtin_amdgcn_readfirstlane(*a.ecount) : a.nE;
   for (int q = blockIdx.x; q < ne; q += gridDim.x) {
     const int e = a.elist ? __builtin_amdgcn_readfirstlane(a.elist[q]) : q;
+    const Prob P = b.probs ? load_prob(b.probs + __builtin_amdgcn_readfirstlane(b.item_prob[e])) : P0;
+    const int N = P.N;
+    // workspace layout for this item's slab count (at most a.nmax)
+    V2* PSI = XZ + (size_t)N * M * LD;
+    float2* DI = nullptr;
+    float2* ZC = nullptr;
+    float2* YB = nullptr;
+    double2* P64 = nullptr;
+    if constexpr (MIX) {
+      DI = (float2*)(XZ + (size_t)(N + 1) * M * LD);
+      ZC = DI + (size_t)N * MM;
+      YB = ZC + (size_t)N * M * LD;
+      P64 = (double2*)(YB + (size_t)M * LD);
+    }
+    double* ldos_e = nullptr;
+    if (a.ldos) ldos_e = a.ldos + (b.probs ? b.item_ldos[e] : (size_t)e * 2 * N);
     const cpx<double> z = mk<double>(a.E[e], a.eta);
     const double2* sL = a.sig + (size_t)(2 * e) * MM;
     const double2* sR = sL + MM;
@@ -981,7 +1026,7 @@ __global__ __launch_bounds__(NT, M > 64 ? 1 : 2) void k_sweep(Prob P, SweepArgs 
       for (int q2 = 0; q2 < NWAVE; ++q2) v += prt[(q2 * 2 + s) * N + i];
       if constexpr (MIX)
         for (int q2 = 0; q2 < NWAVE; ++q2) v += prt2[(q2 * 2 + s) * N + i];
-      if (a.ldos) a.ldos[((size_t)e * 2 + s) * N + i] = v * ipi;
+      if (ldos_e) ldos_e[(size_t)s * N + i] = v * ipi;
     }
     if (t == 0) {
       a.T[e] = Te;
@@ -1024,25 +1069,26 @@ __global__ __launch_bounds__(64) void k_compact(const int* redo, int nE, int* el
 
 // ------------------------------------------------------------- launchers
 template <int M>
-hipError_t launch_decimate(const Prob& P, const double* E, int nE, double eta, int sides, double tol,
-                           int maxit, double heavy_tol, double2* scratch, int grid, double2* sig, double2* wf,
-                           double* sgn, int* iters, int* nheavy, hipStream_t st) {
-  hipLaunchKernelGGL((k_decimate<M>), dim3(grid), dim3(NT), 0, st, P, E, nE, eta, sides, tol, maxit, heavy_tol,
+hipError_t launch_decimate(const Prob& P, const BatchDesc& b, const double* E, int nE, double eta, int sides,
+                           double tol, int maxit, double heavy_tol, double2* scratch, int grid, double2* sig,
+                           double2* wf, double* sgn, int* iters, int* nheavy, hipStream_t st) {
+  hipLaunchKernelGGL((k_decimate<M>), dim3(grid), dim3(NT), 0, st, P, b, E, nE, eta, sides, tol, maxit, heavy_tol,
                      scratch, sig, wf, sgn, iters, nheavy);
   return hipGetLastError();
 }
 
 template <typename R, int M, bool MIX>
-hipError_t launch_sweep(const Prob& P, const SweepArgs& a, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((k_sweep<R, M, MIX>), dim3(grid), dim3(NT), 0, st, P, a);
+hipError_t launch_sweep(const Prob& P, const SweepArgs& a, const BatchDesc& b, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((k_sweep<R, M, MIX>), dim3(grid), dim3(NT), 0, st, P, a, b);
   return hipGetLastError();
 }
 
-hipError_t run_decimate(int M, const Prob& P, const double* E, int nE, double eta, int sides, double tol,
-                        int maxit, double heavy_tol, double2* scratch, int grid, double2* sig, double2* wf,
-                        double* sgn, int* iters, int* nheavy, hipStream_t st) {
+hipError_t run_decimate(int M, const Prob& P, const BatchDesc& b, const double* E, int nE, double eta, int sides,
+                        double tol, int maxit, double heavy_tol, double2* scratch, int grid, double2* sig,
+                        double2* wf, double* sgn, int* iters, int* nheavy, hipStream_t st) {
 #define QTX_DEC(MM) \
-  return launch_decimate<MM>(P, E, nE, eta, sides, tol, maxit, heavy_tol, scratch, grid, sig, wf, sgn, iters, nheavy, st)
+  return launch_decimate<MM>(P, b, E, nE, eta, sides, tol, maxit, heavy_tol, scratch, grid, sig, wf, sgn, iters, \
+                             nheavy, st)
   switch (M) {
     case 16: QTX_DEC(16);
     case 32: QTX_DEC(32);
@@ -1055,9 +1101,10 @@ hipError_t run_decimate(int M, const Prob& P, const double* E, int nE, double et
 #undef QTX_DEC
 }
 
-hipError_t run_sweep(int M, bool mixed, const Prob& P, const SweepArgs& a, int grid, hipStream_t st) {
+hipError_t run_sweep(int M, bool mixed, const Prob& P, const SweepArgs& a, const BatchDesc& b, int grid,
+                     hipStream_t st) {
 #define QTX_SWEEP(MM) \
-  return mixed ? launch_sweep<float, MM, true>(P, a, grid, st) : launch_sweep<double, MM, false>(P, a, grid, st)
+  return mixed ? launch_sweep<float, MM, true>(P, a, b, grid, st) : launch_sweep<double, MM, false>(P, a, b, grid, st)
   switch (M) {
     case 16: QTX_SWEEP(16);
     case 32: QTX_SWEEP(32);
