@@ -138,6 +138,115 @@ def time_path(ctx, torch, E_t, T_t, L_t, I_t, eta, prec, steps, warmup):
             "info": info}
 
 
+def bench_batch(args):
+    """64 devices of uneven slab count (50..400) and block size (32..128),
+    256 energies each: the batched launch (FP64 and mixed) against the
+    plain FP64 per-device loop."""
+    import torch
+    from paper_1903_00548_amd import _lib, workloads
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    wl = workloads.config3()
+    ctx = _lib.Context(0)
+    probs = [_lib.fill(ctx.problem(), d) for d in wl.devices]
+    n_items = sum(len(E) for E in wl.energies)
+    flops = sum(len(E) * (d.N + 22) * (152.0 / 3.0) * d.m ** 3 for d, E in zip(wl.devices, wl.energies))
+    out = {}
+
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        t = []
+        for _ in range(steps):
+            a = time.perf_counter()
+            r = fn()
+            t.append(time.perf_counter() - a)
+        return r, t
+
+    # the plain FP64 per-device loop first, one context per block size
+    # (refilled per device; closed before the batch allocates its buffers)
+    per_m = {}
+
+    def loop():
+        Ts = []
+        for d, E in zip(wl.devices, wl.energies):
+            c = per_m.setdefault(d.m, _lib.Context(0))
+            Ts.append(_lib.fill(c, d).solve(E, wl.eta, _lib.FP64, want_ldos=True)[0])
+        return Ts
+    Tl, t = timed(loop, 1, 1)
+    out["loop_fp64"] = {"energy_solves_per_s": n_items / float(np.median(t)), "s_per_pass": float(np.median(t))}
+    print(json.dumps({"loop_fp64": out["loop_fp64"]}), file=sys.stderr, flush=True)
+    for c in per_m.values():
+        c.close()
+    per_m.clear()
+
+    for name, prec, steps, warmup in (("batch_fp64", _lib.FP64, args.steps, 1),
+                                      ("batch_mixed", _lib.MIXED, 1, 0)):
+        (Ts, _, st), t = timed(lambda: _lib.solve_batch(ctx, probs, wl.energies, wl.eta, prec), steps, warmup)
+        out[name] = {"energy_solves_per_s": n_items / float(np.median(t)), "s_per_batch": float(np.median(t)),
+                     "frac_of_fp64_peak": flops / float(np.median(t)) / 78.6e12, "status": int(st), "T": Ts}
+        print(json.dumps({name: {k: v for k, v in out[name].items() if k != "T"}}), file=sys.stderr, flush=True)
+
+    dT = max(float(np.abs(a - b).max()) for a, b in zip(out["batch_mixed"]["T"], out["batch_fp64"]["T"]))
+    same = all(np.array_equal(a, b) for a, b in zip(out["batch_fp64"]["T"], Tl))
+    for k in ("batch_fp64", "batch_mixed"):
+        del out[k]["T"]
+    best = out["batch_fp64"]
+    line = {
+        "metric": "energy-solves/s, 64 uneven devices (N 50-400, m 32-128), 256 energies each",
+        "value": best["energy_solves_per_s"], "unit": "energy-solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": 1, "ms_per_step": 1e3 * best["s_per_batch"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "batch64_uneven_E256", "devices": len(wl.devices), "energies_per_step": n_items,
+                   "eta": wl.eta, "path": "batch_fp64"},
+        "paths": out, "mixed_max_dT_vs_fp64": dT, "batch_equals_per_device_loop": same,
+    }
+    print(json.dumps(line))
+
+
+def bench_serve(args):
+    """Serving workload: Poisson requests (devices from a pool of 8 lead sets,
+    N 50..400, m 32..128, 512..4096 lattice energies, right-lead bias).  The
+    configured load (200 req/s) is far above one GPU's capacity, so it runs
+    for a bounded wall time and reports what completed; a second run offers
+    requests at about 80 % of the throughput measured in the first."""
+    import torch
+    from paper_1903_00548_amd import _lib, serve, workloads
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    pool = workloads.serving_lead_pool()
+    prec = _lib.FP64 if args.serve_precision == "fp64" else _lib.MIXED
+
+    def make(reqs):
+        return [serve.Request(rid=k, t_arrival=q["t"], device=workloads.serving_device(q, pool), E=q["E"])
+                for k, q in enumerate(reqs)]
+
+    results = {}
+    backend = serve.QtxBackend(0, eta=1e-6, precision=prec, want_ldos=True)
+    configured = workloads.serving_requests(rate=200.0, duration=args.serve_seconds)
+    srv = serve.Server(backend, hbm_budget=96 << 30, max_active=32, energies_per_step=512)
+    st = srv.run(make(configured), time_limit=args.serve_seconds)
+    st["offered_requests"] = len(configured)
+    st["offered_rate_per_s"] = 200.0
+    results["configured_200_per_s"] = st
+    print(json.dumps({"configured": st}), file=sys.stderr, flush=True)
+    mean_nE = float(np.mean([len(q["E"]) for q in configured]))
+    rate = 0.8 * st["energy_solves_per_s"] / mean_nE
+    scaled = workloads.serving_requests(rate=rate, duration=args.serve_seconds, seed=5)
+    srv = serve.Server(backend, hbm_budget=96 << 30, max_active=32, energies_per_step=512)
+    st2 = srv.run(make(scaled), time_limit=4 * args.serve_seconds)
+    st2["offered_requests"] = len(scaled)
+    st2["offered_rate_per_s"] = rate
+    results["rate_scaled_80pct"] = st2
+    print(json.dumps({
+        "metric": "served energy-solves/s and p50/p99 request latency (Poisson requests, continuous batching)",
+        "value": st2["energy_solves_per_s"], "unit": "energy-solves/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if prec == _lib.FP64 else "f32+f64", "data": "synthetic",
+        "config": {"workload": "serve_poisson_pool8", "seconds": args.serve_seconds,
+                   "precision": args.serve_precision},
+        "runs": results,
+    }))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -147,7 +256,24 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration)")
+    ap.add_argument("--workload", choices=("cfg1", "batch64", "serve"), default="cfg1",
+                    help="cfg1: the headline N=200, m=64 grid (default); batch64: the uneven 64-device "
+                         "batch; serve: the Poisson request loop")
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
+    ap.add_argument("--serve-precision", choices=("fp64", "mixed"), default="fp64")
     args = ap.parse_args()
+    if args.workload == "serve":
+        if args.gpus != 1:
+            print("bench.py: one GPU only", file=sys.stderr)
+            sys.exit(2)
+        bench_serve(args)
+        return
+    if args.workload == "batch64":
+        if args.gpus != 1:
+            print("bench.py: one GPU only", file=sys.stderr)
+            sys.exit(2)
+        bench_batch(args)
+        return
     if args.copy_calibration:
         copy_calibration()
         return
