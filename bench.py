@@ -226,6 +226,7 @@ def bench_serve(args):
     st = srv.run(make(configured), time_limit=args.serve_seconds)
     st["offered_requests"] = len(configured)
     st["offered_rate_per_s"] = 200.0
+    st["sigma_cache_hits_misses_entries"] = list(backend.ctx.sigma_cache_stats())
     results["configured_200_per_s"] = st
     print(json.dumps({"configured": st}), file=sys.stderr, flush=True)
     mean_nE = float(np.mean([len(q["E"]) for q in configured]))
@@ -235,6 +236,7 @@ def bench_serve(args):
     st2 = srv.run(make(scaled), time_limit=4 * args.serve_seconds)
     st2["offered_requests"] = len(scaled)
     st2["offered_rate_per_s"] = rate
+    st2["sigma_cache_hits_misses_entries"] = list(backend.ctx.sigma_cache_stats())
     results["rate_scaled_80pct"] = st2
     print(json.dumps({
         "metric": "served energy-solves/s and p50/p99 request latency (Poisson requests, continuous batching)",

@@ -171,6 +171,13 @@ qtx_status qtx_self_energy(qtx_ctx* ctx, const double* E, int nE, double eta,
  *                           0 refines every column;
  *   "workgroups_per_cu"     1 or 2        2      resident energies per CU;
  *   "energies_per_launch"   [1, 2^20]     4096   energies per launch chunk;
+ *   "sigma_cache_bytes"     [0, 1e13]     16 GiB qtx_solve_batch keeps the lead
+ *                           self-energies, broadening factors and signs of
+ *                           every (lead blocks, E - V_lead) it has solved, up
+ *                           to this many bytes of device memory per block
+ *                           size, and reuses them (least recently used are
+ *                           replaced); 0 disables the cache.  Changing eta
+ *                           or a decimation option empties it;
  *   "use_graph"             0 or 1        1      qtx_solve_batch captures its
  *                           launch sequence in a HIP graph and replays it
  *                           while the batch shape is unchanged.
@@ -196,6 +203,13 @@ qtx_status qtx_problem_create(qtx_ctx* parent, qtx_ctx** problem);
 qtx_status qtx_solve_batch(qtx_ctx* ctx, int nprob, qtx_ctx* const* probs,
                            const double* const* E, const int* nE, double eta,
                            qtx_precision prec, double* const* T, double* const* ldos);
+
+/* Self-energy cache of qtx_solve_batch (option "sigma_cache_bytes"):
+ * contact lookups that found their entry (hits) and that had to run the
+ * decimation (misses) since the context was created, and the entries now
+ * held.  Each may be NULL.  For callers that serve many requests on the
+ * same leads and energy lattice. */
+qtx_status qtx_sigma_cache_stats(qtx_ctx* ctx, long long* hits, long long* misses, long long* slots);
 
 /* Host helper: slab charge from a solved grid with quadrature weights w:
  * charge[i] = sum_k w[k] (f((E_k - muL)/kT) ldos[k][0][i]

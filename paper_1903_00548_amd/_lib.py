@@ -54,6 +54,7 @@ _SIGS = {
     "qtx_problem_create": (c_int, [c_void_p, POINTER(c_void_p)]),
     "qtx_kernel_times": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p]),
     "qtx_set_option": (c_int, [c_void_p, c_char_p, c_double]),
+    "qtx_sigma_cache_stats": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "qtx_solve_batch": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_double, c_int,
                                 c_void_p, c_void_p]),
     "qtx_charge": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_double, c_double, c_double,
@@ -195,6 +196,12 @@ class Context:
 
     def set_option(self, name: str, value: float):
         self._check(self.lib.qtx_set_option(self.h, name.encode(), float(value)))
+
+    def sigma_cache_stats(self):
+        """(hits, misses, entries) of the batch self-energy cache."""
+        h, m_, n = ctypes.c_longlong(), ctypes.c_longlong(), ctypes.c_longlong()
+        self._check(self.lib.qtx_sigma_cache_stats(self.h, ctypes.byref(h), ctypes.byref(m_), ctypes.byref(n)))
+        return h.value, m_.value, n.value
 
     def problem(self):
         h = c_void_p()

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <unordered_map>
 #include <string>
 #include <vector>
 
@@ -67,6 +68,24 @@ struct qtx_ctx {
   DevBuf wE, wT, wldos, winfo;
   DevBuf sig, wf, sgn, iters, nheavy, dscr, sws, part;
   DevBuf redo, elist, ecount;                  // mixed: energies re-solved in FP64
+
+  uint64_t lead_hash[2] = {0, 0};
+
+  // self-energy cache of batched solves, per padded block size: slot k
+  // holds both surface self-energies, broadening factors, signs, doublings
+  // and refined-column counts of one (lead, shifted energy)
+  struct SigCache {
+    int M = 0, cap = 0;
+    DevBuf sig, wf, sgn, iters, nheavy;
+    std::unordered_map<unsigned long long, int> index;   // key hash -> slot
+    std::vector<std::pair<uint64_t, uint64_t>> key;       // per slot
+    std::vector<long long> tick;                          // last call that used the slot, -1 free
+  };
+  std::map<int, SigCache> sigcache;
+  double sigcache_bytes = 16.0 * (1ull << 30);
+  long long cache_hits = 0, cache_misses = 0, cache_calls = 0;
+  std::vector<double> cache_params;                      // eta and decimation settings of the cached data
+  DevBuf bslot, bjobE, bjobLead;
 
   // batched solves: flattened items of all problems, and the captured
   // launch sequence of the last batch shape
@@ -230,7 +249,7 @@ qtx_status solve_device_core(qtx_ctx* c, const double* E_dev, int nE, double eta
       QTX_HIP(c, c->ecount.ensure(sizeof(int)));
     }
     qtx::Prob P = make_prob(c);
-    qtx::SweepArgs a;
+    qtx::SweepArgs a{};
     a.E = E_dev + e0;
     a.nE = ne;
     a.eta = eta;
@@ -301,6 +320,13 @@ void qtx_destroy(qtx_ctx* c) {
   for (hipEvent_t e : c->ev_sw) hipEventDestroy(e);
   if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
   if (c->graph) hipGraphDestroy(c->graph);
+  for (auto& kv : c->sigcache) {
+    DevBuf* cb[] = {&kv.second.sig, &kv.second.wf, &kv.second.sgn, &kv.second.iters, &kv.second.nheavy};
+    for (DevBuf* b : cb) b->release();
+  }
+  c->bslot.release();
+  c->bjobE.release();
+  c->bjobLead.release();
   DevBuf* bufs[] = {&c->dlead[0], &c->dlead[1], &c->ddev, &c->dV, &c->wE, &c->wT, &c->wldos, &c->winfo,
                     &c->sig, &c->wf, &c->sgn, &c->iters, &c->nheavy, &c->dscr, &c->sws, &c->part,
                     &c->redo, &c->elist, &c->ecount, &c->bprobs, &c->bitem_prob, &c->bitem_ldos,
@@ -358,6 +384,11 @@ qtx_status qtx_set_lead(qtx_ctx* c, qtx_side side, int m, const qtx_c128* H00, c
   const qtx_c128* srcs[4] = {H00, H01, S00, S01};
   for (int q = 0; q < 4; ++q)
     for (int i = 0; i < m * m; ++i) hl[(size_t)q * m * m + i] = cd(srcs[q][i].re, srcs[q][i].im);
+  // content hash of the lead blocks (keys of the self-energy cache)
+  uint64_t hh = 1469598103934665603ull ^ (uint64_t)m;
+  const unsigned char* bytes = reinterpret_cast<const unsigned char*>(hl.data());
+  for (size_t i = 0; i < hl.size() * sizeof(cd); ++i) hh = (hh ^ bytes[i]) * 1099511628211ull;
+  c->lead_hash[side] = hh;
   c->Vlead[side] = V_lead;
   c->lead_set[side] = true;
   return QTX_OK;
@@ -558,6 +589,15 @@ qtx_status qtx_set_option(qtx_ctx* c, const char* name, double value) {
   } else if (n == "workgroups_per_cu") {
     if (!integral || value < 1 || value > 2) return fail(c, QTX_EINVAL, "workgroups_per_cu must be 1 or 2");
     c->wg_per_cu = (int)value;
+  } else if (n == "sigma_cache_bytes") {
+    if (!(value >= 0.0 && value <= 1e13)) return fail(c, QTX_EINVAL, "sigma_cache_bytes must be in [0, 1e13]");
+    c->sigcache_bytes = value;
+    for (auto& kv : c->sigcache) {           // shrink or drop: start over
+      kv.second.index.clear();
+      kv.second.key.clear();
+      kv.second.tick.clear();
+      kv.second.cap = 0;
+    }
   } else if (n == "use_graph") {
     if (!(value == 0.0 || value == 1.0)) return fail(c, QTX_EINVAL, "use_graph must be 0 or 1");
     c->use_graph = value != 0.0;
@@ -601,6 +641,11 @@ struct BatchChunk {
   int M, nmax, item0, nitems, job0, njobs;
 };
 
+// Decimation jobs of one block size that fill self-energy cache slots.
+struct DecGroup {
+  int M, job0, njobs;
+};
+
 void drop_graph(qtx_ctx* c) {
   if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
   if (c->graph) hipGraphDestroy(c->graph);
@@ -612,12 +657,30 @@ void drop_graph(qtx_ctx* c) {
 // The launch sequence of a batch (decimation, sweep, and for the mixed
 // path the compaction and FP64 re-solve of unconverged items), chunk by
 // chunk on the context stream.  Buffers must already have their sizes.
-qtx_status enqueue_batch(qtx_ctx* c, const std::vector<BatchChunk>& chunks, double eta, bool mixed) {
+qtx_status enqueue_batch(qtx_ctx* c, const std::vector<BatchChunk>& chunks, const std::vector<DecGroup>& groups,
+                         double eta, bool mixed, bool cached) {
+  for (const DecGroup& g : groups) {
+    if (g.njobs == 0) continue;
+    qtx_ctx::SigCache& sc = c->sigcache[g.M];
+    const int wg = g.M > 64 ? 1 : c->wg_per_cu;
+    qtx::BatchDesc b{};
+    b.probs = c->bprobs.as<qtx::Prob>();
+    b.job_item = c->bjob_item.as<int>() + g.job0;
+    b.njobs = g.njobs;
+    b.job_E = c->bjobE.as<double>() + g.job0;
+    b.job_lead = c->bjobLead.as<const double2*>() + g.job0;
+    qtx::Prob P0{};
+    P0.M = g.M;
+    const int gdec = std::max(1, std::min(g.njobs, c->num_cu * wg));
+    QTX_HIP(c, qtx::run_decimate(g.M, P0, b, b.job_E, g.njobs, eta, 2, c->dec_tol, c->dec_maxit, c->heavy_tol,
+                                 c->dscr.as<double2>(), gdec, sc.sig.as<double2>(), sc.wf.as<double2>(),
+                                 sc.sgn.as<double>(), sc.iters.as<int>(), sc.nheavy.as<int>(), c->stream));
+  }
   for (const BatchChunk& k : chunks) {
     const int M = k.M;
     const bool big = M > 64;
     const int wg = big ? 1 : c->wg_per_cu;
-    qtx::BatchDesc b;
+    qtx::BatchDesc b{};
     b.probs = c->bprobs.as<qtx::Prob>();
     b.item_prob = c->bitem_prob.as<int>() + k.item0;
     b.item_ldos = c->bitem_ldos.as<size_t>() + k.item0;
@@ -627,20 +690,34 @@ qtx_status enqueue_batch(qtx_ctx* c, const std::vector<BatchChunk>& chunks, doub
     qtx::Prob P0{};
     P0.N = k.nmax;
     P0.M = M;
-    const int gdec = std::max(1, std::min(k.njobs, c->num_cu * wg));
-    QTX_HIP(c, qtx::run_decimate(M, P0, b, c->bE.as<double>() + k.item0, k.nitems, eta, 2, c->dec_tol, c->dec_maxit,
-                                 c->heavy_tol, c->dscr.as<double2>(), gdec, c->sig.as<double2>(), c->wf.as<double2>(),
-                                 c->sgn.as<double>(), c->iters.as<int>(), c->nheavy.as<int>(), c->stream));
+    if (!cached) {
+      const int gdec = std::max(1, std::min(k.njobs, c->num_cu * wg));
+      QTX_HIP(c, qtx::run_decimate(M, P0, b, c->bE.as<double>() + k.item0, k.nitems, eta, 2, c->dec_tol,
+                                   c->dec_maxit, c->heavy_tol, c->dscr.as<double2>(), gdec, c->sig.as<double2>(),
+                                   c->wf.as<double2>(), c->sgn.as<double>(), c->iters.as<int>(),
+                                   c->nheavy.as<int>(), c->stream));
+    }
     const int grid = std::max(1, std::min(k.nitems, c->num_cu * wg));
-    qtx::SweepArgs a;
+    qtx::SweepArgs a{};
     a.E = c->bE.as<double>() + k.item0;
     a.nE = k.nitems;
     a.eta = eta;
-    a.sig = c->sig.as<double2>();
-    a.wf = c->wf.as<double2>();
-    a.sgn = c->sgn.as<double>();
-    a.iters = c->iters.as<int>();
-    a.nheavy = c->nheavy.as<int>();
+    if (cached) {
+      qtx_ctx::SigCache& sc = c->sigcache[M];
+      a.sig = sc.sig.as<double2>();
+      a.wf = sc.wf.as<double2>();
+      a.sgn = sc.sgn.as<double>();
+      a.iters = sc.iters.as<int>();
+      a.nheavy = sc.nheavy.as<int>();
+      a.sig_slot = c->bslot.as<int>() + 2 * (size_t)k.item0;
+    } else {
+      a.sig = c->sig.as<double2>();
+      a.wf = c->wf.as<double2>();
+      a.sgn = c->sgn.as<double>();
+      a.iters = c->iters.as<int>();
+      a.nheavy = c->nheavy.as<int>();
+      a.sig_slot = nullptr;
+    }
     a.ws = c->sws.as<char>();
     a.ws_bytes = qtx::sweep_ws_bytes(k.nmax, M, mixed);
     a.part = c->part.as<double>();
@@ -746,8 +823,126 @@ qtx_status qtx_solve_batch(qtx_ctx* c, int nprob, qtx_ctx* const* probs, const d
   const int nitems = (int)item_prob.size();
   if (nitems == 0) return QTX_OK;
 
+  // self-energy cache: both contacts of every item look up (lead content,
+  // shifted energy E - V); misses become decimation jobs into free or
+  // least recently used slots that this call does not use
+  bool cached = c->sigcache_bytes > 0;
+  std::vector<int> slot2;
+  std::vector<int> cjob_slot;
+  std::vector<double> cjob_E;
+  std::vector<const double2*> cjob_lead;
+  std::vector<DecGroup> groups;
+  long long hits = 0, misses = 0;
+  // until this call has run its decimation jobs, the slots it assigned hold
+  // no data: any early return drops the cache index
+  struct CacheGuard {
+    qtx_ctx* c;
+    bool armed = true;
+    ~CacheGuard() {
+      if (!armed) return;
+      for (auto& kv : c->sigcache) {
+        kv.second.index.clear();
+        std::fill(kv.second.tick.begin(), kv.second.tick.end(), -1);
+      }
+    }
+  } guard{c};
+  if (cached) {
+    const std::vector<double> params = {eta, c->dec_tol, (double)c->dec_maxit, c->heavy_tol};
+    if (params != c->cache_params) {
+      for (auto& kv : c->sigcache) {
+        kv.second.index.clear();
+        std::fill(kv.second.tick.begin(), kv.second.tick.end(), -1);
+      }
+      c->cache_params = params;
+    }
+    const long long now = ++c->cache_calls;
+    slot2.assign(2 * (size_t)nitems, 0);
+    bool overflow = false;
+    for (int i = 0; i < nitems && !overflow;) {
+      const int M = probs[item_prob[i]]->M;
+      qtx_ctx::SigCache& sc = c->sigcache[M];
+      const size_t MM = (size_t)M * M;
+      const size_t entry = 2 * MM * 2 * sizeof(double2) + 2 * M * sizeof(double) + 4 * sizeof(int);
+      const int cap = (int)std::min<double>(1 << 22, std::max(16.0, std::floor(c->sigcache_bytes / entry)));
+      if (sc.cap != cap) {
+        sc.index.clear();
+        sc.key.assign(cap, {0, 0});
+        sc.tick.assign(cap, -1);
+        sc.cap = cap;
+        sc.M = M;
+      }
+      QTX_HIP(c, sc.sig.ensure((size_t)cap * 2 * MM * sizeof(double2)));
+      QTX_HIP(c, sc.wf.ensure((size_t)cap * 2 * MM * sizeof(double2)));
+      QTX_HIP(c, sc.sgn.ensure((size_t)cap * 2 * M * sizeof(double)));
+      QTX_HIP(c, sc.iters.ensure((size_t)cap * 2 * sizeof(int)));
+      QTX_HIP(c, sc.nheavy.ensure((size_t)cap * 2 * sizeof(int)));
+      DecGroup g{M, (int)cjob_slot.size(), 0};
+      int hand = 0, scanned = 0;
+      for (; i < nitems && probs[item_prob[i]]->M == M; ++i) {
+        const qtx_ctx* q = probs[item_prob[i]];
+        for (int side = 0; side < 2 && !overflow; ++side) {
+          const double Es = hE[i] - q->Vlead[side];
+          uint64_t eb;
+          std::memcpy(&eb, &Es, sizeof(eb));
+          const std::pair<uint64_t, uint64_t> key(q->lead_hash[side], eb);
+          const unsigned long long hk = key.first * 0x9E3779B97F4A7C15ull ^ key.second;
+          auto it = sc.index.find(hk);
+          int slot = -1;
+          if (it != sc.index.end() && sc.key[it->second] == key) {
+            slot = it->second;
+            ++hits;
+          } else {
+            // clock scan for a slot not used by this call
+            while (scanned < 2 * cap && sc.tick[hand] == now) {
+              hand = (hand + 1) % cap;
+              ++scanned;
+            }
+            if (sc.tick[hand] == now) {
+              overflow = true;
+              break;
+            }
+            slot = hand;
+            hand = (hand + 1) % cap;
+            if (sc.tick[slot] >= 0) {
+              const auto& old = sc.key[slot];
+              auto ot = sc.index.find(old.first * 0x9E3779B97F4A7C15ull ^ old.second);
+              if (ot != sc.index.end() && ot->second == slot) sc.index.erase(ot);
+            }
+            if (it != sc.index.end()) sc.index.erase(it);   // hash collision: the new key takes over
+            sc.key[slot] = key;
+            sc.index[hk] = slot;
+            cjob_slot.push_back(slot);
+            cjob_E.push_back(Es);
+            cjob_lead.push_back(q->dlead[side].as<double2>());
+            ++misses;
+          }
+          sc.tick[slot] = now;
+          slot2[2 * (size_t)i + side] = slot;
+        }
+      }
+      g.njobs = (int)cjob_slot.size() - g.job0;
+      groups.push_back(g);
+    }
+    if (overflow) {
+      // this batch needs more distinct contacts than the cache holds: drop
+      // what this call assigned and solve it without the cache
+      for (auto& kv : c->sigcache) {
+        kv.second.index.clear();
+        std::fill(kv.second.tick.begin(), kv.second.tick.end(), -1);
+      }
+      cached = false;
+      groups.clear();
+      hits = misses = 0;
+    }
+  }
+
   // buffer sizes (all allocations before any capture)
   size_t sig_b = 0, dscr_b = 0, sws_b = 0, part_b = 0, per_b = 0;
+  for (const DecGroup& g : groups) {
+    const int wg = g.M > 64 ? 1 : c->wg_per_cu;
+    const size_t gdec = std::max(1, std::min(g.njobs, c->num_cu * wg));
+    dscr_b = std::max(dscr_b, gdec * qtx::dec_ws_elems(g.M) * sizeof(double2));
+  }
   for (const BatchChunk& k : chunks) {
     const size_t MM = (size_t)k.M * k.M;
     const int wg = k.M > 64 ? 1 : c->wg_per_cu;
@@ -775,7 +970,7 @@ qtx_status qtx_solve_batch(qtx_ctx* c, int nprob, qtx_ctx* const* probs, const d
   QTX_HIP(c, c->bprobs.ensure(nprob * sizeof(qtx::Prob)));
   QTX_HIP(c, c->bitem_prob.ensure(nitems * sizeof(int)));
   QTX_HIP(c, c->bitem_ldos.ensure(nitems * sizeof(size_t)));
-  QTX_HIP(c, c->bjob_item.ensure(job_item.size() * sizeof(int)));
+  QTX_HIP(c, c->bjob_item.ensure(std::max(std::max(job_item.size(), cjob_slot.size()), (size_t)1) * sizeof(int)));
   QTX_HIP(c, c->bjob_side.ensure(job_side.size() * sizeof(int)));
   QTX_HIP(c, c->bE.ensure(nitems * sizeof(double)));
   QTX_HIP(c, c->bT.ensure(nitems * sizeof(double)));
@@ -791,6 +986,24 @@ qtx_status qtx_solve_batch(qtx_ctx* c, int nprob, qtx_ctx* const* probs, const d
   QTX_HIP(c, hipMemcpyAsync(c->bjob_side.p, job_side.data(), job_side.size() * sizeof(int), hipMemcpyHostToDevice,
                             c->stream));
   QTX_HIP(c, hipMemcpyAsync(c->bE.p, hE.data(), nitems * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  if (cached) {
+    QTX_HIP(c, c->bslot.ensure(slot2.size() * sizeof(int)));
+    QTX_HIP(c, hipMemcpyAsync(c->bslot.p, slot2.data(), slot2.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
+    const size_t nj = std::max<size_t>(cjob_slot.size(), 1);
+    QTX_HIP(c, c->bjob_item.ensure(std::max(nj, job_item.size()) * sizeof(int)));
+    QTX_HIP(c, c->bjobE.ensure(nj * sizeof(double)));
+    QTX_HIP(c, c->bjobLead.ensure(nj * sizeof(void*)));
+    if (!cjob_slot.empty()) {
+      QTX_HIP(c, hipMemcpyAsync(c->bjob_item.p, cjob_slot.data(), cjob_slot.size() * sizeof(int),
+                                hipMemcpyHostToDevice, c->stream));
+      QTX_HIP(c, hipMemcpyAsync(c->bjobE.p, cjob_E.data(), cjob_E.size() * sizeof(double), hipMemcpyHostToDevice,
+                                c->stream));
+      QTX_HIP(c, hipMemcpyAsync(c->bjobLead.p, cjob_lead.data(), cjob_lead.size() * sizeof(void*),
+                                hipMemcpyHostToDevice, c->stream));
+    }
+  }
+  c->cache_hits += hits;
+  c->cache_misses += misses;
 
   // the launch sequence depends on the batch shape (and the buffers, whose
   // sizes follow from it): replay the captured graph while it is unchanged
@@ -814,15 +1027,22 @@ qtx_status qtx_solve_batch(qtx_ctx* c, int nprob, qtx_ctx* const* probs, const d
     sig.push_back((long long)(uintptr_t)bp);
   for (const BatchChunk& k : chunks)
     for (int v : {k.M, k.nmax, k.item0, k.nitems, k.job0, k.njobs}) sig.push_back(v);
+  sig.push_back(cached);
+  for (const DecGroup& g : groups)
+    for (int v : {g.M, g.job0, g.njobs}) sig.push_back(v);
+  for (auto& kv : c->sigcache) sig.push_back((long long)(uintptr_t)kv.second.sig.p);
+  sig.push_back((long long)(uintptr_t)c->bslot.p);
+  sig.push_back((long long)(uintptr_t)c->bjobE.p);
+  sig.push_back((long long)(uintptr_t)c->bjob_item.p);
   if (!c->use_graph) {
     drop_graph(c);
-    qtx_status s = enqueue_batch(c, chunks, eta, mixed);
+    qtx_status s = enqueue_batch(c, chunks, groups, eta, mixed, cached);
     if (s != QTX_OK) return s;
   } else {
     if (sig != c->batch_sig || !c->graph_exec) {
       drop_graph(c);
       QTX_HIP(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-      qtx_status s = enqueue_batch(c, chunks, eta, mixed);
+      qtx_status s = enqueue_batch(c, chunks, groups, eta, mixed, cached);
       hipGraph_t g = nullptr;
       hipError_t ce = hipStreamEndCapture(c->stream, &g);
       if (s != QTX_OK) {
@@ -844,6 +1064,7 @@ qtx_status qtx_solve_batch(qtx_ctx* c, int nprob, qtx_ctx* const* probs, const d
     QTX_HIP(c, hipMemcpyAsync(hL.data(), c->bldos.p, ldos_total * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   QTX_HIP(c, hipMemcpyAsync(hinfo.data(), c->binfo.p, nitems * sizeof(qtx_info), hipMemcpyDeviceToHost, c->stream));
   QTX_HIP(c, hipStreamSynchronize(c->stream));
+  guard.armed = false;
   bool flagged = false;
   for (int i = 0; i < nitems; ++i) {
     const int p = item_prob[i], e = item_e[i];
@@ -853,6 +1074,16 @@ qtx_status qtx_solve_batch(qtx_ctx* c, int nprob, qtx_ctx* const* probs, const d
     flagged |= hinfo[i].flags != 0;
   }
   if (flagged) return fail(c, QTX_ENOTCONV, "some energies were flagged");
+  return QTX_OK;
+}
+
+qtx_status qtx_sigma_cache_stats(qtx_ctx* c, long long* hits, long long* misses, long long* slots) {
+  if (!c) return QTX_EINVAL;
+  long long used = 0;
+  for (auto& kv : c->sigcache) used += (long long)kv.second.index.size();
+  if (hits) *hits = c->cache_hits;
+  if (misses) *misses = c->cache_misses;
+  if (slots) *slots = used;
   return QTX_OK;
 }
 

@@ -49,6 +49,9 @@ struct Prob {
 // over njobs jobs (item job_item[j], contact job_side[j]: 0 left, 1 right,
 // -1 both when the problem's leads are the same).  probs == nullptr: one
 // problem, passed by value.
+// Self-energy cache (job_E non-null): decimation job j fills slot
+// job_item[j] of the cache with both surface self-energies of the lead
+// job_lead[j] at the shifted energy job_E[j] (E - V already applied).
 struct BatchDesc {
   const Prob* probs;
   const int* item_prob;
@@ -56,6 +59,8 @@ struct BatchDesc {
   const int* job_item;
   const int* job_side;
   int njobs;
+  const double* job_E;
+  const double2* const* job_lead;
 };
 
 // Arguments of one sweep launch.  Energy e uses sig/wf/sgn/iters/nheavy
@@ -71,6 +76,9 @@ struct SweepArgs {
   const double* sgn;       // signs of the broadening factors (2 M)
   const int* iters;        // doublings per side (2), negative if capped
   const int* nheavy;       // refined columns per side (2), mixed sweep only
+  const int* sig_slot;     // non-null: item e takes the left contact from slot
+                           // sig_slot[2e] and the right one from sig_slot[2e+1]
+                           // of sig/wf/sgn/iters/nheavy (else slot e for both)
   char* ws;
   size_t ws_bytes;
   double* part;            // per workgroup NWAVE * 2 * nmax doubles (twice that, mixed)

@@ -381,7 +381,14 @@ __global__ __launch_bounds__(NT, M > 64 ? 1 : 2) void k_decimate(Prob P0, BatchD
     // leads are the same; batch: the job list names item and side
     int e, side;
     Prob P = P0;
-    if (b.probs) {
+    if (b.job_E) {
+      // self-energy cache: job j fills slot job_item[j] (both surfaces) for
+      // the lead job_lead[j] at the already shifted energy job_E[j]
+      e = __builtin_amdgcn_readfirstlane(b.job_item[job]);
+      side = -1;
+      P.leadL = P.leadR = uni(b.job_lead[job]);
+      P.VL = P.VR = 0.0;
+    } else if (b.probs) {
       e = __builtin_amdgcn_readfirstlane(b.job_item[job]);
       side = __builtin_amdgcn_readfirstlane(b.job_side[job]);
       P = load_prob(b.probs + __builtin_amdgcn_readfirstlane(b.item_prob[e]));
@@ -392,7 +399,7 @@ __global__ __launch_bounds__(NT, M > 64 ? 1 : 2) void k_decimate(Prob P0, BatchD
     const double2* lead = (side == 1) ? P.leadR : P.leadL;
     const double V = (side == 1) ? P.VR : P.VL;
     const double2 *H00 = lead, *H01 = lead + MM, *S00 = lead + 2 * MM, *S01 = lead + 3 * MM;
-    const cpx<double> zx = mk<double>(E[e] - V, eta);
+    const cpx<double> zx = mk<double>((b.job_E ? b.job_E[job] : E[e]) - V, eta);
     double scl = 0.0;
     for (int idx = t; idx < MM; idx += NT) {
       const int r = idx / M, c = idx - r * M;
@@ -545,16 +552,13 @@ __global__ __launch_bounds__(NT, M > 64 ? 1 : 2) void k_decimate(Prob P0, BatchD
 // slab takes two barriers forward and one backward.  Returns the last
 // relative residual; *steps receives the corrections applied.
 template <int M>
-__device__ __forceinline__ double refine(const Prob& P, const SweepArgs& a, int e, cpx<double> z, int hR, int hL,
+__device__ __forceinline__ double refine(const Prob& P, const SweepArgs& a, const double2* sL, const double2* sR,
+                                         const double2* WL, const double2* WR, cpx<double> z, int hR, int hL,
                                          const float2* XZ, const float2* DI, float2* ZC, float2* YB, double2* P64,
                                          double* red, int* steps) {
   constexpr int MT = M / 16, MM = M * M, LD = 2 * M;
   const int N = P.N, t = threadIdx.x, w = t >> 6;
   const int npair = MT * (hR + hL);
-  const double2* sL = a.sig + (size_t)(2 * e) * MM;
-  const double2* sR = sL + MM;
-  const double2* WL = a.wf + (size_t)(2 * e) * MM;
-  const double2* WR = WL + MM;
   // column tile of the q-th refined tile: right injection first
   auto colt = [&](int q) { return q < hR ? q : MT + q - hR; };
   double bb = 0.0;
@@ -735,16 +739,20 @@ __global__ __launch_bounds__(NT, M > 64 ? 1 : 2) void k_sweep(Prob P0, SweepArgs
     double* ldos_e = nullptr;
     if (a.ldos) ldos_e = a.ldos + (b.probs ? b.item_ldos[e] : (size_t)e * 2 * N);
     const cpx<double> z = mk<double>(a.E[e], a.eta);
-    const double2* sL = a.sig + (size_t)(2 * e) * MM;
-    const double2* sR = sL + MM;
-    const double2* WL = a.wf + (size_t)(2 * e) * MM;
-    const double2* WR = WL + MM;
-    const double* sgL = a.sgn + (size_t)(2 * e) * M;
-    const double* sgR = sgL + M;
+    // contact data: the left surface of slot sl and the right surface of
+    // slot sr (both e, unless a self-energy cache supplies the slots)
+    const int sl = a.sig_slot ? __builtin_amdgcn_readfirstlane(a.sig_slot[2 * e]) : e;
+    const int sr = a.sig_slot ? __builtin_amdgcn_readfirstlane(a.sig_slot[2 * e + 1]) : e;
+    const double2* sL = a.sig + (size_t)(2 * sl) * MM;
+    const double2* sR = a.sig + (size_t)(2 * sr + 1) * MM;
+    const double2* WL = a.wf + (size_t)(2 * sl) * MM;
+    const double2* WR = a.wf + (size_t)(2 * sr + 1) * MM;
+    const double* sgL = a.sgn + (size_t)(2 * sl) * M;
+    const double* sgR = a.sgn + (size_t)(2 * sr + 1) * M;
     int hL = MT, hR = MT;                      // heavy column tiles (MIX)
     if constexpr (MIX) {
-      hL = __builtin_amdgcn_readfirstlane(min(max((a.nheavy[2 * e] + 15) / 16, 1), MT));
-      hR = __builtin_amdgcn_readfirstlane(min(max((a.nheavy[2 * e + 1] + 15) / 16, 1), MT));
+      hL = __builtin_amdgcn_readfirstlane(min(max((a.nheavy[2 * sl] + 15) / 16, 1), MT));
+      hR = __builtin_amdgcn_readfirstlane(min(max((a.nheavy[2 * sr + 1] + 15) / 16, 1), MT));
     }
     for (int i = 0; i < N; ++i) {
       __syncthreads();
@@ -969,7 +977,7 @@ __global__ __launch_bounds__(NT, M > 64 ? 1 : 2) void k_sweep(Prob P0, SweepArgs
     int steps = 0;
     double rel = 0.0;
     if constexpr (MIX) {
-      rel = refine<M>(P, a, e, z, hR, hL, (const float2*)XZ, DI, ZC, YB, P64, tred, &steps);
+      rel = refine<M>(P, a, sL, sR, WL, WR, z, hR, hL, (const float2*)XZ, DI, ZC, YB, P64, tred, &steps);
       // transmission and the heavy columns' densities from the refined solution
       {
         const double2* PN = P64 + (size_t)(N - 1) * M * LD;
@@ -1030,7 +1038,7 @@ __global__ __launch_bounds__(NT, M > 64 ? 1 : 2) void k_sweep(Prob P0, SweepArgs
     }
     if (t == 0) {
       a.T[e] = Te;
-      const int i0 = a.iters[2 * e], i1 = a.iters[2 * e + 1];
+      const int i0 = a.iters[2 * sl], i1 = a.iters[2 * sr + 1];
       const bool rbad = MIX && !(rel <= a.rtol);
       if constexpr (MIX) a.redo[e] = (rbad || bad) ? 1 : 0;
       if (a.info) {

@@ -115,3 +115,48 @@ def test_batch_errors(gpu_lib, batch):
     assert ei.value.status == _lib.EINVAL
     T, L, st = _lib.solve_batch(ctx, [], [], ETA)
     assert T == [] and st == _lib.OK
+
+
+def test_sigma_cache_reuse_and_equality(gpu_lib):
+    """Two problems on the same lead blocks, the second with its right lead
+    shifted by a multiple of the lattice step: its contacts find the first
+    problem's self-energies.  Results equal the uncached solves bit for bit;
+    a repeated batch runs no decimation; a cache too small for the batch
+    falls back to solving without it."""
+    step = 2.0 ** -11
+    lead = W.random_lead(np.random.default_rng(41), 24)
+    shifted = W.Lead(H00=lead.H00, H01=lead.H01, S00=lead.S00, S01=lead.S01, V=-8 * step)
+    d1 = W.Device(N=9, m=24, lead_L=lead, lead_R=lead, V=np.zeros(9), pot_mode=W.POT_DIAG)
+    d2 = W.Device(N=6, m=24, lead_L=lead, lead_R=shifted, V=np.linspace(0.0, -8 * step, 6),
+                  pot_mode=W.POT_LINEAR_FE)
+    E1 = -1.0 + step * np.arange(40)
+    E2 = E1[10:30]
+
+    ref_ctx = _lib.Context(0)
+    ref_ctx.set_option("sigma_cache_bytes", 0)
+    rp = [_lib.fill(ref_ctx.problem(), d) for d in (d1, d2)]
+    Tr, Lr, _ = _lib.solve_batch(ref_ctx, rp, [E1, E2], ETA)
+    assert ref_ctx.sigma_cache_stats() == (0, 0, 0)
+
+    ctx = _lib.Context(0)
+    probs = [_lib.fill(ctx.problem(), d) for d in (d1, d2)]
+    Ts, Ls, _ = _lib.solve_batch(ctx, probs, [E1, E2], ETA)
+    hits, misses, slots = ctx.sigma_cache_stats()
+    # d1: 40 entries (both contacts share one); d2 left: 20 hits; d2 right at
+    # E - V_R = E + 8 step: 20 lookups, 20 of them inside E1's range -> hits
+    assert misses == 40 and hits == 40 + 20 + 20, (hits, misses)
+    for k in range(2):
+        assert np.array_equal(Ts[k], Tr[k]) and np.array_equal(Ls[k], Lr[k])
+    Ts2, Ls2, _ = _lib.solve_batch(ctx, probs, [E1, E2], ETA)
+    h2, m2, _ = ctx.sigma_cache_stats()
+    assert m2 == misses and h2 == hits + 120
+    for k in range(2):
+        assert np.array_equal(Ts2[k], Tr[k]) and np.array_equal(Ls2[k], Lr[k])
+
+    small = _lib.Context(0)
+    small.set_option("sigma_cache_bytes", 1.0)          # 16 entries: too few for 40 distinct contacts
+    sp = [_lib.fill(small.problem(), d) for d in (d1, d2)]
+    Ts3, Ls3, _ = _lib.solve_batch(small, sp, [E1, E2], ETA)
+    for k in range(2):
+        assert np.array_equal(Ts3[k], Tr[k]) and np.array_equal(Ls3[k], Lr[k])
+    assert small.sigma_cache_stats()[2] == 0
