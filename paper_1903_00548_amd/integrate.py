@@ -1,0 +1,145 @@
+"""Energy integration over the transport solve (Sec. "Density", eq.
+density_3d; Sec. "Transmission and Ballistic Current", eq. current; the
+charge Jacobian of eq. density_jacobian).
+
+The integrals run over energies whose integrand is one solve each, with
+singular features (band edges of the contacts) at places not known in
+advance, so they are taken by adaptive Simpson quadrature.  The driver is
+batched: every round collects the new abscissae of all panels that fail
+their error test and evaluates them in ONE solver call (one launch sequence
+on the GPU), instead of recursing panel by panel.
+
+Panel [a, b] with midpoint m and quarter points l, r: S1 = Simpson on
+(a, m, b), S2 = Simpson on (a, l, m) + (m, r, b); the panel is accepted
+when max|S2 - S1| / 15 <= tol (b - a) / (B - A) (the absolute tolerance
+spread over the interval [A, B]) and contributes the Richardson value
+S2 + (S2 - S1) / 15; otherwise it is split at m.
+
+Quantities (n^L_i, n^R_i: slab densities of states per injecting contact,
+T: transmission; f: Fermi function):
+  density   n_i = int dE [f(E - muL) n^L_i(E) + f(E - muR) n^R_i(E)]
+  jacobian  dn_i/dmu = int dE [-f'(E - muL) n^L_i(E) - f'(E - muR) n^R_i(E)]
+            (the derivative of the density with respect to a rigid shift
+            of both electrochemical potentials; eq. density_jacobian writes
+            it with df/dE, whose sign is opposite)
+  current   J = int dE T(E) [f(E - muL) - f(E - muR)]  (eV);
+            I = (2 e^2 / h) J  with spin degeneracy 2.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Callable, Dict, Optional
+
+import numpy as np
+
+TWO_E2_OVER_H = 7.748091729e-5      # A per eV of J (2 e^2 / h in siemens)
+
+
+def fermi(x, kT):
+    """1 / (1 + exp(x / kT)), evaluated without overflow."""
+    return 0.5 * (1.0 - np.tanh(0.5 * np.asarray(x, dtype=float) / kT))
+
+
+def minus_dfermi(x, kT):
+    """-df/dx = 1 / (4 kT cosh^2(x / 2kT))."""
+    c = np.cosh(np.minimum(np.abs(0.5 * np.asarray(x, dtype=float) / kT), 350.0))
+    return 1.0 / (4.0 * kT * c * c)
+
+
+@dataclasses.dataclass
+class Result:
+    value: np.ndarray                 # integral of every integrand component
+    error_estimate: float             # sum of the accepted panels' |S2 - S1| / 15 (max norm)
+    converged: bool
+    evaluations: int                  # distinct abscissae evaluated
+    rounds: int                       # solver calls
+    energies: np.ndarray              # all abscissae, sorted
+
+
+def adaptive_simpson(F: Callable[[np.ndarray], np.ndarray], A: float, B: float, tol: float,
+                     n0: int = 16, max_rounds: int = 40, min_width: float = 1e-10) -> Result:
+    """Integrate the vector function F over [A, B] to absolute tolerance tol
+    (max norm over components).  F takes a 1-D array of energies and returns
+    an array of shape (len(E), K)."""
+    if not (B > A) or not (tol > 0):
+        raise ValueError("need B > A and tol > 0")
+    vals: Dict[float, np.ndarray] = {}
+    rounds = 0
+
+    def evaluate(points):
+        nonlocal rounds
+        new = sorted(p for p in points if p not in vals)
+        if not new:
+            return
+        out = np.asarray(F(np.array(new)), dtype=float)
+        if out.ndim == 1:
+            out = out[:, None]
+        for e, v in zip(new, out):
+            vals[e] = v
+        rounds += 1
+
+    edges = np.linspace(A, B, n0 + 1)
+    pending = [(float(edges[k]), float(edges[k + 1])) for k in range(n0)]
+    total = None
+    err_total = 0.0
+    while pending and rounds < max_rounds:
+        pts = set()
+        for a, b in pending:
+            m = 0.5 * (a + b)
+            pts.update((a, 0.5 * (a + m), m, 0.5 * (m + b), b))
+        evaluate(pts)
+        nxt = []
+        for a, b in pending:
+            m = 0.5 * (a + b)
+            l, r = 0.5 * (a + m), 0.5 * (m + b)
+            fa, fl, fm, fr, fb = vals[a], vals[l], vals[m], vals[r], vals[b]
+            s1 = (b - a) / 6.0 * (fa + 4.0 * fm + fb)
+            s2 = (m - a) / 6.0 * (fa + 4.0 * fl + fm) + (b - m) / 6.0 * (fm + 4.0 * fr + fb)
+            err = float(np.max(np.abs(s2 - s1))) / 15.0
+            if err <= tol * (b - a) / (B - A) or (b - a) < min_width:
+                v = s2 + (s2 - s1) / 15.0
+                total = v if total is None else total + v
+                err_total += err
+            else:
+                nxt.extend(((a, m), (m, b)))
+        pending = nxt
+    converged = not pending
+    for a, b in pending:                      # out of rounds: take what is known
+        m = 0.5 * (a + b)
+        l, r = 0.5 * (a + m), 0.5 * (m + b)
+        if all(p in vals for p in (a, l, m, r, b)):
+            s2 = (m - a) / 6.0 * (vals[a] + 4.0 * vals[l] + vals[m]) + (b - m) / 6.0 * (vals[m] + 4.0 * vals[r] + vals[b])
+        else:
+            s2 = (b - a) / 6.0 * (vals[a] + 4.0 * vals[m] + vals[b])
+        total = s2 if total is None else total + s2
+    return Result(value=np.asarray(total), error_estimate=err_total, converged=converged,
+                  evaluations=len(vals), rounds=rounds, energies=np.array(sorted(vals)))
+
+
+def integrand(quantity: str, solve: Callable, muL: float, muR: float, kT: float):
+    """Integrand of one quantity from a solver E -> (T, ldos[nE, 2, N])."""
+    if quantity not in ("density", "jacobian", "current"):
+        raise ValueError(f"unknown quantity {quantity!r}")
+
+    def F(E):
+        T, L = solve(E)
+        if quantity == "current":
+            return (T * (fermi(E - muL, kT) - fermi(E - muR, kT)))[:, None]
+        w = fermi if quantity == "density" else minus_dfermi
+        return w(E - muL, kT)[:, None] * L[:, 0, :] + w(E - muR, kT)[:, None] * L[:, 1, :]
+    return F
+
+
+def integrate(solve: Callable, quantity: str, A: float, B: float, muL: float, muR: float, kT: float,
+              tol: float, n0: int = 16, max_rounds: int = 40) -> Result:
+    """Adaptive integral of a quantity over [A, B] (see the module docstring)
+    with the transport solve as integrand."""
+    return adaptive_simpson(integrand(quantity, solve, muL, muR, kT), A, B, tol, n0=n0, max_rounds=max_rounds)
+
+
+def qtx_solver(ctx, eta: float, precision: int = 0):
+    """E -> (T, ldos) through the HIP library (one batched call per round)."""
+    def solve(E):
+        T, L, _, _ = ctx.solve(np.ascontiguousarray(E, dtype=np.float64), eta, precision, want_ldos=True)
+        return T, L
+    return solve

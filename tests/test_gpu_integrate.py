@@ -1,0 +1,52 @@
+"""Energy integrals (density, its potential derivative, current) by the
+adaptive driver over the HIP solve, against the oracle's plain composite
+Simpson on a uniform grid.  A broadening of 0.05 eV keeps the integrands
+smooth on the reference grid; the reference's own error is estimated by
+halving its step."""
+import numpy as np
+import pytest
+
+from oracle import integrals as oint
+from paper_1903_00548_amd import _lib
+from paper_1903_00548_amd import integrate as I
+from paper_1903_00548_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+ETA = 0.05
+MUL, MUR, KT = 0.1, -0.1, 0.05
+
+
+@pytest.fixture(scope="module")
+def setup():
+    dev = W.small_random_device(51, 10, 8, uniform=False, same_leads=True, pot_mode=W.POT_LINEAR_FE)
+    ctx = _lib.context_for(dev, 0)
+    return dev, ctx
+
+
+def _ref(dev, A, B):
+    fine = oint.integrals(dev, ETA, A, B, MUL, MUR, KT, 2048)
+    coarse = oint.integrals(dev, ETA, A, B, MUL, MUR, KT, 1024)
+    return fine, coarse
+
+
+def test_density_jacobian_current(setup):
+    dev, ctx = setup
+    solve = I.qtx_solver(ctx, ETA)
+    A, B = -7.0, MUL + 20 * KT
+    (dens, jac, _), (dens_c, jac_c, _) = _ref(dev, A, B)
+    rd = I.integrate(solve, "density", A, B, MUL, MUR, KT, tol=1e-7)
+    rj = I.integrate(solve, "jacobian", A, B, MUL, MUR, KT, tol=1e-7)
+    assert rd.converged and rj.converged
+    for got, ref, refc, name in ((rd.value, dens, dens_c, "density"), (rj.value, jac, jac_c, "jacobian")):
+        bar = 10 * np.abs(ref - refc).max() + 1e-6 * max(1.0, np.abs(ref).max())
+        err = np.abs(got - ref).max()
+        print(f"{name}: max|adaptive - reference| = {err:.2e} (bar {bar:.2e}), {rd.evaluations} energies")
+        assert err <= bar
+    A2, B2 = MUR - 20 * KT, MUL + 20 * KT
+    (_, _, cur), (_, _, cur_c) = _ref(dev, A2, B2)
+    rc = I.integrate(solve, "current", A2, B2, MUL, MUR, KT, tol=1e-9)
+    bar = 10 * abs(cur - cur_c) + 1e-8
+    assert abs(rc.value[0] - cur) <= bar, (rc.value[0], cur, bar)
+    # each round is one batched solve of new energies only
+    assert rc.rounds <= 40 and len(np.unique(rc.energies)) == rc.evaluations
