@@ -138,6 +138,72 @@ def time_path(ctx, torch, E_t, T_t, L_t, I_t, eta, prec, steps, warmup):
             "info": info}
 
 
+def bench_cfg2(args):
+    """N = 400, m = 128: 3840 energies in [-1.5, 1.5] plus 256 within 1 meV of
+    the lead band edges.  Mixed and FP64 paths; the mixed path's error
+    against FP64 on every energy (uniform and band-edge sets reported
+    separately) and both against the oracle on sampled energies."""
+    import torch
+    from paper_1903_00548_amd import _lib, workloads
+    import oracle
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    edges = np.loadtxt(os.path.join(ROOT, "tests", "golden", "cfg2_band_edge_energies.txt"))
+    wl = workloads.config2(band_edge_energies=edges)
+    dev = wl.device
+    nE, n_uni = len(wl.E), len(wl.E) - len(edges)
+    ctx = _lib.context_for(dev, 0)
+    ctx.set_stream(torch.cuda.current_stream().cuda_stream)
+    E_t = torch.tensor(wl.E, dtype=torch.float64, device="cuda")
+    T_t = torch.empty(nE, dtype=torch.float64, device="cuda")
+    L_t = torch.empty((nE, 2, dev.N), dtype=torch.float64, device="cuda")
+    I_t = torch.empty(nE * _lib.INFO_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+    res = {}
+    for name, prec in (("fp64", _lib.FP64), ("mixed", _lib.MIXED)):
+        # warm up on a slice that already fills the grid (allocates the workspace)
+        ctx.solve_device(E_t.data_ptr(), 512, wl.eta, prec, T_t.data_ptr(), L_t.data_ptr(), I_t.data_ptr())
+        torch.cuda.synchronize()
+        res[name] = time_path(ctx, torch, E_t, T_t, L_t, I_t, wl.eta, prec, 1, 0)
+        print(json.dumps({name: {"s": res[name]["s"], "sweep_ms": res[name]["sweep_ms"],
+                                 "dec_ms": res[name]["dec_ms"]}}), file=sys.stderr, flush=True)
+    T64, L64, Tm, Lm = res["fp64"]["T"], res["fp64"]["ldos"], res["mixed"]["T"], res["mixed"]["ldos"]
+    scale = np.maximum(1.0, np.abs(L64).max(axis=2))
+    dT = np.abs(Tm - T64)
+    dn = (np.abs(Lm - L64).max(axis=2) / scale).max(axis=1)
+    idx = np.array([0, n_uni // 2, n_uni + 3, nE - 7])
+    Tref, Lref = oracle.solve_device(dev, wl.E[idx], wl.eta)
+    sref = np.maximum(1.0, np.abs(Lref).max(axis=2))
+    ora = {}
+    for name, T, L in (("fp64", T64, L64), ("mixed", Tm, Lm)):
+        ora[name] = {"max_dT": float(np.abs(T[idx] - Tref).max()),
+                     "max_rel_dn": float((np.abs(L[idx] - Lref).max(axis=2) / sref).max())}
+    mi = res["mixed"]["info"]
+    flops = nE * (dev.N + float(np.mean(res["fp64"]["info"]["dec_iters"]))) * (152.0 / 3.0) * dev.m ** 3
+    paths = {}
+    for name in ("fp64", "mixed"):
+        r = res[name]
+        paths[name] = {"energy_solves_per_s": nE / r["s"], "s_per_grid": r["s"], "sweep_kernel_ms": r["sweep_ms"],
+                       "decimation_kernel_ms": r["dec_ms"], "whole_solve_frac_of_fp64_peak": flops / r["s"] / 78.6e12}
+    line = {
+        "metric": "energy-solves/s (N=400 slabs, m=128, 4096 energies incl. 256 band-edge) mixed vs FP64",
+        "value": paths["mixed"]["energy_solves_per_s"], "unit": "energy-solves/s", "n_gpus": 1, "steps": 1,
+        "warmup": 1, "ms_per_step": 1e3 * res["mixed"]["s"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "cfg2_N400_m128_E4096", "N": dev.N, "m": dev.m, "energies": nE,
+                   "band_edge_energies": len(edges), "eta": wl.eta},
+        "paths": paths,
+        "mixed_vs_fp64": {
+            "uniform_max_dT": float(dT[:n_uni].max()), "band_edge_max_dT": float(dT[n_uni:].max()),
+            "uniform_max_rel_dn": float(dn[:n_uni].max()), "band_edge_max_rel_dn": float(dn[n_uni:].max()),
+            "refine_steps_histogram": np.bincount(mi["refine_steps"], minlength=4).tolist(),
+            "fp64_fallbacks_uniform": int(mi["fell_back_fp64"][:n_uni].sum()),
+            "fp64_fallbacks_band_edge": int(mi["fell_back_fp64"][n_uni:].sum()),
+            "flagged": int((mi["flags"] != 0).sum()),
+        },
+        "vs_oracle_sampled": {"energy_indices": idx.tolist(), **ora},
+    }
+    print(json.dumps(line))
+
+
 def bench_batch(args):
     """64 devices of uneven slab count (50..400) and block size (32..128),
     256 energies each: the batched launch (FP64 and mixed) against the
@@ -258,12 +324,18 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration)")
-    ap.add_argument("--workload", choices=("cfg1", "batch64", "serve"), default="cfg1",
+    ap.add_argument("--workload", choices=("cfg1", "cfg2", "batch64", "serve"), default="cfg1",
                     help="cfg1: the headline N=200, m=64 grid (default); batch64: the uneven 64-device "
                          "batch; serve: the Poisson request loop")
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--serve-precision", choices=("fp64", "mixed"), default="fp64")
     args = ap.parse_args()
+    if args.workload == "cfg2":
+        if args.gpus != 1:
+            print("bench.py: one GPU only", file=sys.stderr)
+            sys.exit(2)
+        bench_cfg2(args)
+        return
     if args.workload == "serve":
         if args.gpus != 1:
             print("bench.py: one GPU only", file=sys.stderr)
