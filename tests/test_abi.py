@@ -61,3 +61,25 @@ def test_null_arguments_rejected_without_device(lib):
     f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                   ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_void_p]
     assert f(None, None, 1, 1, None, 0.0, 0.0, 0.025, None) == _lib.EINVAL
+
+
+def test_charge_helper_matches_its_definition(lib):
+    """qtx_charge is host code: charge_i = sum_k w_k (f_L n^L_ik + f_R n^R_ik)."""
+    f = lib.qtx_charge
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                  ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_void_p]
+    import numpy as np
+    from oracle import integrals as oint
+    rng = np.random.default_rng(3)
+    nE, N = 17, 5
+    E = np.sort(rng.uniform(-1, 1, nE))
+    w = rng.uniform(0, 0.1, nE)
+    ldos = rng.uniform(0, 3, (nE, 2, N))
+    out = np.zeros(N)
+    muL, muR, kT = 0.12, -0.05, 0.03
+    p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    assert f(p(ldos), p(w), nE, N, p(E), muL, muR, kT, p(out)) == _lib.OK
+    ref = (w * oint.fermi(E, muL, kT)) @ ldos[:, 0, :] + (w * oint.fermi(E, muR, kT)) @ ldos[:, 1, :]
+    assert np.abs(out - ref).max() < 1e-13
+    assert f(p(ldos), p(w), nE, N, p(E), muL, muR, 0.0, p(out)) == _lib.EINVAL       # kT must be > 0

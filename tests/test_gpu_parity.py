@@ -120,3 +120,35 @@ def test_empty_grid_and_errors(gpu_lib):
     assert T.shape == (0,) and st == _lib.OK
     with pytest.raises(_lib.QtxError):
         ctx.solve(wl.E, -1.0)
+
+
+def test_decimation_cap_is_flagged_not_hidden(gpu_lib):
+    """With the doubling count capped far below convergence every energy is
+    flagged QTX_FLAG_DEC_NOTCONV and the call returns QTX_ENOTCONV, with
+    outputs still written (finite)."""
+    wl = W.config0()
+    ctx = _ctx(wl.device)
+    ctx.set_option("decimation_max_iters", 2)
+    T, L, info, st = ctx.solve(wl.E[:6], wl.eta, _lib.FP64)
+    assert st == _lib.ENOTCONV
+    assert np.all(info["flags"] & _lib.FLAG_DEC_NOTCONV)
+    assert np.all(info["dec_iters"] == -1)
+    ctx.set_option("decimation_max_iters", 60)
+    T2, L2, info2, st2 = ctx.solve(wl.E[:6], wl.eta, _lib.FP64)
+    assert st2 == _lib.OK and np.all(info2["flags"] == 0)
+
+
+def test_solve_device_on_a_torch_stream(gpu_lib):
+    """qtx_solve_device on torch tensors and torch's current stream gives
+    the host-buffer path's results."""
+    import torch
+    wl = W.config0()
+    ctx = _ctx(wl.device)
+    T, L, _, _ = ctx.solve(wl.E, wl.eta, _lib.FP64)
+    ctx.set_stream(torch.cuda.current_stream().cuda_stream)
+    E_t = torch.tensor(wl.E, dtype=torch.float64, device="cuda")
+    T_t = torch.empty(len(wl.E), dtype=torch.float64, device="cuda")
+    L_t = torch.empty((len(wl.E), 2, wl.device.N), dtype=torch.float64, device="cuda")
+    ctx.solve_device(E_t.data_ptr(), len(wl.E), wl.eta, _lib.FP64, T_t.data_ptr(), L_t.data_ptr())
+    torch.cuda.synchronize()
+    assert np.array_equal(T_t.cpu().numpy(), T) and np.array_equal(L_t.cpu().numpy(), L)
