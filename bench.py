@@ -204,6 +204,40 @@ def bench_cfg2(args):
     print(json.dumps(line))
 
 
+def bench_bands(args):
+    """Band structure of a lead (Bloch eigenproblem per k point) on the GPU:
+    k points per second at m = 64 and m = 128, 8192 k points per call."""
+    import torch
+    from paper_1903_00548_amd import _lib, workloads
+    from oracle import bands as obands
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    out = {}
+    k = np.linspace(-np.pi, np.pi, 8192, endpoint=False)
+    for m in (64, 128):
+        lead = workloads.random_lead(np.random.default_rng(7 + m), m)
+        ctx = _lib.Context(0)
+        ctx.set_lead(_lib.LEFT, lead.H00, lead.H01, lead.S00, lead.S01, 0.0)
+        ctx.bands(_lib.LEFT, k[:512])
+        t = []
+        for _ in range(args.steps):
+            a = time.perf_counter()
+            E = ctx.bands(_lib.LEFT, k)
+            t.append(time.perf_counter() - a)
+        sample = k[::1024]
+        ref = obands.bands(sample, lead.H00, lead.H01, lead.S00, lead.S01)
+        a = time.perf_counter()
+        obands.bands(sample, lead.H00, lead.H01, lead.S00, lead.S01)
+        cpu = len(sample) / (time.perf_counter() - a)
+        out[f"m{m}"] = {"k_points_per_s": len(k) / float(np.median(t)), "s_per_call": float(np.median(t)),
+                        "max_abs_dE_vs_oracle_sampled": float(np.abs(E[::1024] - ref).max()),
+                        "oracle_k_points_per_s_one_core": cpu}
+    print(json.dumps({
+        "metric": "band-structure k points/s (Bloch eigenproblem per k, FP64)", "value": out["m64"]["k_points_per_s"],
+        "unit": "k points/s", "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": 1e3 * out["m64"]["s_per_call"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "bands_lead_k8192", "k_points": len(k)}, "sizes": out}))
+
+
 def bench_batch(args):
     """64 devices of uneven slab count (50..400) and block size (32..128),
     256 energies each: the batched launch (FP64 and mixed) against the
@@ -324,12 +358,15 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration)")
-    ap.add_argument("--workload", choices=("cfg1", "cfg2", "batch64", "serve"), default="cfg1",
+    ap.add_argument("--workload", choices=("cfg1", "cfg2", "batch64", "serve", "bands"), default="cfg1",
                     help="cfg1: the headline N=200, m=64 grid (default); batch64: the uneven 64-device "
                          "batch; serve: the Poisson request loop")
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--serve-precision", choices=("fp64", "mixed"), default="fp64")
     args = ap.parse_args()
+    if args.workload == "bands":
+        bench_bands(args)
+        return
     if args.workload == "cfg2":
         if args.gpus != 1:
             print("bench.py: one GPU only", file=sys.stderr)

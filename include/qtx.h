@@ -185,6 +185,17 @@ qtx_status qtx_self_energy(qtx_ctx* ctx, const double* E, int nE, double eta,
  * or a value out of range (the setting is then unchanged). */
 qtx_status qtx_set_option(qtx_ctx* ctx, const char* name, double value);
 
+/* Band structure of one lead: the eigenvalues of the Bloch problem
+ * H(k) c = E S(k) c with H(k) = H00 + e^{ik} H01 + e^{-ik} H01^H and S(k)
+ * likewise (Bloch's theorem applied to the slab equations of eq.
+ * infinite_system; the band-structure reconstruction of Sec. "Electronic
+ * Structure").  k[nk]: Bloch phases (radians per slab).  E[nk*m] (host,
+ * caller-owned): E[q*m + n] = E_n(k_q) + V_lead, ascending in n, FP64.
+ * One GPU workgroup per k point.  QTX_ESTATE before qtx_set_lead(side),
+ * QTX_ENOTCONV if an energy came out non-finite (S(k) not positive
+ * definite).  Synchronous. */
+qtx_status qtx_bands(qtx_ctx* ctx, qtx_side side, const double* k, int nk, double* E);
+
 /* ---- batching and serving --------------------------------------------- */
 
 /* A problem is a context that shares the parent's device and stream and

@@ -55,6 +55,7 @@ _SIGS = {
     "qtx_kernel_times": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p]),
     "qtx_set_option": (c_int, [c_void_p, c_char_p, c_double]),
     "qtx_sigma_cache_stats": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "qtx_bands": (c_int, [c_void_p, c_int, c_void_p, c_int, c_void_p]),
     "qtx_solve_batch": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_double, c_int,
                                 c_void_p, c_void_p]),
     "qtx_charge": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_double, c_double, c_double,
@@ -196,6 +197,13 @@ class Context:
 
     def set_option(self, name: str, value: float):
         self._check(self.lib.qtx_set_option(self.h, name.encode(), float(value)))
+
+    def bands(self, side, k):
+        """Band energies E_n(k) + V_lead of one lead, shape (len(k), m)."""
+        k = np.ascontiguousarray(k, dtype=np.float64)
+        E = np.empty((len(k), self.m))
+        self._check(self.lib.qtx_bands(self.h, int(side), _ptr(k), len(k), _ptr(E)))
+        return E
 
     def sigma_cache_stats(self):
         """(hits, misses, entries) of the batch self-energy cache."""

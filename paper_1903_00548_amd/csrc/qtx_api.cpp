@@ -1077,6 +1077,31 @@ qtx_status qtx_solve_batch(qtx_ctx* c, int nprob, qtx_ctx* const* probs, const d
   return QTX_OK;
 }
 
+qtx_status qtx_bands(qtx_ctx* c, qtx_side side, const double* k, int nk, double* E) {
+  if (!c) return QTX_EINVAL;
+  if (side != QTX_LEFT && side != QTX_RIGHT) return fail(c, QTX_EINVAL, "side must be QTX_LEFT or QTX_RIGHT");
+  if (nk < 0) return fail(c, QTX_EINVAL, "nk must be >= 0");
+  if (!c->lead_set[side]) return fail(c, QTX_ESTATE, "the lead must be set first");
+  if (nk == 0) return QTX_OK;
+  if (!k || !E) return fail(c, QTX_EINVAL, "k and E must not be NULL");
+  for (int q = 0; q < nk; ++q)
+    if (!std::isfinite(k[q])) return fail(c, QTX_EINVAL, "k must be finite");
+  hipSetDevice(c->device);
+  const int M = c->M, m = c->m;
+  const int grid = std::max(1, std::min(nk, c->num_cu));
+  QTX_HIP(c, c->wE.ensure((size_t)nk * sizeof(double)));
+  QTX_HIP(c, c->wT.ensure((size_t)nk * m * sizeof(double)));
+  if (M > 64) QTX_HIP(c, c->dscr.ensure((size_t)grid * 2 * M * (M + 1) * sizeof(double2)));
+  QTX_HIP(c, hipMemcpyAsync(c->wE.p, k, (size_t)nk * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  QTX_HIP(c, qtx::run_bands(M, c->dlead[side].as<double2>(), m, c->Vlead[side], c->wE.as<double>(), nk,
+                            M > 64 ? c->dscr.as<double2>() : nullptr, grid, c->wT.as<double>(), c->stream));
+  QTX_HIP(c, hipMemcpyAsync(E, c->wT.p, (size_t)nk * m * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  QTX_HIP(c, hipStreamSynchronize(c->stream));
+  for (size_t i = 0; i < (size_t)nk * m; ++i)
+    if (!std::isfinite(E[i])) return fail(c, QTX_ENOTCONV, "non-finite band energy (S(k) not positive definite?)");
+  return QTX_OK;
+}
+
 qtx_status qtx_sigma_cache_stats(qtx_ctx* c, long long* hits, long long* misses, long long* slots) {
   if (!c) return QTX_EINVAL;
   long long used = 0;

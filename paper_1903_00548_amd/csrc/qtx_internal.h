@@ -129,6 +129,12 @@ hipError_t run_decimate(int M, const Prob& P, const BatchDesc& b, const double* 
 hipError_t run_sweep(int M, bool mixed, const Prob& P, const SweepArgs& a, const BatchDesc& b, int grid,
                      hipStream_t st);
 
+// Band energies of one lead (padded blocks, physical size m) at nk Bloch
+// phases: E[q * m + n] = E_n(k_q) + V.  work: grid * 2 M (M + 1) complex
+// doubles when M > 64 (else unused).
+hipError_t run_bands(int M, const double2* lead, int m, double V, const double* k, int nk, double2* work, int grid,
+                     double* E, hipStream_t st);
+
 // elist[0 .. *ecount) = the energies e < nE with redo[e] != 0 (one wave).
 hipError_t run_compact(const int* redo, int nE, int* elist, int* ecount, hipStream_t st);
 

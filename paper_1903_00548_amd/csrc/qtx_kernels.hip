@@ -1075,6 +1075,203 @@ __global__ __launch_bounds__(64) void k_compact(const int* redo, int nE, int* el
   if (lane == 0) *ecount = base;
 }
 
+// ----------------------------------------------------------- band structure
+// Bands of a lead at Bloch phase k: H(k) c = E S(k) c with
+// H(k) = H00 + e^{ik} H01 + e^{-ik} H01^H and S(k) likewise (Bloch's
+// theorem on the slab equations; the band-structure reconstruction of the
+// results section).  One workgroup per k point, on the physical m x m block:
+//   1. A = H(k), B = S(k), each symmetrised (X + X^H) / 2;
+//   2. B = L L^H (right-looking Cholesky, two barriers per column);
+//   3. C = L^-1 A L^-H: A <- L^-1 A, A <- A^H, A <- L^-1 A (every thread
+//      substitutes its own column, no barrier inside), then symmetrised;
+//   4. Householder reduction of C to Hermitian tridiagonal form: step j
+//      maps column j below the diagonal onto -phase |x| e_1 with
+//      H = I - tau v v^H and updates the trailing block by the rank-2 form
+//      C <- C - v w^H - w v^H, p = tau C v, w = p - (tau/2)(v^H p) v;
+//   5. eigenvalue n by bisection on the Sturm count of the real symmetric
+//      tridiagonal (d, |e|), which has the same spectrum; thread n.
+// Output E[k][n] = E_n(k) + V, ascending.  Matrices in LDS for M <= 64,
+// otherwise in the workgroup's slice of the global workspace.
+template <int M>
+__global__ __launch_bounds__(NT, 1) void k_bands(const double2* lead, int m, double V, const double* kpts, int nk,
+                                               double2* work, double* E) {
+  constexpr int S = M + 1;
+  constexpr bool BIG = M > 64;
+  __shared__ cpx<double> lds[BIG ? 1 : 2 * M * S];
+  __shared__ cpx<double> vv[M], pw[M];
+  __shared__ double dd[M], ee[M], red[NWAVE];
+  __shared__ double scal[4];
+  const int t = threadIdx.x;
+  cpx<double>* A;
+  if constexpr (BIG) A = (cpx<double>*)(work + (size_t)blockIdx.x * 2 * M * S);
+  else A = lds;
+  cpx<double>* B = A + M * S;
+  const int MM = M * M;
+  const double2 *H00 = lead, *H01 = lead + MM, *S00 = lead + 2 * MM, *S01 = lead + 3 * MM;
+  for (int q = blockIdx.x; q < nk; q += gridDim.x) {
+    const double kq = kpts[q];
+    const cpx<double> ph = mk<double>(cos(kq), sin(kq));
+    __syncthreads();
+    // 1. Bloch matrices
+    for (int idx = t; idx < m * m; idx += NT) {
+      const int r = idx / m, c = idx - r * m;
+      auto bloch = [&](const double2* X0, const double2* X1, int a, int b) {
+        // X0[a][b] + e^{ik} X1[a][b] + e^{-ik} conj(X1[b][a])
+        const cpx<double> x0 = ldd(X0 + a * M + b), x1 = ldd(X1 + a * M + b), x2 = ldd(X1 + b * M + a);
+        return mk<double>(x0.re + ph.re * x1.re - ph.im * x1.im + ph.re * x2.re - ph.im * x2.im,
+                          x0.im + ph.re * x1.im + ph.im * x1.re - ph.re * x2.im - ph.im * x2.re);
+      };
+      const cpx<double> h1 = bloch(H00, H01, r, c), h2 = bloch(H00, H01, c, r);
+      const cpx<double> s1 = bloch(S00, S01, r, c), s2 = bloch(S00, S01, c, r);
+      A[r * S + c] = mk<double>(0.5 * (h1.re + h2.re), 0.5 * (h1.im - h2.im));
+      B[r * S + c] = mk<double>(0.5 * (s1.re + s2.re), 0.5 * (s1.im - s2.im));
+    }
+    __syncthreads();
+    // 2. Cholesky of B (lower triangle)
+    for (int j = 0; j < m; ++j) {
+      const double dj = sqrt(B[j * S + j].re);
+      for (int i = j + 1 + t; i < m; i += NT) {
+        const cpx<double> v = B[i * S + j];
+        B[i * S + j] = mk<double>(v.re / dj, v.im / dj);
+      }
+      __syncthreads();
+      if (t == 0) B[j * S + j] = mk<double>(dj, 0.0);
+      const int n = m - j - 1;
+      for (int idx = t; idx < n * n; idx += NT) {
+        const int i = j + 1 + idx / n, l = j + 1 + idx % n;
+        if (l > i) continue;
+        const cpx<double> a = B[i * S + j], b = B[l * S + j];
+        cpx<double> x = B[i * S + l];
+        x.re -= a.re * b.re + a.im * b.im;
+        x.im -= a.im * b.re - a.re * b.im;
+        B[i * S + l] = x;
+      }
+      __syncthreads();
+    }
+    // 3. C = L^-1 A L^-H
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int c = t; c < m; c += NT) {
+        for (int i = 0; i < m; ++i) {
+          cpx<double> y = A[i * S + c];
+          for (int k2 = 0; k2 < i; ++k2) y = cfms(y, B[i * S + k2], A[k2 * S + c]);
+          const double li = B[i * S + i].re;
+          A[i * S + c] = mk<double>(y.re / li, y.im / li);
+        }
+      }
+      __syncthreads();
+      // A <- (A + A^H) / 2 after the second pass, A <- A^H after the first
+      for (int idx = t; idx < m * m; idx += NT) {
+        const int r = idx / m, c = idx - r * m;
+        if (c < r) continue;
+        const cpx<double> x = A[r * S + c], y = A[c * S + r];
+        if (pass == 0) {
+          A[r * S + c] = cconj(y);
+          A[c * S + r] = cconj(x);
+        } else {
+          const cpx<double> u = mk<double>(0.5 * (x.re + y.re), 0.5 * (x.im - y.im));
+          A[r * S + c] = u;
+          A[c * S + r] = cconj(u);
+        }
+      }
+      __syncthreads();
+    }
+    // 4. Householder tridiagonalisation
+    for (int j = 0; j + 2 < m; ++j) {
+      const int n = m - j - 1, o = j + 1;            // trailing block rows / columns o..m-1
+      double ss = 0.0;
+      for (int r = t; r < n; r += NT) {
+        const cpx<double> x = A[(o + r) * S + j];
+        ss += x.re * x.re + x.im * x.im;
+      }
+      ss = block_sum(ss, red);
+      const double alpha = sqrt(ss);
+      const cpx<double> x0 = A[o * S + j];
+      const double ax0 = sqrt(x0.re * x0.re + x0.im * x0.im);
+      if (t == 0) {
+        dd[j] = A[j * S + j].re;
+        ee[j] = alpha;
+      }
+      if (alpha == 0.0) continue;                    // uniform: column already reduced
+      const cpx<double> th = ax0 > 0.0 ? mk<double>(x0.re / ax0, x0.im / ax0) : mk<double>(1.0, 0.0);
+      const double tau = 1.0 / (alpha * (alpha + ax0));
+      for (int r = t; r < n; r += NT) {
+        cpx<double> x = A[(o + r) * S + j];
+        if (r == 0) x = mk<double>(x.re + th.re * alpha, x.im + th.im * alpha);
+        vv[r] = x;
+      }
+      __syncthreads();
+      // p = tau C v (rows of the trailing block), then v^H p
+      double kre = 0.0, kim = 0.0;
+      for (int r = t; r < n; r += NT) {
+        cpx<double> acc = mk<double>(0.0, 0.0);
+        for (int c = 0; c < n; ++c) {
+          const cpx<double> a = A[(o + r) * S + o + c], v = vv[c];
+          acc.re += a.re * v.re - a.im * v.im;
+          acc.im += a.re * v.im + a.im * v.re;
+        }
+        acc = mk<double>(tau * acc.re, tau * acc.im);
+        pw[r] = acc;
+        const cpx<double> v = vv[r];
+        kre += v.re * acc.re + v.im * acc.im;        // conj(v) p
+        kim += v.re * acc.im - v.im * acc.re;
+      }
+      kre = block_sum(kre, red);
+      kim = block_sum(kim, red);
+      const double hre = 0.5 * tau * kre, him = 0.5 * tau * kim;
+      for (int r = t; r < n; r += NT) {
+        const cpx<double> v = vv[r], p = pw[r];
+        pw[r] = mk<double>(p.re - (hre * v.re - him * v.im), p.im - (hre * v.im + him * v.re));
+      }
+      __syncthreads();
+      for (int idx = t; idx < n * n; idx += NT) {
+        const int r = idx / n, c = idx - r * n;
+        const cpx<double> vr = vv[r], vc = vv[c], wr = pw[r], wc = pw[c];
+        cpx<double> x = A[(o + r) * S + o + c];
+        x.re -= vr.re * wc.re + vr.im * wc.im + wr.re * vc.re + wr.im * vc.im;
+        x.im -= vr.im * wc.re - vr.re * wc.im + wr.im * vc.re - wr.re * vc.im;
+        A[(o + r) * S + o + c] = x;
+      }
+      __syncthreads();
+    }
+    if (t == 0) {
+      if (m >= 2) {
+        const cpx<double> x = A[(m - 1) * S + m - 2];
+        dd[m - 2] = A[(m - 2) * S + m - 2].re;
+        ee[m - 2] = sqrt(x.re * x.re + x.im * x.im);
+      }
+      dd[m - 1] = A[(m - 1) * S + m - 1].re;
+      ee[m - 1] = 0.0;
+      double lo = dd[0], hi = dd[0];
+      for (int i = 0; i < m; ++i) {
+        const double r = (i > 0 ? ee[i - 1] : 0.0) + ee[i];
+        lo = fmin(lo, dd[i] - r);
+        hi = fmax(hi, dd[i] + r);
+      }
+      scal[0] = lo - 1e-12 * (fabs(lo) + 1.0);
+      scal[1] = hi + 1e-12 * (fabs(hi) + 1.0);
+    }
+    __syncthreads();
+    // 5. bisection: eigenvalue n is the smallest x with #{eigenvalues < x} > n
+    for (int n = t; n < m; n += NT) {
+      double lo = scal[0], hi = scal[1];
+      for (int it = 0; it < 100 && hi - lo > 4e-16 * fmax(fabs(lo), fabs(hi)); ++it) {
+        const double x = 0.5 * (lo + hi);
+        int cnt = 0;
+        double qv = dd[0] - x;
+        if (qv < 0.0) ++cnt;
+        for (int i = 1; i < m; ++i) {
+          const double den = qv != 0.0 ? qv : 1e-300;
+          qv = dd[i] - x - ee[i - 1] * ee[i - 1] / den;
+          if (qv < 0.0) ++cnt;
+        }
+        if (cnt > n) hi = x;
+        else lo = x;
+      }
+      E[(size_t)q * m + n] = 0.5 * (lo + hi) + V;
+    }
+  }
+}
+
 // ------------------------------------------------------------- launchers
 template <int M>
 hipError_t launch_decimate(const Prob& P, const BatchDesc& b, const double* E, int nE, double eta, int sides,
@@ -1123,6 +1320,23 @@ hipError_t run_sweep(int M, bool mixed, const Prob& P, const SweepArgs& a, const
     default: return hipErrorInvalidValue;
   }
 #undef QTX_SWEEP
+}
+
+hipError_t run_bands(int M, const double2* lead, int m, double V, const double* k, int nk, double2* work, int grid,
+                     double* E, hipStream_t st) {
+#define QTX_BANDS(MM) \
+  hipLaunchKernelGGL(k_bands<MM>, dim3(grid), dim3(NT), 0, st, lead, m, V, k, nk, work, E); \
+  return hipGetLastError()
+  switch (M) {
+    case 16: QTX_BANDS(16);
+    case 32: QTX_BANDS(32);
+    case 48: QTX_BANDS(48);
+    case 64: QTX_BANDS(64);
+    case 96: QTX_BANDS(96);
+    case 128: QTX_BANDS(128);
+    default: return hipErrorInvalidValue;
+  }
+#undef QTX_BANDS
 }
 
 hipError_t run_compact(const int* redo, int nE, int* elist, int* ecount, hipStream_t st) {

@@ -14,6 +14,14 @@ def pytest_configure(config):
 
 @pytest.fixture(scope="session")
 def gpu_lib():
-    """The HIP library, loaded once per session; fails loudly if absent."""
+    """The HIP library, loaded once per session; fails loudly if absent.
+
+    PyTorch is initialised first, as in the benchmark and in production
+    use (PyTorch owns device memory and streams): the library then binds
+    to the HIP runtime that torch loaded, and torch tensors and streams
+    can be handed to it."""
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.init()
     from paper_1903_00548_amd import _lib
     return _lib.load()

@@ -229,3 +229,19 @@ def test_potential_weights_linear_fe():
     kink[2] = 1.0
     Vd, Vu = oracle.potential_weights(kink, 0.0, 0.0, POT_LINEAR_FE)
     assert np.allclose(Vd, [0, 0.125, 0.75, 0.125, 0]) and np.allclose(Vu, [0, 0.5, 0.5, 0])
+
+
+def test_bands_closed_form_decoupled_with_overlap():
+    """Decoupled bands with a diagonal overlap coupling: each band is
+    E_n(k) = (e_n - 2 t_n cos k) / (1 + 2 s_n cos k) (plus the lead
+    potential), sorted at every k."""
+    e = np.array([-1.0, 0.3, 0.7, 2.0])
+    tt = np.array([0.5, 0.2, 0.9, 0.4])
+    ss = np.array([0.05, -0.02, 0.03, 0.0])
+    H00, H01 = np.diag(e).astype(complex), np.diag(-tt).astype(complex)
+    S00, S01 = np.eye(4, dtype=complex), np.diag(ss).astype(complex)
+    k = np.linspace(-np.pi, np.pi, 37)
+    got = bands.bands(k, H00, H01, S00, S01, V=0.25)
+    c = np.cos(k)[:, None]
+    ref = np.sort((e - 2 * tt * c) / (1 + 2 * ss * c), axis=1) + 0.25
+    assert np.abs(got - ref).max() < 1e-13
