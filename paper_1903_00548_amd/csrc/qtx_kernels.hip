@@ -196,11 +196,14 @@ __device__ __forceinline__ void gj_update(cpx<R>* mat, int S, int k, const cpx<R
 // gj_scratch<M>() elements.  The result is the inverse up to the pivot order:
 // A^-1[j][c] = mat[piv[j]][pinv[c]], so A^-1 B = P (mat (Q B)) with
 // (Q B)[k] = B[piv[k]] and row r of the product landing in row pinv[r].
-// Ends with a barrier.
+// Ends with a barrier.  The elimination is the latency-bound critical path
+// of its workgroup, so its waves raise their issue priority over the other
+// workgroup resident on the CU (which is then mostly in MFMA phases).
 template <typename R, int M>
 __device__ __forceinline__ void gj_inverse(cpx<R>* mat, int S, cpx<R>* Y, BGJ<R, M>& sc) {
-  constexpr int NP = M / 16, MT = M / 16;
-  const int t = threadIdx.x, w = t >> 6;
+  constexpr int NP = M / 16;
+  const int t = threadIdx.x;
+  __builtin_amdgcn_s_setprio(2);
   if (t < M) sc.ppanel[t] = -1;
   __syncthreads();
   for (int k = 0; k < NP; ++k) {
@@ -219,6 +222,7 @@ __device__ __forceinline__ void gj_inverse(cpx<R>* mat, int S, cpx<R>* Y, BGJ<R,
   }
   if (t < M) sc.pinv[sc.piv[t]] = t;
   __syncthreads();
+  __builtin_amdgcn_s_setprio(0);
 }
 
 // ------------------------------------------------ broadening factorisation
