@@ -175,8 +175,9 @@ qtx_status qtx_self_energy(qtx_ctx* ctx, const double* E, int nE, double eta,
  *                           self-energies, broadening factors and signs of
  *                           every (lead blocks, E - V_lead) it has solved, up
  *                           to this many bytes of device memory per block
- *                           size, and reuses them (least recently used are
- *                           replaced); 0 disables the cache.  Changing eta
+ *                           size, and reuses them (when full, entries are
+ *                           replaced oldest first, never one the current
+ *                           call uses); 0 disables the cache.  Changing eta
  *                           or a decimation option empties it;
  *   "use_graph"             0 or 1        1      qtx_solve_batch captures its
  *                           launch sequence in a HIP graph and replays it

@@ -80,6 +80,7 @@ struct qtx_ctx {
     std::unordered_map<unsigned long long, int> index;   // key hash -> slot
     std::vector<std::pair<uint64_t, uint64_t>> key;       // per slot
     std::vector<long long> tick;                          // last call that used the slot, -1 free
+    int hand = 0;                                         // next slot the replacement scan looks at
   };
   std::map<int, SigCache> sigcache;
   double sigcache_bytes = 16.0 * (1ull << 30);
@@ -824,8 +825,9 @@ qtx_status qtx_solve_batch(qtx_ctx* c, int nprob, qtx_ctx* const* probs, const d
   if (nitems == 0) return QTX_OK;
 
   // self-energy cache: both contacts of every item look up (lead content,
-  // shifted energy E - V); misses become decimation jobs into free or
-  // least recently used slots that this call does not use
+  // shifted energy E - V); misses become decimation jobs into slots taken
+  // in round-robin order (clock hand kept per cache), skipping the slots
+  // this call uses
   bool cached = c->sigcache_bytes > 0;
   std::vector<int> slot2;
   std::vector<int> cjob_slot;
@@ -870,6 +872,7 @@ qtx_status qtx_solve_batch(qtx_ctx* c, int nprob, qtx_ctx* const* probs, const d
         sc.tick.assign(cap, -1);
         sc.cap = cap;
         sc.M = M;
+        sc.hand = 0;
       }
       QTX_HIP(c, sc.sig.ensure((size_t)cap * 2 * MM * sizeof(double2)));
       QTX_HIP(c, sc.wf.ensure((size_t)cap * 2 * MM * sizeof(double2)));
@@ -877,7 +880,9 @@ qtx_status qtx_solve_batch(qtx_ctx* c, int nprob, qtx_ctx* const* probs, const d
       QTX_HIP(c, sc.iters.ensure((size_t)cap * 2 * sizeof(int)));
       QTX_HIP(c, sc.nheavy.ensure((size_t)cap * 2 * sizeof(int)));
       DecGroup g{M, (int)cjob_slot.size(), 0};
-      int hand = 0, scanned = 0;
+      int& hand = sc.hand;
+      if (hand >= cap) hand = 0;
+      int scanned = 0;
       for (; i < nitems && probs[item_prob[i]]->M == M; ++i) {
         const qtx_ctx* q = probs[item_prob[i]];
         for (int side = 0; side < 2 && !overflow; ++side) {

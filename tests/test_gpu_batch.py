@@ -160,3 +160,23 @@ def test_sigma_cache_reuse_and_equality(gpu_lib):
     for k in range(2):
         assert np.array_equal(Ts3[k], Tr[k]) and np.array_equal(Ls3[k], Lr[k])
     assert small.sigma_cache_stats()[2] == 0
+
+
+def test_sigma_cache_replacement_across_calls(gpu_lib):
+    """A 16-entry cache over calls of 10 new contacts each: the second call
+    replaces entries of the first (never its own), a repeat of the second
+    call finds all of its entries, and every result equals the uncached
+    solve."""
+    lead = W.random_lead(np.random.default_rng(43), 12)
+    dev = W.Device(N=5, m=12, lead_L=lead, lead_R=lead, V=np.zeros(5), pot_mode=W.POT_DIAG)
+    ctx = _lib.Context(0)
+    ctx.set_option("sigma_cache_bytes", 1.0)            # the minimum: 16 entries
+    p = _lib.fill(ctx.problem(), dev)
+    ref = _lib.context_for(dev, 0)
+    grids = [np.linspace(-1.0, 1.0, 10), np.linspace(-0.9, 1.1, 10)]
+    for call, E in enumerate(grids + grids[1:]):
+        Ts, Ls, _ = _lib.solve_batch(ctx, [p], [E], ETA)
+        Tr, Lr, _, _ = ref.solve(E, ETA, _lib.FP64)
+        assert np.array_equal(Ts[0], Tr) and np.array_equal(Ls[0], Lr), call
+    hits, misses, slots = ctx.sigma_cache_stats()
+    assert (hits, misses) == (10, 20) and slots == 16
