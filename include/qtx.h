@@ -169,7 +169,9 @@ qtx_status qtx_self_energy(qtx_ctx* ctx, const double* E, int nE, double eta,
  *                           this times the largest are refined (whole tiles
  *                           of 16 columns, at least one tile per contact);
  *                           0 refines every column;
- *   "workgroups_per_cu"     1 or 2        2      resident energies per CU;
+ *   "workgroups_per_cu"     [1, 4]        2      resident energies per CU for
+ *                           blocks up to 64 (blocks above 64 use one);
+ *                           setting it discards autotuned values;
  *   "energies_per_launch"   [1, 2^20]     4096   energies per launch chunk;
  *   "sigma_cache_bytes"     [0, 1e13]     16 GiB qtx_solve_batch keeps the lead
  *                           self-energies, broadening factors and signs of
@@ -215,6 +217,18 @@ qtx_status qtx_problem_create(qtx_ctx* parent, qtx_ctx** problem);
 qtx_status qtx_solve_batch(qtx_ctx* ctx, int nprob, qtx_ctx* const* probs,
                            const double* const* E, const int* nE, double eta,
                            qtx_precision prec, double* const* T, double* const* ldos);
+
+/* Autotuning of the launch shape for the context's problem: for every
+ * number of resident workgroups per CU (one energy each) from 1 to 4 that
+ * the kernels' register and LDS use allow at this block size, time the
+ * solve of the sample energies E[nE] (host, eta, prec) and keep the
+ * fastest.  The choice is stored for this block size and precision in the
+ * context (and in its parent, for batched solves) and used by later
+ * solves.  *wg_out (or NULL) receives it; times_ms[4] (or NULL) the
+ * measured milliseconds per candidate (0 where a count was not possible).
+ * Takes about twice the solve time of the sample per candidate. */
+qtx_status qtx_autotune(qtx_ctx* ctx, const double* E, int nE, double eta, qtx_precision prec,
+                        int* wg_out, double* times_ms);
 
 /* Self-energy cache of qtx_solve_batch (option "sigma_cache_bytes"):
  * contact lookups that found their entry (hits) and that had to run the

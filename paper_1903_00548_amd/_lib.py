@@ -56,6 +56,7 @@ _SIGS = {
     "qtx_set_option": (c_int, [c_void_p, c_char_p, c_double]),
     "qtx_sigma_cache_stats": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "qtx_bands": (c_int, [c_void_p, c_int, c_void_p, c_int, c_void_p]),
+    "qtx_autotune": (c_int, [c_void_p, c_void_p, c_int, c_double, c_int, c_void_p, c_void_p]),
     "qtx_solve_batch": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_double, c_int,
                                 c_void_p, c_void_p]),
     "qtx_charge": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_double, c_double, c_double,
@@ -197,6 +198,16 @@ class Context:
 
     def set_option(self, name: str, value: float):
         self._check(self.lib.qtx_set_option(self.h, name.encode(), float(value)))
+
+    def autotune(self, E, eta, precision=FP64):
+        """Pick the workgroups per CU for this problem from timed solves of
+        the sample energies; returns (chosen, times_ms[4])."""
+        E = np.ascontiguousarray(E, dtype=np.float64)
+        wg = c_int()
+        times = np.zeros(4)
+        self._check(self.lib.qtx_autotune(self.h, _ptr(E), len(E), float(eta), int(precision), ctypes.byref(wg),
+                                          _ptr(times)))
+        return wg.value, times
 
     def bands(self, side, k):
         """Band energies E_n(k) + V_lead of one lead, shape (len(k), m)."""

@@ -109,6 +109,7 @@ struct qtx_ctx {
   double refine_tol = 1e-12;      // stop when ||r|| <= refine_tol ||b||
   int refine_max = 3;             // corrections per energy before the FP64 fallback
   double heavy_tol = 1e-8;        // refine columns with pivot >= heavy_tol * largest
+  std::map<int, int> tuned_wg[2];  // autotuned workgroups per CU by block size (FP64, mixed)
 };
 
 namespace {
@@ -179,8 +180,14 @@ qtx_status check_ready(qtx_ctx* c) {
   return QTX_OK;
 }
 
-// Resident workgroups per CU: blocks above 64 take a whole CU.
-int wgs_per_cu(const qtx_ctx* c) { return c->M > 64 ? 1 : c->wg_per_cu; }
+// Resident workgroups per CU for block size M: the autotuned value if there
+// is one, else blocks above 64 take a whole CU and smaller ones the
+// configured count (two by default).
+int wgs_per_cu(const qtx_ctx* c, int M, bool mixed) {
+  auto it = c->tuned_wg[mixed].find(M);
+  if (it != c->tuned_wg[mixed].end()) return it->second;
+  return M > 64 ? 1 : c->wg_per_cu;
+}
 
 qtx::Prob make_prob(const qtx_ctx* c) {
   qtx::Prob P;
@@ -206,11 +213,11 @@ qtx::Prob make_prob(const qtx_ctx* c) {
 }
 
 // decimation for energies E_dev[0..nE) into ctx->sig / wf / sgn / iters
-qtx_status stage_decimate(qtx_ctx* c, const double* E_dev, int nE, double eta) {
+qtx_status stage_decimate(qtx_ctx* c, const double* E_dev, int nE, double eta, bool mixed) {
   const int M = c->M;
   const size_t MM = (size_t)M * M;
   const int sides = leads_identical(c) ? 1 : 2;
-  const int grid = std::max(1, std::min(nE * sides, c->num_cu * wgs_per_cu(c)));
+  const int grid = std::max(1, std::min(nE * sides, c->num_cu * wgs_per_cu(c, M, mixed)));
   QTX_HIP(c, c->sig.ensure((size_t)nE * 2 * MM * sizeof(double2)));
   QTX_HIP(c, c->wf.ensure((size_t)nE * 2 * MM * sizeof(double2)));
   QTX_HIP(c, c->sgn.ensure((size_t)nE * 2 * M * sizeof(double)));
@@ -238,9 +245,9 @@ qtx_status solve_device_core(qtx_ctx* c, const double* E_dev, int nE, double eta
   const int M = c->M, N = c->N;
   for (int e0 = 0; e0 < nE; e0 += c->chunk) {
     const int ne = std::min(c->chunk, nE - e0);
-    s = stage_decimate(c, E_dev + e0, ne, eta);
+    s = stage_decimate(c, E_dev + e0, ne, eta, mixed);
     if (s != QTX_OK) return s;
-    const int grid = std::max(1, std::min(ne, c->num_cu * wgs_per_cu(c)));
+    const int grid = std::max(1, std::min(ne, c->num_cu * wgs_per_cu(c, M, mixed)));
     const size_t wsb = qtx::sweep_ws_bytes(N, M, mixed);
     QTX_HIP(c, c->sws.ensure((size_t)grid * wsb));
     QTX_HIP(c, c->part.ensure((size_t)grid * 4 * 2 * N * (mixed ? 2 : 1) * sizeof(double)));
@@ -505,7 +512,7 @@ qtx_status qtx_self_energy(qtx_ctx* c, const double* E, int nE, double eta, qtx_
   const size_t MM = (size_t)M * M;
   QTX_HIP(c, c->wE.ensure((size_t)nE * sizeof(double)));
   QTX_HIP(c, hipMemcpyAsync(c->wE.p, E, (size_t)nE * sizeof(double), hipMemcpyHostToDevice, c->stream));
-  qtx_status s = stage_decimate(c, c->wE.as<double>(), nE, eta);
+  qtx_status s = stage_decimate(c, c->wE.as<double>(), nE, eta, false);
   if (s != QTX_OK) return s;
   std::vector<double2> hs((size_t)nE * 2 * MM), hw;
   std::vector<double> hg;
@@ -588,8 +595,10 @@ qtx_status qtx_set_option(qtx_ctx* c, const char* name, double value) {
     if (!(value >= 0.0 && value <= 1.0)) return fail(c, QTX_EINVAL, "refine_weight_tol must be in [0, 1]");
     c->heavy_tol = value;
   } else if (n == "workgroups_per_cu") {
-    if (!integral || value < 1 || value > 2) return fail(c, QTX_EINVAL, "workgroups_per_cu must be 1 or 2");
+    if (!integral || value < 1 || value > 4) return fail(c, QTX_EINVAL, "workgroups_per_cu must be in [1, 4]");
     c->wg_per_cu = (int)value;
+    c->tuned_wg[0].clear();
+    c->tuned_wg[1].clear();
   } else if (n == "sigma_cache_bytes") {
     if (!(value >= 0.0 && value <= 1e13)) return fail(c, QTX_EINVAL, "sigma_cache_bytes must be in [0, 1e13]");
     c->sigcache_bytes = value;
@@ -621,6 +630,8 @@ qtx_status qtx_problem_create(qtx_ctx* parent, qtx_ctx** problem) {
   c->dec_maxit = parent->dec_maxit;
   c->chunk = parent->chunk;
   c->wg_per_cu = parent->wg_per_cu;
+  c->tuned_wg[0] = parent->tuned_wg[0];
+  c->tuned_wg[1] = parent->tuned_wg[1];
   c->refine_tol = parent->refine_tol;
   c->refine_max = parent->refine_max;
   c->heavy_tol = parent->heavy_tol;
@@ -663,7 +674,7 @@ qtx_status enqueue_batch(qtx_ctx* c, const std::vector<BatchChunk>& chunks, cons
   for (const DecGroup& g : groups) {
     if (g.njobs == 0) continue;
     qtx_ctx::SigCache& sc = c->sigcache[g.M];
-    const int wg = g.M > 64 ? 1 : c->wg_per_cu;
+    const int wg = wgs_per_cu(c, g.M, mixed);
     qtx::BatchDesc b{};
     b.probs = c->bprobs.as<qtx::Prob>();
     b.job_item = c->bjob_item.as<int>() + g.job0;
@@ -680,7 +691,7 @@ qtx_status enqueue_batch(qtx_ctx* c, const std::vector<BatchChunk>& chunks, cons
   for (const BatchChunk& k : chunks) {
     const int M = k.M;
     const bool big = M > 64;
-    const int wg = big ? 1 : c->wg_per_cu;
+    const int wg = wgs_per_cu(c, M, mixed);
     qtx::BatchDesc b{};
     b.probs = c->bprobs.as<qtx::Prob>();
     b.item_prob = c->bitem_prob.as<int>() + k.item0;
@@ -944,13 +955,13 @@ qtx_status qtx_solve_batch(qtx_ctx* c, int nprob, qtx_ctx* const* probs, const d
   // buffer sizes (all allocations before any capture)
   size_t sig_b = 0, dscr_b = 0, sws_b = 0, part_b = 0, per_b = 0;
   for (const DecGroup& g : groups) {
-    const int wg = g.M > 64 ? 1 : c->wg_per_cu;
+    const int wg = wgs_per_cu(c, g.M, mixed);
     const size_t gdec = std::max(1, std::min(g.njobs, c->num_cu * wg));
     dscr_b = std::max(dscr_b, gdec * qtx::dec_ws_elems(g.M) * sizeof(double2));
   }
   for (const BatchChunk& k : chunks) {
     const size_t MM = (size_t)k.M * k.M;
-    const int wg = k.M > 64 ? 1 : c->wg_per_cu;
+    const int wg = wgs_per_cu(c, k.M, mixed);
     const size_t gdec = std::max(1, std::min(k.njobs, c->num_cu * wg));
     const size_t grid = std::max(1, std::min(k.nitems, c->num_cu * wg));
     sig_b = std::max(sig_b, (size_t)k.nitems * 2 * MM * sizeof(double2));
@@ -1015,6 +1026,7 @@ qtx_status qtx_solve_batch(qtx_ctx* c, int nprob, qtx_ctx* const* probs, const d
   std::vector<long long> sig;
   sig.push_back(mixed);
   sig.push_back(c->wg_per_cu);
+  for (const BatchChunk& k : chunks) sig.push_back(wgs_per_cu(c, k.M, mixed));
   sig.push_back(c->chunk);
   sig.push_back(c->refine_max);
   long long eb;
@@ -1079,6 +1091,74 @@ qtx_status qtx_solve_batch(qtx_ctx* c, int nprob, qtx_ctx* const* probs, const d
     flagged |= hinfo[i].flags != 0;
   }
   if (flagged) return fail(c, QTX_ENOTCONV, "some energies were flagged");
+  return QTX_OK;
+}
+
+qtx_status qtx_autotune(qtx_ctx* c, const double* E, int nE, double eta, qtx_precision prec, int* wg_out,
+                        double* times_ms) {
+  if (!c) return QTX_EINVAL;
+  if (prec != QTX_FP64 && prec != QTX_MIXED) return fail(c, QTX_EINVAL, "precision must be QTX_FP64 or QTX_MIXED");
+  if (nE < 1 || !E) return fail(c, QTX_EINVAL, "need at least one sample energy");
+  if (!(eta >= 0.0)) return fail(c, QTX_EINVAL, "eta must be >= 0");
+  for (int e = 0; e < nE; ++e)
+    if (!std::isfinite(E[e])) return fail(c, QTX_EINVAL, "energies must be finite");
+  qtx_status s = check_ready(c);
+  if (s != QTX_OK) return s;
+  hipSetDevice(c->device);
+  const bool mixed = prec == QTX_MIXED;
+  const int M = c->M, N = c->N;
+  int occ_sweep = 0, occ_dec = 0;
+  QTX_HIP(c, qtx::max_resident(M, mixed, &occ_sweep, &occ_dec));
+  // mixed sweeps of blocks above 64 keep one workgroup per CU: their
+  // workspace (about 0.5 GB per workgroup at N = 400) bounds the count
+  const int cand = std::max(1, std::min(M > 64 && mixed ? 1 : 4, occ_sweep));
+  QTX_HIP(c, c->wE.ensure((size_t)nE * sizeof(double)));
+  QTX_HIP(c, c->wT.ensure((size_t)nE * sizeof(double)));
+  QTX_HIP(c, c->wldos.ensure((size_t)nE * 2 * N * sizeof(double)));
+  QTX_HIP(c, hipMemcpyAsync(c->wE.p, E, (size_t)nE * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  hipEvent_t e0, e1;
+  QTX_HIP(c, hipEventCreate(&e0));
+  QTX_HIP(c, hipEventCreate(&e1));
+  const bool timing = c->timing;
+  c->timing = false;
+  double best = 1e300;
+  int best_wg = 1;
+  qtx_status st = QTX_OK;
+  for (int wg = 1; wg <= 4; ++wg) {
+    if (times_ms) times_ms[wg - 1] = 0.0;
+    if (wg > cand) continue;
+    c->tuned_wg[mixed][M] = wg;
+    // once to allocate, once timed
+    for (int rep = 0; rep < 2 && st == QTX_OK; ++rep) {
+      if (rep == 1 && hipEventRecord(e0, c->stream) != hipSuccess) st = fail(c, QTX_EDEVICE, "hipEventRecord");
+      if (st == QTX_OK)
+        st = solve_device_core(c, c->wE.as<double>(), nE, eta, prec, c->wT.as<double>(), c->wldos.as<double>(),
+                               nullptr);
+      if (st == QTX_OK && rep == 1 && hipEventRecord(e1, c->stream) != hipSuccess)
+        st = fail(c, QTX_EDEVICE, "hipEventRecord");
+    }
+    if (st != QTX_OK) break;
+    float ms = 0.0f;
+    if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      st = fail(c, QTX_EDEVICE, "event timing failed");
+      break;
+    }
+    if (times_ms) times_ms[wg - 1] = ms;
+    if (ms < best) {
+      best = ms;
+      best_wg = wg;
+    }
+  }
+  c->timing = timing;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (st != QTX_OK) {
+    c->tuned_wg[mixed].erase(M);
+    return st;
+  }
+  c->tuned_wg[mixed][M] = best_wg;
+  if (c->parent) c->parent->tuned_wg[mixed][M] = best_wg;
+  if (wg_out) *wg_out = best_wg;
   return QTX_OK;
 }
 

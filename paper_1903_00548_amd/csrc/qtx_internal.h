@@ -135,6 +135,10 @@ hipError_t run_sweep(int M, bool mixed, const Prob& P, const SweepArgs& a, const
 hipError_t run_bands(int M, const double2* lead, int m, double V, const double* k, int nk, double2* work, int grid,
                      double* E, hipStream_t st);
 
+// Workgroups of the sweep (FP64 or mixed) and of the decimation that one CU
+// can hold at block size M, from the kernels' register and LDS use.
+hipError_t max_resident(int M, bool mixed, int* sweep_wgs, int* dec_wgs);
+
 // elist[0 .. *ecount) = the energies e < nE with redo[e] != 0 (one wave).
 hipError_t run_compact(const int* redo, int nE, int* elist, int* ecount, hipStream_t st);
 

@@ -1343,6 +1343,29 @@ hipError_t run_bands(int M, const double2* lead, int m, double V, const double* 
 #undef QTX_BANDS
 }
 
+hipError_t max_resident(int M, bool mixed, int* sweep_wgs, int* dec_wgs) {
+  int a = 0, b = 0;
+  hipError_t e = hipSuccess;
+#define QTX_OCC(MM)                                                                                              \
+  e = mixed ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_sweep<float, MM, true>, NT, 0)               \
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_sweep<double, MM, false>, NT, 0);            \
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_decimate<MM>, NT, 0);           \
+  break
+  switch (M) {
+    case 16: QTX_OCC(16);
+    case 32: QTX_OCC(32);
+    case 48: QTX_OCC(48);
+    case 64: QTX_OCC(64);
+    case 96: QTX_OCC(96);
+    case 128: QTX_OCC(128);
+    default: return hipErrorInvalidValue;
+  }
+#undef QTX_OCC
+  *sweep_wgs = a;
+  *dec_wgs = b;
+  return e;
+}
+
 hipError_t run_compact(const int* redo, int nE, int* elist, int* ecount, hipStream_t st) {
   hipLaunchKernelGGL(k_compact, dim3(1), dim3(64), 0, st, redo, nE, elist, ecount);
   return hipGetLastError();

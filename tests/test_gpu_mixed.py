@@ -111,7 +111,7 @@ def test_mixed_refine_every_column(gpu_lib):
 def test_set_option_validation(gpu_lib):
     ctx = _lib.Context(0)
     for name, bad in (("refine_tol", 0.0), ("refine_tol", 2.0), ("refine_max_steps", 1.5),
-                      ("refine_max_steps", -1), ("refine_weight_tol", -0.1), ("workgroups_per_cu", 3),
+                      ("refine_max_steps", -1), ("refine_weight_tol", -0.1), ("workgroups_per_cu", 5),
                       ("energies_per_launch", 0), ("decimation_max_iters", 0), ("no_such_option", 1.0)):
         with pytest.raises(_lib.QtxError) as ei:
             ctx.set_option(name, bad)
