@@ -279,6 +279,20 @@ def bench_batch(args):
         c.close()
     per_m.clear()
 
+    # launch shape per block size: autotuned on the first device of each size,
+    # with as many sample energies as the batch holds items of that size
+    # (capped at 4096), so that the sample fills the GPU like the batch does
+    tuned = {}
+    items = {}
+    for d, E in zip(wl.devices, wl.energies):
+        items[d.m] = items.get(d.m, 0) + len(E)
+    for d, E, pr in zip(wl.devices, wl.energies, probs):
+        if d.m not in tuned:
+            sample = np.resize(E, min(items[d.m], 4096))
+            tuned[d.m] = pr.autotune(sample, wl.eta, _lib.FP64)[0]
+    out["autotuned_workgroups_per_cu"] = {str(k): v for k, v in sorted(tuned.items())}
+    print(json.dumps({"autotuned": out["autotuned_workgroups_per_cu"]}), file=sys.stderr, flush=True)
+
     for name, prec, steps, warmup in (("batch_fp64", _lib.FP64, args.steps, 1),
                                       ("batch_mixed", _lib.MIXED, 1, 0)):
         (Ts, _, st), t = timed(lambda: _lib.solve_batch(ctx, probs, wl.energies, wl.eta, prec), steps, warmup)
