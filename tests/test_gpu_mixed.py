@@ -132,3 +132,21 @@ def test_mixed_chunked_launches_match_single_launch(gpu_lib):
     ctx.set_option("workgroups_per_cu", 1)
     T2, L2, _, _ = ctx.solve(wl.E, wl.eta, _lib.MIXED)
     assert np.array_equal(T1, T2) and np.array_equal(L1, L2)
+
+
+def test_mixed_band_edge_energies_m128(gpu_lib):
+    """Mixed path at N = 400, m = 128 on 64 energies within 1 meV of the lead
+    band edges (the hardest-conditioned set): every energy within 1e-8 of
+    the FP64 path, two of them against the oracle."""
+    import os
+    edges = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "cfg2_band_edge_energies.txt"))
+    wl = W.config2()
+    dev = wl.device
+    E = edges[::4]
+    ctx = _lib.context_for(dev, 0)
+    T64, L64, _, _ = ctx.solve(E, wl.eta, _lib.FP64)
+    T, L, info, st = ctx.solve(E, wl.eta, _lib.MIXED)
+    assert st == _lib.OK
+    _check(T, L, T64, L64, "band-edge mixed vs fp64", tolT=TOL_T - 1e-10)
+    Tref, Lref = oracle.solve_device(dev, E[[3, 40]], wl.eta)
+    _check(T[[3, 40]], L[[3, 40]], Tref, Lref, "band-edge mixed vs oracle")

@@ -152,3 +152,20 @@ def test_solve_device_on_a_torch_stream(gpu_lib):
     ctx.solve_device(E_t.data_ptr(), len(wl.E), wl.eta, _lib.FP64, T_t.data_ptr(), L_t.data_ptr())
     torch.cuda.synchronize()
     assert np.array_equal(T_t.cpu().numpy(), T) and np.array_equal(L_t.cpu().numpy(), L)
+
+
+def test_cfg2_full_size_sampled(gpu_lib):
+    """N = 400, m = 128 with its 4096 energies (band-edge set included) in one
+    FP64 call, as the benchmark runs it: every output finite, four energies
+    (two uniform, two within 1 meV of a band edge) against the oracle."""
+    import os
+    edges = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "cfg2_band_edge_energies.txt"))
+    wl = W.config2(band_edge_energies=edges)
+    dev = wl.device
+    ctx = _ctx(dev)
+    T, L, info, st = ctx.solve(wl.E, wl.eta, _lib.FP64)
+    assert st == _lib.OK and np.all(np.isfinite(T)) and np.all(np.isfinite(L))
+    n_uni = len(wl.E) - len(edges)
+    idx = np.array([7, n_uni - 100, n_uni + 11, len(wl.E) - 2])
+    Tref, Lref = oracle.solve_device(dev, wl.E[idx], wl.eta)
+    _check(T[idx], L[idx], Tref, Lref, label="cfg2")
