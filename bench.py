@@ -238,6 +238,100 @@ def bench_bands(args):
         "config": {"workload": "bands_lead_k8192", "k_points": len(k)}, "sizes": out}))
 
 
+def dm_weights(E, muL=0.0, muR=-0.1, kT=0.025):
+    """Quadrature weights h/3 (1, 4, 2, ..., 4, 1) (composite Simpson on the
+    first 2k+1 points, trapezoid on a last odd interval) times the Fermi
+    occupation of each contact."""
+    n = len(E)
+    h = E[1] - E[0]
+    q = np.zeros(n)
+    k = n if n % 2 == 1 else n - 1
+    q[:k:2] = 2.0
+    q[1:k:2] = 4.0
+    q[0] = q[k - 1] = 1.0
+    q[:k] *= h / 3.0
+    if k < n:
+        q[k - 1] += 0.5 * h
+        q[k] += 0.5 * h
+    f = lambda x: 0.5 * (1.0 - np.tanh(0.5 * x / kT))
+    return q * f(E - muL), q * f(E - muR)
+
+
+def bench_density_matrix(args):
+    """Nearest-neighbour density-matrix blocks over the N=200, m=64 grid of
+    2048 energies (quadrature weights times Fermi occupations, muL = 0,
+    muR = -0.1 eV, kT = 25 meV): decimation, the FP64 sweep with the
+    rho_ii / rho_{i,i+1} products, and the reduction over workgroups.
+    Inputs and outputs stay in HBM."""
+    import torch
+    from paper_1903_00548_amd import _lib, workloads
+    from oracle.density_matrix import density_matrix_blocks
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    wl = workloads.config1()
+    dev = wl.device
+    N, m, nE = dev.N, dev.m, len(wl.E)
+    wL, wR = dm_weights(wl.E)
+    cpu = None
+    if not args.no_cpu_baseline:
+        k = 8
+        sub = np.linspace(0, nE - 1, k).astype(int)
+        a = time.perf_counter()
+        density_matrix_blocks(dev, wl.E[sub], wL[sub], wR[sub], wl.eta)
+        dt = time.perf_counter() - a
+        cpu = {"value": k / dt, "unit": "energy-solves/s", "cores": 1, "kind": "oracle",
+               "sample": f"{k} of the {nE} energies, density-matrix oracle (dense block columns), one process"}
+    ctx = _lib.context_for(dev, 0)
+    stream = torch.cuda.current_stream()
+    ctx.set_stream(stream.cuda_stream)
+    dd = lambda x: torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+    E_t, wL_t, wR_t = dd(wl.E), dd(wL), dd(wR)
+    rd_t = torch.empty((N, m, m), dtype=torch.complex128, device="cuda")
+    ro_t = torch.empty((N - 1, m, m), dtype=torch.complex128, device="cuda")
+    T_t = torch.empty(nE, dtype=torch.float64, device="cuda")
+    L_t = torch.empty((nE, 2, N), dtype=torch.float64, device="cuda")
+
+    def step():
+        ctx.density_matrix_device(E_t.data_ptr(), wL_t.data_ptr(), wR_t.data_ptr(), nE, wl.eta, rd_t.data_ptr(),
+                                  ro_t.data_ptr(), T_t.data_ptr(), L_t.data_ptr())
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.kernel_times(True)
+    t = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        a = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        t.append(time.perf_counter() - a)
+    total = time.perf_counter() - t0
+    dec_ms, sweep_ms, launches = ctx.kernel_times(False)
+    rd = rd_t.cpu().numpy()
+    L = L_t.cpu().numpy()
+    tr = np.real(np.einsum("iaa->i", rd))
+    ref = wL @ L[:, 0, :] + wR @ L[:, 1, :]
+    trace_err = float(np.abs(tr - ref).max() / max(1.0, np.abs(ref).max()))
+    herm = float(np.abs(rd - np.swapaxes(rd.conj(), -1, -2)).max() / max(1.0, np.abs(rd).max()))
+    flops = nE * (N * (152.0 / 3.0) + (2 * N - 1) * 16.0) * m ** 3
+    ach = flops / (sweep_ms / args.steps * 1e-3) / 1e12
+    print(json.dumps({
+        "metric": "energy-solves/s with nearest-neighbour density-matrix blocks (N=200 slabs, m=64, FP64)",
+        "value": args.steps * nE / total, "unit": "energy-solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * total / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "cfg1_N200_m64_E2048_density_matrix", "N": N, "m": m, "energies_per_step": nE,
+                   "eta": wl.eta, "muL": 0.0, "muR": -0.1, "kT": 0.025},
+        "roofline": {"bound": "mfma", "achieved": ach, "peak": PEAK["fp64"], "unit": "TFLOP/s",
+                     "frac": ach / PEAK["fp64"], "traffic": None,
+                     "kernel": "k_sweep density-matrix variant (sweeps + rho_ii, rho_i,i+1 products)"},
+        "cpu_baseline": cpu,
+        "sweep_kernel_ms_per_step": sweep_ms / args.steps, "decimation_kernel_ms_per_step": dec_ms / args.steps,
+        "p50_step_ms": 1e3 * float(np.percentile(t, 50)), "p99_step_ms": 1e3 * float(np.percentile(t, 99)),
+        "trace_vs_slab_densities_rel": trace_err, "rho_ii_hermiticity_rel": herm,
+    }))
+
+
 def bench_batch(args):
     """64 devices of uneven slab count (50..400) and block size (32..128),
     256 energies each: the batched launch (FP64 and mixed) against the
@@ -372,7 +466,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration)")
-    ap.add_argument("--workload", choices=("cfg1", "cfg2", "batch64", "serve", "bands"), default="cfg1",
+    ap.add_argument("--workload", choices=("cfg1", "cfg2", "batch64", "serve", "bands", "density_matrix"),
+                    default="cfg1",
                     help="cfg1: the headline N=200, m=64 grid (default); batch64: the uneven 64-device "
                          "batch; serve: the Poisson request loop")
     ap.add_argument("--serve-seconds", type=float, default=60.0)
@@ -380,6 +475,12 @@ def main():
     args = ap.parse_args()
     if args.workload == "bands":
         bench_bands(args)
+        return
+    if args.workload == "density_matrix":
+        if args.gpus != 1:
+            print("bench.py: one GPU only", file=sys.stderr)
+            sys.exit(2)
+        bench_density_matrix(args)
         return
     if args.workload == "cfg2":
         if args.gpus != 1:

@@ -144,6 +144,45 @@ qtx_status qtx_solve_device(qtx_ctx* ctx, const double* E_dev, int nE, double et
                             qtx_precision prec, double* T_dev, double* ldos_dev,
                             qtx_info* info_dev);
 
+/* Nearest-neighbour blocks of the density matrix in the slab basis (the
+ * Bloch-basis density matrix of Sec. "Density", eq. density_matrices, whose
+ * on-slab and neighbouring-slab blocks suffice for the density,
+ * eq. density_3d_fast), accumulated over an energy grid with per-contact
+ * weights:
+ *   rho_ij = sum_e (1/pi) [wL[e] G_{i,0} Gamma_L G_{j,0}^H
+ *                          + wR[e] G_{i,N-1} Gamma_R G_{j,N-1}^H]   at E[e],
+ * i.e. the FP64 solution psi of each injecting contact weighted column by
+ * column.  wL[e], wR[e] carry the quadrature weight times the occupation of
+ * the contact (e.g. Simpson weight times f(E - mu)); any finite values.
+ * The paper's n_{i'n'k',ink} is rho with its index pairs exchanged
+ * (n[i' a][i b] = rho_{i i'}[b][a]); rho is Hermitian as a whole:
+ * rho_{i+1,i} = rho_{i,i+1}^H.
+ * Host buffers, row-major m x m blocks, caller-allocated:
+ *   rho_diag[N*m*m]       rho_ii, i = 0..N-1;
+ *   rho_off[(N-1)*m*m]    rho_{i,i+1}, i = 0..N-2 (may be NULL when N = 1);
+ *   T[nE], ldos[nE*2*N], info[nE]: as in qtx_solve (each may be NULL).
+ * The sum over energies is formed in a fixed order for a given grid, block
+ * size and option set.  Device memory: one accumulator of (2N-1) M^2 complex
+ * doubles per resident workgroup (M the padded block), at most option
+ * "density_matrix_bytes" (default 64 GiB) in total; QTX_ENOMEM if not even
+ * one fits.  nE = 0 zeroes the outputs.  Returns QTX_OK, QTX_ENOTCONV
+ * (outputs written, some energy flagged) or an error code.  Synchronous. */
+qtx_status qtx_density_matrix(qtx_ctx* ctx, const double* E, const double* wL, const double* wR,
+                              int nE, double eta, qtx_c128* rho_diag, qtx_c128* rho_off,
+                              double* T, double* ldos, qtx_info* info);
+
+/* Same as qtx_density_matrix with DEVICE pointers, enqueued on the context
+ * stream without a host synchronisation: E_dev, wL_dev, wR_dev [nE];
+ * rho_diag_dev, rho_off_dev as rho_diag, rho_off; T_dev [nE] required,
+ * ldos_dev and info_dev may be NULL.  Weights are not checked on the host
+ * (a non-finite weight gives non-finite blocks).  Per-energy convergence is
+ * reported through info_dev only.  The buffers must stay alive until the
+ * stream has executed the work. */
+qtx_status qtx_density_matrix_device(qtx_ctx* ctx, const double* E_dev, const double* wL_dev,
+                                     const double* wR_dev, int nE, double eta,
+                                     qtx_c128* rho_diag_dev, qtx_c128* rho_off_dev,
+                                     double* T_dev, double* ldos_dev, qtx_info* info_dev);
+
 /* Self-energies and broadening factors alone (the decimation step of the
  * solve, exposed for verification).  Host buffers:
  *   sigma[nE*2*m*m]  Sigma_L then Sigma_R per energy (row-major, m x m);
@@ -181,6 +220,9 @@ qtx_status qtx_self_energy(qtx_ctx* ctx, const double* E, int nE, double eta,
  *                           replaced oldest first, never one the current
  *                           call uses); 0 disables the cache.  Changing eta
  *                           or a decimation option empties it;
+ *   "density_matrix_bytes"  [0, 1e13]     64 GiB device memory for the
+ *                           per-workgroup accumulators of qtx_density_matrix
+ *                           (fewer workgroups run when they do not all fit);
  *   "use_graph"             0 or 1        1      qtx_solve_batch captures its
  *                           launch sequence in a HIP graph and replays it
  *                           while the batch shape is unchanged.

@@ -18,6 +18,9 @@ device alike):
   slab-resolved density of states per injecting contact
   n_i = (1/pi) Re sum_{j in slab i} [G Gamma G^H]_jj (Sec. "Density", node
   density; Sec. "Transmission and Ballistic Current");
+* the nearest-neighbour blocks of the slab-basis density matrix over an
+  energy grid with per-contact weights (Sec. "Density",
+  eq. density_matrices; oracle.density_matrix);
 * the paper's own mode-space QTBM at eta = 0 as a cross-check (eqs.
   hellmann-feynman, normalization, transmission).
 
@@ -32,10 +35,12 @@ from .device import (potential_weights, assemble, first_block_column,
                      last_block_column, columns_dense, columns_banded,
                      columns_two_pass)
 from .observables import transmission, slab_dos, solve_energy, solve_device
+from .density_matrix import density_matrix_blocks
 
 __all__ = [
     "lead_operators", "complex_band_modes", "self_energies", "broadening",
     "open_channels", "potential_weights", "assemble", "first_block_column",
     "last_block_column", "columns_dense", "columns_banded", "columns_two_pass",
     "transmission", "slab_dos", "solve_energy", "solve_device",
+    "density_matrix_blocks",
 ]

@@ -21,7 +21,10 @@ states", "Density", "Transmission and Ballistic Current"):
    out-flowing travelling modes (eq. transmission); the reflection uses the
    source's out-flowing modes after removing the injected wave; T + R = 1;
 6. node density n_i = sum_gamma g_gamma sum_{j in slab i} |c_{gamma,j}|^2
-   with g_gamma = 2/|v_gamma| (spin 2).
+   with g_gamma = 2/|v_gamma| (spin 2), and the nearest-neighbour blocks of
+   the density matrix per contact, sum_gamma g_gamma c_{gamma,i} c_{gamma,j}^H
+   for j = i, i + 1 (eq. density_matrices at one energy, unit weight and
+   occupation; the paper's index order is the transpose).
 """
 from __future__ import annotations
 
@@ -78,8 +81,15 @@ def qtbm_energy(dev, E, tol=1e-8):
     vL_out = mL["v"][mL["left"]]
 
     N = dev.N
+    m = dev.m
     out = dict(T_LR=[], R_LR=[], T_RL=[], R_RL=[], v_inj_L=[], v_inj_R=[],
-               nL=np.zeros(N), nR=np.zeros(N), B_L=[], B_R=[])
+               nL=np.zeros(N), nR=np.zeros(N), B_L=[], B_R=[],
+               rhoL_d=np.zeros((N, m, m), complex), rhoL_o=np.zeros((N - 1, m, m), complex),
+               rhoR_d=np.zeros((N, m, m), complex), rhoR_o=np.zeros((N - 1, m, m), complex))
+
+    def add_blocks(key, g, c):
+        out[key + "_d"] += g * np.einsum("ia,ib->iab", c, c.conj())
+        out[key + "_o"] += g * np.einsum("ia,ib->iab", c[:-1], c[1:].conj())
     # injection from the source: incoming = right-going travelling modes
     for g in np.nonzero(mL["right"] & mL["trav"])[0]:
         cg, lg, vg = mL["c"][:, g], mL["lam"][g], mL["v"][g]
@@ -94,6 +104,7 @@ def qtbm_energy(dev, E, tol=1e-8):
         out["v_inj_L"].append(vg)
         out["B_L"].append(B)
         out["nL"] += (2.0 / abs(vg)) * np.sum(np.abs(c) ** 2, axis=1)
+        add_blocks("rhoL", 2.0 / abs(vg), c)
     # injection from the drain: incoming = left-going travelling modes
     for g in np.nonzero(mR["left"] & mR["trav"])[0]:
         cg, lg, vg = mR["c"][:, g], mR["lam"][g], mR["v"][g]
@@ -108,6 +119,7 @@ def qtbm_energy(dev, E, tol=1e-8):
         out["v_inj_R"].append(vg)
         out["B_R"].append(B)
         out["nR"] += (2.0 / abs(vg)) * np.sum(np.abs(c) ** 2, axis=1)
+        add_blocks("rhoR", 2.0 / abs(vg), c)
     out["n_open_L"] = len(out["T_LR"])
     out["n_open_R"] = len(out["T_RL"])
     out["gamma_L"] = broadening(sigL)

@@ -59,6 +59,10 @@ _SIGS = {
     "qtx_autotune": (c_int, [c_void_p, c_void_p, c_int, c_double, c_int, c_void_p, c_void_p]),
     "qtx_solve_batch": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_double, c_int,
                                 c_void_p, c_void_p]),
+    "qtx_density_matrix": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_double, c_void_p, c_void_p,
+                                   c_void_p, c_void_p, c_void_p]),
+    "qtx_density_matrix_device": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_double, c_void_p,
+                                          c_void_p, c_void_p, c_void_p, c_void_p]),
     "qtx_charge": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_double, c_double, c_double,
                            c_void_p]),
 }
@@ -174,6 +178,35 @@ class Context:
         st = self.lib.qtx_solve_device(self.h, c_void_p(E_ptr), int(nE), float(eta), int(precision),
                                        c_void_p(T_ptr), c_void_p(ldos_ptr or None),
                                        c_void_p(info_ptr or None))
+        return self._check(st, allow_notconv=True)
+
+    def density_matrix(self, E, wL, wR, eta, want_ldos=False):
+        """Energy-weighted density-matrix blocks (see qtx_density_matrix):
+        rho_diag (N, m, m), rho_off (N-1, m, m), T (nE,), ldos (nE, 2, N)
+        or None, info, status."""
+        E = np.ascontiguousarray(E, dtype=np.float64)
+        nE = E.shape[0]
+        wL = np.ascontiguousarray(np.broadcast_to(np.asarray(wL, dtype=np.float64), (nE,)))
+        wR = np.ascontiguousarray(np.broadcast_to(np.asarray(wR, dtype=np.float64), (nE,)))
+        N, m = self.N, self.m
+        rd = np.empty((N, m, m), dtype=np.complex128)
+        ro = np.empty((max(N - 1, 0), m, m), dtype=np.complex128)
+        T = np.empty(nE)
+        ldos = np.empty((nE, 2, N)) if want_ldos else None
+        info = np.zeros(nE, dtype=INFO_DTYPE)
+        st = self.lib.qtx_density_matrix(self.h, _ptr(E), _ptr(wL), _ptr(wR), nE, float(eta), _ptr(rd),
+                                         _ptr(ro) if N > 1 else None, _ptr(T), _ptr(ldos), _ptr(info))
+        st = self._check(st, allow_notconv=True)
+        return rd, ro, T, ldos, info, st
+
+    def density_matrix_device(self, E_ptr, wL_ptr, wR_ptr, nE, eta, rho_d_ptr, rho_o_ptr, T_ptr, ldos_ptr=0,
+                              info_ptr=0):
+        """Device pointers (e.g. torch tensor data_ptr()); enqueued on the
+        context stream."""
+        st = self.lib.qtx_density_matrix_device(self.h, c_void_p(E_ptr), c_void_p(wL_ptr), c_void_p(wR_ptr), int(nE),
+                                                float(eta), c_void_p(rho_d_ptr), c_void_p(rho_o_ptr or None),
+                                                c_void_p(T_ptr), c_void_p(ldos_ptr or None),
+                                                c_void_p(info_ptr or None))
         return self._check(st, allow_notconv=True)
 
     def self_energy(self, E, eta):

@@ -68,6 +68,8 @@ struct qtx_ctx {
   DevBuf wE, wT, wldos, winfo;
   DevBuf sig, wf, sgn, iters, nheavy, dscr, sws, part;
   DevBuf redo, elist, ecount;                  // mixed: energies re-solved in FP64
+  DevBuf dmw, rho, dmout;                      // density-matrix blocks: weights, accumulators, sums
+  double dm_bytes = 64.0 * (1ull << 30);       // cap on the per-workgroup accumulators
 
   uint64_t lead_hash[2] = {0, 0};
 
@@ -294,6 +296,70 @@ qtx_status solve_device_core(qtx_ctx* c, const double* E_dev, int nE, double eta
   return QTX_OK;
 }
 
+// Density-matrix blocks of an energy grid, enqueued on the context stream:
+// decimation and the density-matrix sweep per launch chunk into one
+// accumulator per workgroup, then their sum into out_d / out_o (device,
+// m x m blocks).  T, ldos (or null) and info (or null) as in a solve.
+qtx_status density_matrix_core(qtx_ctx* c, const double* E_dev, const double* wL_dev, const double* wR_dev, int nE,
+                               double eta, double2* out_d, double2* out_o, double* T_dev, double* ldos_dev,
+                               qtx_info* info_dev) {
+  qtx_status s = check_ready(c);
+  if (s != QTX_OK) return s;
+  if (nE < 0 || !(eta >= 0.0)) return fail(c, QTX_EINVAL, "nE must be >= 0 and eta >= 0");
+  const int N = c->N, m = c->m, M = c->M;
+  if (!out_d || (N > 1 && !out_o)) return fail(c, QTX_EINVAL, "rho_diag (and rho_off when N > 1) must not be NULL");
+  const size_t mm = (size_t)m * m, nblk = 2 * (size_t)N - 1;
+  if (nE == 0) {
+    QTX_HIP(c, hipMemsetAsync(out_d, 0, (size_t)N * mm * sizeof(double2), c->stream));
+    if (N > 1) QTX_HIP(c, hipMemsetAsync(out_o, 0, (size_t)(N - 1) * mm * sizeof(double2), c->stream));
+    return QTX_OK;
+  }
+  if (!E_dev || !wL_dev || !wR_dev || !T_dev) return fail(c, QTX_EINVAL, "E, wL, wR and T must not be NULL");
+  const size_t MM = (size_t)M * M, stride = nblk * MM;
+  const size_t per_wg = stride * sizeof(double2);
+  const int cap = (int)std::min<double>(1 << 20, std::floor(c->dm_bytes / (double)per_wg));
+  if (cap < 1) return fail(c, QTX_ENOMEM, "density_matrix_bytes is below one workgroup's accumulators");
+  // one accumulator per workgroup; every workgroup takes its first energy
+  // in the first launch (grid <= the first launch's energies)
+  const int first = std::min(c->chunk, nE);
+  const int grid = std::max(1, std::min({first, c->num_cu * wgs_per_cu(c, M, false), cap}));
+  const size_t wsb = qtx::sweep_ws_bytes(N, M, false, true);
+  QTX_HIP(c, c->rho.ensure((size_t)grid * per_wg));
+  QTX_HIP(c, c->sws.ensure((size_t)grid * wsb));
+  QTX_HIP(c, c->part.ensure((size_t)grid * 4 * 2 * N * sizeof(double)));
+  for (int e0 = 0; e0 < nE; e0 += c->chunk) {
+    const int ne = std::min(c->chunk, nE - e0);
+    s = stage_decimate(c, E_dev + e0, ne, eta, false);
+    if (s != QTX_OK) return s;
+    qtx::SweepArgs a{};
+    a.E = E_dev + e0;
+    a.nE = ne;
+    a.eta = eta;
+    a.sig = c->sig.as<double2>();
+    a.wf = c->wf.as<double2>();
+    a.sgn = c->sgn.as<double>();
+    a.iters = c->iters.as<int>();
+    a.nheavy = c->nheavy.as<int>();
+    a.ws = c->sws.as<char>();
+    a.ws_bytes = wsb;
+    a.part = c->part.as<double>();
+    a.nmax = N;
+    a.T = T_dev + e0;
+    a.ldos = ldos_dev ? ldos_dev + (size_t)e0 * 2 * N : nullptr;
+    a.info = info_dev ? info_dev + e0 : nullptr;
+    a.dmwL = wL_dev + e0;
+    a.dmwR = wR_dev + e0;
+    a.rho = c->rho.as<double2>();
+    a.rho_stride = stride;
+    a.rho_first = e0 == 0;
+    QTX_HIP(c, record(c, c->ev_sw, c->n_sw));
+    QTX_HIP(c, qtx::run_sweep_dm(M, make_prob(c), a, grid, c->stream));
+    QTX_HIP(c, record(c, c->ev_sw, c->n_sw));
+  }
+  QTX_HIP(c, qtx::run_dm_reduce(c->rho.as<double2>(), grid, stride, N, M, m, out_d, out_o, c->stream));
+  return QTX_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -500,6 +566,67 @@ qtx_status qtx_solve(qtx_ctx* c, const double* E, int nE, double eta, qtx_precis
   return QTX_OK;
 }
 
+qtx_status qtx_density_matrix_device(qtx_ctx* c, const double* E_dev, const double* wL_dev, const double* wR_dev,
+                                     int nE, double eta, qtx_c128* rho_diag_dev, qtx_c128* rho_off_dev,
+                                     double* T_dev, double* ldos_dev, qtx_info* info_dev) {
+  if (!c) return QTX_EINVAL;
+  hipSetDevice(c->device);
+  return density_matrix_core(c, E_dev, wL_dev, wR_dev, nE, eta, (double2*)rho_diag_dev, (double2*)rho_off_dev,
+                             T_dev, ldos_dev, info_dev);
+}
+
+qtx_status qtx_density_matrix(qtx_ctx* c, const double* E, const double* wL, const double* wR, int nE, double eta,
+                              qtx_c128* rho_diag, qtx_c128* rho_off, double* T, double* ldos, qtx_info* info) {
+  if (!c) return QTX_EINVAL;
+  qtx_status s = check_ready(c);
+  if (s != QTX_OK) return s;
+  const int N = c->N, m = c->m;
+  if (nE < 0 || !(eta >= 0.0)) return fail(c, QTX_EINVAL, "nE must be >= 0 and eta >= 0");
+  if (!rho_diag || (N > 1 && !rho_off)) return fail(c, QTX_EINVAL, "rho_diag (and rho_off when N > 1) must not be NULL");
+  const size_t mm = (size_t)m * m, nblk = 2 * (size_t)N - 1;
+  if (nE == 0) {
+    std::memset(rho_diag, 0, (size_t)N * mm * sizeof(qtx_c128));
+    if (N > 1) std::memset(rho_off, 0, (size_t)(N - 1) * mm * sizeof(qtx_c128));
+    return QTX_OK;
+  }
+  if (!E || !wL || !wR) return fail(c, QTX_EINVAL, "E, wL and wR must not be NULL");
+  for (int e = 0; e < nE; ++e)
+    if (!std::isfinite(E[e]) || !std::isfinite(wL[e]) || !std::isfinite(wR[e]))
+      return fail(c, QTX_EINVAL, "energies and weights must be finite");
+  hipSetDevice(c->device);
+  QTX_HIP(c, c->wE.ensure((size_t)nE * sizeof(double)));
+  QTX_HIP(c, c->wT.ensure((size_t)nE * sizeof(double)));
+  QTX_HIP(c, c->wldos.ensure((size_t)nE * 2 * N * sizeof(double)));
+  QTX_HIP(c, c->winfo.ensure((size_t)nE * sizeof(qtx_info)));
+  QTX_HIP(c, c->dmw.ensure((size_t)2 * nE * sizeof(double)));
+  QTX_HIP(c, c->dmout.ensure(nblk * mm * sizeof(double2)));
+  double* wdev = c->dmw.as<double>();
+  QTX_HIP(c, hipMemcpyAsync(c->wE.p, E, (size_t)nE * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  QTX_HIP(c, hipMemcpyAsync(wdev, wL, (size_t)nE * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  QTX_HIP(c, hipMemcpyAsync(wdev + nE, wR, (size_t)nE * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  double2* od = c->dmout.as<double2>();
+  s = density_matrix_core(c, c->wE.as<double>(), wdev, wdev + nE, nE, eta, od, od + (size_t)N * mm,
+                          c->wT.as<double>(), c->wldos.as<double>(), c->winfo.as<qtx_info>());
+  if (s != QTX_OK) return s;
+  std::vector<qtx_info> hinfo(nE);
+  QTX_HIP(c, hipMemcpyAsync(rho_diag, od, (size_t)N * mm * sizeof(double2), hipMemcpyDeviceToHost, c->stream));
+  if (N > 1)
+    QTX_HIP(c, hipMemcpyAsync(rho_off, od + (size_t)N * mm, (size_t)(N - 1) * mm * sizeof(double2),
+                              hipMemcpyDeviceToHost, c->stream));
+  if (T) QTX_HIP(c, hipMemcpyAsync(T, c->wT.p, (size_t)nE * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  if (ldos)
+    QTX_HIP(c, hipMemcpyAsync(ldos, c->wldos.p, (size_t)nE * 2 * N * sizeof(double), hipMemcpyDeviceToHost,
+                              c->stream));
+  QTX_HIP(c, hipMemcpyAsync(hinfo.data(), c->winfo.p, (size_t)nE * sizeof(qtx_info), hipMemcpyDeviceToHost,
+                            c->stream));
+  QTX_HIP(c, hipStreamSynchronize(c->stream));
+  bool flagged = false;
+  for (int e = 0; e < nE; ++e) flagged |= (hinfo[e].flags != 0);
+  if (info) std::memcpy(info, hinfo.data(), (size_t)nE * sizeof(qtx_info));
+  if (flagged) return fail(c, QTX_ENOTCONV, "some energies were flagged (see qtx_info.flags)");
+  return QTX_OK;
+}
+
 qtx_status qtx_self_energy(qtx_ctx* c, const double* E, int nE, double eta, qtx_c128* sigma, qtx_c128* wfac,
                            double* sgn, int* iters) {
   if (!c) return QTX_EINVAL;
@@ -611,6 +738,9 @@ qtx_status qtx_set_option(qtx_ctx* c, const char* name, double value) {
   } else if (n == "use_graph") {
     if (!(value == 0.0 || value == 1.0)) return fail(c, QTX_EINVAL, "use_graph must be 0 or 1");
     c->use_graph = value != 0.0;
+  } else if (n == "density_matrix_bytes") {
+    if (!(value >= 0.0 && value <= 1e13)) return fail(c, QTX_EINVAL, "density_matrix_bytes must be in [0, 1e13]");
+    c->dm_bytes = value;
   } else if (n == "energies_per_launch") {
     if (!integral || value < 1 || value > (1 << 20)) return fail(c, QTX_EINVAL, "energies_per_launch must be in [1, 2^20]");
     c->chunk = (int)value;

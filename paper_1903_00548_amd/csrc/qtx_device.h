@@ -218,6 +218,27 @@ template <typename R> struct BGen {
   }
 };
 
+// A[row][k] = w_k P[row][k] with w_k = wR sR[k] for k < M and wL sL[k - M]
+// above: a solution block [right-injected | left-injected] with each
+// column weighted by its broadening sign and its contact's weight.
+struct APsiW {
+  const double2* p; int ld; const double* sR; const double* sL; double wR, wL; int M;
+  __device__ __forceinline__ cpx<double> get(int row, int k) const {
+    const double w = k < M ? wR * sR[k] : wL * sL[k - M];
+    const cpx<double> v = ldd(p + (size_t)row * ld + k);
+    return mk<double>(w * v.re, w * v.im);
+  }
+};
+
+// B[k][col] = conj(P[col][k]): the conjugate transpose of a solution block.
+struct BPsiH {
+  const double2* p; int ld;
+  __device__ __forceinline__ cpx<double> get(int k, int col) const {
+    const cpx<double> v = ldd(p + (size_t)col * ld + k);
+    return mk<double>(v.re, -v.im);
+  }
+};
+
 // acc[ti] (ti = 0..MT-1, a full column of tiles) += A[:, 0:16*KT] * B[0:16*KT, tile tj].
 // One k-slice per step (lane group g carries k = 16 kb + 4 g + s); the
 // operands of the next slice are loaded while the MFMAs of the current one

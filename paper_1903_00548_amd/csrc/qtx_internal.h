@@ -91,6 +91,15 @@ struct SweepArgs {
   int* redo;               // mixed: 1 where the refinement did not converge
   double rtol;             // mixed: stop when ||r|| <= rtol ||b||
   int maxstep;             // mixed: at most this many corrections
+  // density-matrix sweep only: weights dmwL[e] (left-injected columns) and
+  // dmwR[e] (right-injected) of energy e; workgroup b accumulates rho_ii
+  // and rho_{i,i+1} (blocks 2i and 2i+1, M x M each) at rho + b rho_stride,
+  // starting from zero at its first energy when rho_first is set
+  const double* dmwL;
+  const double* dmwR;
+  double2* rho;
+  size_t rho_stride;
+  int rho_first;
 };
 
 // Per-workgroup sweep workspace.  FP64 sweep: [X_i | z_i] for N slabs plus
@@ -99,13 +108,14 @@ struct SweepArgs {
 // Schur complements (M x M floats); the correction columns (N M x 2M
 // floats); one slab of right-hand sides (M x 2M floats); the refined
 // solution (N M x 2M doubles).
+// The density-matrix sweep (FP64) keeps a second back-substitution buffer.
 // Blocks above 64 (96, 128) keep two more M x (M + 1) complex matrices of
 // the sweep precision at the end: the working matrix and the staged
 // coupling block.
-inline size_t sweep_ws_bytes(int N, int M, bool mixed) {
+inline size_t sweep_ws_bytes(int N, int M, bool mixed, bool dm = false) {
   const size_t MM = (size_t)M * M;
   const size_t big = M > 64 ? 2 * (size_t)M * (M + 1) * (mixed ? sizeof(float2) : sizeof(double2)) : 0;
-  if (!mixed) return (size_t)(N + 1) * 2 * MM * sizeof(double2) + big;
+  if (!mixed) return (size_t)(N + (dm ? 2 : 1)) * 2 * MM * sizeof(double2) + big;
   return ((size_t)(N + 1) * 2 * MM + (size_t)N * MM + (size_t)N * 2 * MM + 2 * MM) * sizeof(float2) +
          (size_t)N * 2 * MM * sizeof(double2) + big;
 }
@@ -129,15 +139,27 @@ hipError_t run_decimate(int M, const Prob& P, const BatchDesc& b, const double* 
 hipError_t run_sweep(int M, bool mixed, const Prob& P, const SweepArgs& a, const BatchDesc& b, int grid,
                      hipStream_t st);
 
+// FP64 sweep that also accumulates the density-matrix blocks (a.dmw,
+// a.rho, a.rho_stride, a.rho_first; workspace sweep_ws_bytes(N, M, false,
+// true)).  One problem, no energy list.
+hipError_t run_sweep_dm(int M, const Prob& P, const SweepArgs& a, int grid, hipStream_t st);
+
+// out_d[i] (m x m, i < N) and out_o[i] (i < N - 1) = the sum over the nwg
+// workgroup accumulators (stride elements apart) of blocks 2i and 2i+1,
+// in workgroup order.
+hipError_t run_dm_reduce(const double2* rho, int nwg, size_t stride, int N, int M, int m, double2* out_d,
+                         double2* out_o, hipStream_t st);
+
 // Band energies of one lead (padded blocks, physical size m) at nk Bloch
 // phases: E[q * m + n] = E_n(k_q) + V.  work: grid * 2 M (M + 1) complex
 // doubles when M > 64 (else unused).
 hipError_t run_bands(int M, const double2* lead, int m, double V, const double* k, int nk, double2* work, int grid,
                      double* E, hipStream_t st);
 
-// Workgroups of the sweep (FP64 or mixed) and of the decimation that one CU
-// can hold at block size M, from the kernels' register and LDS use.
-hipError_t max_resident(int M, bool mixed, int* sweep_wgs, int* dec_wgs);
+// Workgroups of the sweep (FP64 or mixed), of the decimation and (dm_wgs
+// non-null) of the density-matrix sweep that one CU can hold at block size
+// M, from the kernels' register and LDS use.
+hipError_t max_resident(int M, bool mixed, int* sweep_wgs, int* dec_wgs, int* dm_wgs = nullptr);
 
 // elist[0 .. *ecount) = the energies e < nE with redo[e] != 0 (one wave).
 hipError_t run_compact(const int* redo, int nE, int* elist, int* ecount, hipStream_t st);

@@ -696,8 +696,9 @@ __device__ __forceinline__ double refine(const Prob& P, const SweepArgs& a, cons
 //
 // With a.elist (FP64 sweep only) the launch re-solves the listed energies,
 // keeping the refinement diagnostics in info and marking the fallback.
-template <typename R, int M, bool MIX>
+template <typename R, int M, bool MIX, bool DM>
 __global__ __launch_bounds__(NT, M > 64 ? 1 : 2) void k_sweep(Prob P0, SweepArgs a, BatchDesc b) {
+  static_assert(!DM || (!MIX && sizeof(R) == 8), "density-matrix blocks come from the FP64 sweep");
   typedef typename vec2t<R>::type V2;
   constexpr int MT = M / 16, MM = M * M, S = M + 1, LD = 2 * M;
   // M > 64: the working matrix and the staged coupling block live at the
@@ -918,6 +919,14 @@ __global__ __launch_bounds__(NT, M > 64 ? 1 : 2) void k_sweep(Prob P0, SweepArgs
     // back substitution with fused slab densities
     for (int i = N - 1; i >= 0; --i) {
       const V2* Xi = XZ + (size_t)i * M * LD;
+      // psi_i overwrites psi_{i+1} column tile by column tile (one wave owns
+      // a column tile); DM keeps both, in alternating buffers
+      V2* PSc = PSI;
+      const V2* PSn = PSI;
+      if constexpr (DM) {
+        PSc = PSI + (size_t)(i & 1) * M * LD;
+        PSn = PSI + (size_t)((i + 1) & 1) * M * LD;
+      }
       if (i < N - 1) {
         // stage -X_i in LDS once per slab (every wave reads all of it);
         // M > 64 reads X_i where it is
@@ -946,8 +955,8 @@ __global__ __launch_bounds__(NT, M > 64 ? 1 : 2) void k_sweep(Prob P0, SweepArgs
           for (int ti = 0; ti < MT; ++ti) tzero(acc[ti]);
         }
         if (i < N - 1) {
-          if constexpr (BIG) cgemm_col<R, MT, MT>(acc, AGlob<R>{Xi, LD, (R)-1}, BGlob<R>{PSI, LD}, tj);
-          else cgemm_col<R, MT, MT>(acc, ALds<R>{mat, S}, BGlob<R>{PSI, LD}, tj);
+          if constexpr (BIG) cgemm_col<R, MT, MT>(acc, AGlob<R>{Xi, LD, (R)-1}, BGlob<R>{PSn, LD}, tj);
+          else cgemm_col<R, MT, MT>(acc, ALds<R>{mat, S}, BGlob<R>{PSn, LD}, tj);
         }
         const int cl = 16 * tj + (lane & 15);
         const double sg = cl < M ? sgR[cl] : sgL[cl - M];
@@ -959,7 +968,7 @@ __global__ __launch_bounds__(NT, M > 64 ? 1 : 2) void k_sweep(Prob P0, SweepArgs
         double pp = 0.0;
         tiles_foreach<R, MT>(acc, tj, [&](int row, int col, int ti, int r) {
           const double re = acc[ti].re[r], im = acc[ti].im[r];
-          st2<R>(PSI + (unsigned)(row * LD + col), mk<R>(acc[ti].re[r], acc[ti].im[r]));
+          st2<R>(PSc + (unsigned)(row * LD + col), mk<R>(acc[ti].re[r], acc[ti].im[r]));
           if constexpr (MIX)
             if (keep) P64[(size_t)i * M * LD + (unsigned)(row * LD + col)] = make_double2(re, im);
           pp += re * re + im * im;
@@ -975,6 +984,42 @@ __global__ __launch_bounds__(NT, M > 64 ? 1 : 2) void k_sweep(Prob P0, SweepArgs
       if (lane == 0) {
         prt[(w * 2 + 0) * N + i] = pL;
         prt[(w * 2 + 1) * N + i] = pR;
+      }
+      if constexpr (DM) {
+        // rho_ii += psi_i W psi_i^H and rho_{i,i+1} += psi_i W psi_{i+1}^H
+        // into this workgroup's accumulators; W weights each injected
+        // column by its sign in Gamma = V diag(s) V^H, the energy's weight
+        // for its contact, and 1/pi.  A task is one column tile of one of
+        // the two blocks; the products read psi where it is (L1/L2).
+        __syncthreads();                        // psi_i complete
+        const double ipi = 0.31830988618379067154;
+        const double wl = a.dmwL[e] * ipi, wr = a.dmwR[e] * ipi;
+        double2* Rb = a.rho + (size_t)blockIdx.x * a.rho_stride + (size_t)(2 * i) * MM;
+        const bool fresh = a.rho_first && q == (int)blockIdx.x;
+        const int ntask = (i < N - 1 ? 2 : 1) * MT;
+#pragma unroll 1
+        for (int task = w; task < ntask; task += NWAVE) {
+          const bool off = task >= MT;
+          const int tj = off ? task - MT : task;
+          double2* Rt = Rb + (off ? MM : 0);
+          ctile<double> acc[MT];
+          if (fresh) {
+#pragma unroll
+            for (int ti = 0; ti < MT; ++ti) tzero(acc[ti]);
+          } else {
+            tiles_foreach<double, MT>(acc, tj, [&](int row, int col, int ti, int r) {
+              const double2 v = Rt[(unsigned)(row * M + col)];
+              acc[ti].re[r] = v.x;
+              acc[ti].im[r] = v.y;
+            });
+          }
+          cgemm_col<double, MT, 2 * MT>(acc, APsiW{PSc, LD, sgR, sgL, wr, wl, M},
+                                        BPsiH{off ? PSn : PSc, LD}, tj);
+          tiles_foreach<double, MT>(acc, tj, [&](int row, int col, int ti, int r) {
+            Rt[(unsigned)(row * M + col)] = make_double2(acc[ti].re[r], acc[ti].im[r]);
+          });
+        }
+        __syncthreads();                        // the next slab overwrites psi_{i+1}
       }
     }
     __syncthreads();
@@ -1061,6 +1106,27 @@ __global__ __launch_bounds__(NT, M > 64 ? 1 : 2) void k_sweep(Prob P0, SweepArgs
         a.info[e] = inf;
       }
     }
+  }
+}
+
+// Sum of the workgroups' density-matrix accumulators, in workgroup order
+// (the result does not depend on scheduling), cut from the padded M x M
+// blocks to the physical m x m ones.  One thread per output element.
+__global__ __launch_bounds__(NT) void k_dm_reduce(const double2* rho, int nwg, size_t stride, int N, int M, int m,
+                                                  double2* out_d, double2* out_o) {
+  const size_t mm = (size_t)m * m, total = (2 * (size_t)N - 1) * mm;
+  for (size_t idx = (size_t)blockIdx.x * NT + threadIdx.x; idx < total; idx += (size_t)gridDim.x * NT) {
+    const size_t blk = idx / mm, rem = idx - blk * mm;
+    const int r = (int)(rem / m), c = (int)(rem - (size_t)r * m);
+    const double2* src = rho + blk * M * M + (size_t)r * M + c;
+    double re = 0.0, im = 0.0;
+    for (int b = 0; b < nwg; ++b) {
+      const double2 v = src[(size_t)b * stride];
+      re += v.x;
+      im += v.y;
+    }
+    double2* dst = (blk & 1) ? out_o + (blk >> 1) * mm + rem : out_d + (blk >> 1) * mm + rem;
+    *dst = make_double2(re, im);
   }
 }
 
@@ -1286,9 +1352,9 @@ hipError_t launch_decimate(const Prob& P, const BatchDesc& b, const double* E, i
   return hipGetLastError();
 }
 
-template <typename R, int M, bool MIX>
+template <typename R, int M, bool MIX, bool DM = false>
 hipError_t launch_sweep(const Prob& P, const SweepArgs& a, const BatchDesc& b, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((k_sweep<R, M, MIX>), dim3(grid), dim3(NT), 0, st, P, a, b);
+  hipLaunchKernelGGL((k_sweep<R, M, MIX, DM>), dim3(grid), dim3(NT), 0, st, P, a, b);
   return hipGetLastError();
 }
 
@@ -1326,6 +1392,30 @@ hipError_t run_sweep(int M, bool mixed, const Prob& P, const SweepArgs& a, const
 #undef QTX_SWEEP
 }
 
+hipError_t run_sweep_dm(int M, const Prob& P, const SweepArgs& a, int grid, hipStream_t st) {
+  const BatchDesc b{};
+#define QTX_SWEEP_DM(MM) return launch_sweep<double, MM, false, true>(P, a, b, grid, st)
+  switch (M) {
+    case 16: QTX_SWEEP_DM(16);
+    case 32: QTX_SWEEP_DM(32);
+    case 48: QTX_SWEEP_DM(48);
+    case 64: QTX_SWEEP_DM(64);
+    case 96: QTX_SWEEP_DM(96);
+    case 128: QTX_SWEEP_DM(128);
+    default: return hipErrorInvalidValue;
+  }
+#undef QTX_SWEEP_DM
+}
+
+hipError_t run_dm_reduce(const double2* rho, int nwg, size_t stride, int N, int M, int m, double2* out_d,
+                         double2* out_o, hipStream_t st) {
+  const size_t total = (2 * (size_t)N - 1) * m * m;
+  const size_t blocks = (total + NT - 1) / NT;
+  const int grid = (int)(blocks < 8192 ? blocks : 8192);
+  hipLaunchKernelGGL(k_dm_reduce, dim3(grid), dim3(NT), 0, st, rho, nwg, stride, N, M, m, out_d, out_o);
+  return hipGetLastError();
+}
+
 hipError_t run_bands(int M, const double2* lead, int m, double V, const double* k, int nk, double2* work, int grid,
                      double* E, hipStream_t st) {
 #define QTX_BANDS(MM) \
@@ -1343,13 +1433,15 @@ hipError_t run_bands(int M, const double2* lead, int m, double V, const double* 
 #undef QTX_BANDS
 }
 
-hipError_t max_resident(int M, bool mixed, int* sweep_wgs, int* dec_wgs) {
+hipError_t max_resident(int M, bool mixed, int* sweep_wgs, int* dec_wgs, int* dm_wgs) {
   int a = 0, b = 0;
   hipError_t e = hipSuccess;
 #define QTX_OCC(MM)                                                                                              \
-  e = mixed ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_sweep<float, MM, true>, NT, 0)               \
-            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_sweep<double, MM, false>, NT, 0);            \
+  e = mixed ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_sweep<float, MM, true, false>, NT, 0)        \
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_sweep<double, MM, false, false>, NT, 0);     \
   if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_decimate<MM>, NT, 0);           \
+  if (e == hipSuccess && dm_wgs)                                                                              \
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(dm_wgs, k_sweep<double, MM, false, true>, NT, 0);        \
   break
   switch (M) {
     case 16: QTX_OCC(16);

@@ -1,0 +1,155 @@
+"""Density-matrix blocks (qtx_density_matrix) against the FP64 oracle.
+
+rho_ii and rho_{i,i+1} summed over an energy grid with per-contact weights
+(Sec. "Density", eq. density_matrices).  Tolerance: every element within
+1e-9 * max(1, max |rho_ref|) of the oracle (the slab-density tolerance of
+the FP64 path, applied to the blocks whose traces are those densities).
+Properties checked at any size: the trace of rho_ii equals the weighted sum
+of the same call's slab densities, rho_ii is Hermitian, and the call's T and
+densities equal those of the plain FP64 solve.
+"""
+import numpy as np
+import pytest
+
+from oracle.density_matrix import density_matrix_blocks
+from paper_1903_00548_amd import _lib
+from paper_1903_00548_amd import workloads as W
+
+import small_cases
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-9
+
+
+def _weights(E, seed):
+    rng = np.random.default_rng(seed)
+    return rng.uniform(0.0, 1.0, len(E)), rng.uniform(-0.5, 1.0, len(E))
+
+
+def _check_blocks(rd, ro, ref_d, ref_o, label):
+    scale = max(1.0, np.abs(ref_d).max(), np.abs(ref_o).max() if ref_o.size else 0.0)
+    assert np.all(np.isfinite(rd)) and np.all(np.isfinite(ro)), label
+    dd = np.abs(rd - ref_d).max() / scale
+    do = (np.abs(ro - ref_o).max() / scale) if ro.size else 0.0
+    assert dd <= TOL and do <= TOL, f"{label}: rel |d rho_ii| {dd:.2e}, |d rho_i,i+1| {do:.2e}"
+
+
+def _check_trace_and_hermitian(rd, L, wL, wR, label):
+    tr = np.real(np.einsum("iaa->i", rd))
+    ref = np.einsum("e,ei->i", wL, L[:, 0, :]) + np.einsum("e,ei->i", wR, L[:, 1, :])
+    s = max(1.0, np.abs(ref).max())
+    assert np.abs(tr - ref).max() <= 1e-12 * s, f"{label}: trace {np.abs(tr - ref).max() / s:.2e}"
+    herm = np.abs(rd - np.swapaxes(rd.conj(), -1, -2)).max() / max(1.0, np.abs(rd).max())
+    assert herm <= 1e-12, f"{label}: rho_ii not Hermitian ({herm:.2e})"
+
+
+@pytest.mark.parametrize("case", small_cases.CASES, ids=lambda c: f"seed{c[0]}-N{c[1]}-m{c[2]}")
+def test_small_devices_against_oracle(gpu_lib, case):
+    dev = small_cases.device(*case)
+    E = small_cases.energies()
+    wL, wR = _weights(E, case[0])
+    ctx = _lib.context_for(dev, 0)
+    rd, ro, T, L, info, st = ctx.density_matrix(E, wL, wR, small_cases.ETA, want_ldos=True)
+    assert rd.shape == (dev.N, dev.m, dev.m) and ro.shape == (dev.N - 1, dev.m, dev.m)
+    ref_d, ref_o = density_matrix_blocks(dev, E, wL, wR, small_cases.ETA)
+    _check_blocks(rd, ro, ref_d, ref_o, f"seed{case[0]}")
+    _check_trace_and_hermitian(rd, L, wL, wR, f"seed{case[0]}")
+    T0, L0, _, _ = ctx.solve(E, small_cases.ETA, _lib.FP64)
+    assert np.abs(T - T0).max() <= 1e-13 and np.abs(L - L0).max() <= 1e-13 * max(1.0, np.abs(L0).max())
+
+
+def test_chunks_and_fewer_workgroups(gpu_lib):
+    """Energies split over several launches, and the accumulators capped
+    at one or three workgroups: the same blocks up to summation order."""
+    dev = small_cases.device(*small_cases.CASES[6])            # N=12, m=64, own blocks
+    E = np.linspace(-1.8, 1.7, 37)
+    wL, wR = _weights(E, 99)
+    ctx = _lib.context_for(dev, 0)
+    base_d, base_o = ctx.density_matrix(E, wL, wR, 1e-6)[:2]
+    per_wg = (2 * dev.N - 1) * 64 * 64 * 16
+    for opts in ({"energies_per_launch": 5}, {"density_matrix_bytes": per_wg},
+                 {"density_matrix_bytes": 3 * per_wg, "energies_per_launch": 7}):
+        c = _lib.context_for(dev, 0)
+        for k, v in opts.items():
+            c.set_option(k, v)
+        d, o = c.density_matrix(E, wL, wR, 1e-6)[:2]
+        s = max(1.0, np.abs(base_d).max())
+        assert np.abs(d - base_d).max() <= 1e-12 * s and np.abs(o - base_o).max() <= 1e-12 * s, opts
+        c.close()
+
+
+def test_repeatable_bitwise_and_linear(gpu_lib):
+    dev = small_cases.device(*small_cases.CASES[1])
+    E = np.linspace(-1.0, 1.0, 9)
+    wL, wR = _weights(E, 5)
+    ctx = _lib.context_for(dev, 0)
+    a = ctx.density_matrix(E, wL, wR, 1e-6)
+    b = ctx.density_matrix(E, wL, wR, 1e-6)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    l = ctx.density_matrix(E, wL, 0.0, 1e-6)
+    r = ctx.density_matrix(E, 0.0, wR, 1e-6)
+    s = max(1.0, np.abs(a[0]).max())
+    assert np.abs(l[0] + r[0] - a[0]).max() <= 1e-13 * s
+    assert np.abs(l[1] + r[1] - a[1]).max() <= 1e-13 * s
+
+
+def test_errors_and_empty(gpu_lib):
+    dev = small_cases.device(*small_cases.CASES[0])
+    ctx = _lib.Context(0)
+    with pytest.raises(_lib.QtxError) as ei:
+        ctx.N, ctx.m = dev.N, dev.m
+        ctx.density_matrix(np.zeros(2), 1.0, 1.0, 1e-6)
+    assert ei.value.status == _lib.ESTATE
+    _lib.fill(ctx, dev)
+    with pytest.raises(_lib.QtxError) as ei:
+        ctx.density_matrix(np.array([0.1, 0.2]), np.array([1.0, np.nan]), 1.0, 1e-6)
+    assert ei.value.status == _lib.EINVAL
+    with pytest.raises(_lib.QtxError) as ei:
+        ctx.density_matrix(np.array([0.1]), 1.0, 1.0, -1.0)
+    assert ei.value.status == _lib.EINVAL
+    ctx.set_option("density_matrix_bytes", 1000.0)
+    with pytest.raises(_lib.QtxError) as ei:
+        ctx.density_matrix(np.array([0.1]), 1.0, 1.0, 1e-6)
+    assert ei.value.status == _lib.ENOMEM
+    with pytest.raises(_lib.QtxError):
+        ctx.set_option("density_matrix_bytes", -1.0)
+    ctx.set_option("density_matrix_bytes", 1e9)
+    rd, ro, T, _, _, st = ctx.density_matrix(np.zeros(0), np.zeros(0), np.zeros(0), 1e-6)
+    assert st == _lib.OK and not rd.any() and not ro.any() and T.shape == (0,)
+
+
+def _cfg1_weights(E):
+    """Quadrature weights of the pattern h/3 (1, 4, 2, 4, ..., 1) on the
+    uniform grid times the Fermi occupations of the two contacts (muL = 0,
+    muR = -0.1 eV, kT = 25 meV)."""
+    h = E[1] - E[0]
+    q = np.full(len(E), 2.0)
+    q[1:-1:2] = 4.0
+    q[0] = q[-1] = 1.0
+    q *= h / 3.0
+    f = lambda x: 0.5 * (1.0 - np.tanh(0.5 * x / 0.025))
+    return q * f(E), q * f(E + 0.1)
+
+
+def test_cfg1_full_size(gpu_lib):
+    """N=200, m=64, 2048 energies in one call (the benchmark's launch).
+    With Simpson-Fermi weights on every energy: trace and Hermiticity.
+    With weights on 6 sampled energies only and zero elsewhere (same
+    launch): the blocks against the oracle's sum over those energies."""
+    wl = W.config1()
+    dev = wl.device
+    ctx = _lib.context_for(dev, 0)
+    wL, wR = _cfg1_weights(wl.E)
+    rd, ro, T, L, info, st = ctx.density_matrix(wl.E, wL, wR, wl.eta, want_ldos=True)
+    assert st == _lib.OK
+    _check_trace_and_hermitian(rd, L, wL, wR, "cfg1")
+    rng = np.random.default_rng(4321)
+    idx = np.sort(np.concatenate([[0, len(wl.E) - 1], rng.choice(len(wl.E), 4, replace=False)]))
+    sL = np.zeros(len(wl.E))
+    sR = np.zeros(len(wl.E))
+    sL[idx] = rng.uniform(0.2, 1.0, len(idx))
+    sR[idx] = rng.uniform(0.2, 1.0, len(idx))
+    rd_s, ro_s = ctx.density_matrix(wl.E, sL, sR, wl.eta)[:2]
+    ref_d, ref_o = density_matrix_blocks(dev, wl.E[idx], sL[idx], sR[idx], wl.eta)
+    _check_blocks(rd_s, ro_s, ref_d, ref_o, "cfg1 sampled")
