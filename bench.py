@@ -39,6 +39,7 @@ def flops_per_energy(N, m, n_dec):
 
 KERNEL_SOURCES = ("paper_1903_00548_amd/csrc/qtx_kernels.hip", "paper_1903_00548_amd/csrc/qtx_device.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_cfg1_fp64_hbm_traffic.md")
+TRAFFIC_FILE_DM = os.path.join(ROOT, "profiles", "k_sweep_density_matrix_cfg1.md")
 
 
 def kernel_source_sha1():
@@ -49,12 +50,12 @@ def kernel_source_sha1():
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per sweep launch from the committed rocprofv3 counter
+def measured_traffic(path=TRAFFIC_FILE):
+    """HBM bytes per sweep launch from a committed rocprofv3 counter
     summary, or None when it is missing or was taken on other kernel
     sources."""
     try:
-        txt = open(TRAFFIC_FILE).read()
+        txt = open(path).read()
     except OSError:
         return None
     vals = dict(line.split(":", 1) for line in txt.splitlines() if ":" in line and not line.startswith("#"))
@@ -323,7 +324,7 @@ def bench_density_matrix(args):
         "config": {"workload": "cfg1_N200_m64_E2048_density_matrix", "N": N, "m": m, "energies_per_step": nE,
                    "eta": wl.eta, "muL": 0.0, "muR": -0.1, "kT": 0.025},
         "roofline": {"bound": "mfma", "achieved": ach, "peak": PEAK["fp64"], "unit": "TFLOP/s",
-                     "frac": ach / PEAK["fp64"], "traffic": None,
+                     "frac": ach / PEAK["fp64"], "traffic": measured_traffic(TRAFFIC_FILE_DM),
                      "kernel": "k_sweep density-matrix variant (sweeps + rho_ii, rho_i,i+1 products)"},
         "cpu_baseline": cpu,
         "sweep_kernel_ms_per_step": sweep_ms / args.steps, "decimation_kernel_ms_per_step": dec_ms / args.steps,
