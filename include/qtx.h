@@ -184,11 +184,14 @@ qtx_status qtx_density_matrix_device(qtx_ctx* ctx, const double* E_dev, const do
                                      double* T_dev, double* ldos_dev, qtx_info* info_dev);
 
 /* Self-energies and broadening factors alone (the decimation step of the
- * solve, exposed for verification).  Host buffers:
+ * solve, or the complex band structure with option self_energy_method 1;
+ * exposed for verification).  Host buffers:
  *   sigma[nE*2*m*m]  Sigma_L then Sigma_R per energy (row-major, m x m);
- *   wfac[nE*2*m*m]   or NULL: W with Gamma = W diag(sgn) W^H per side;
- *   sgn[nE*2*m]      or NULL: the signs (+1, -1, or 0 for unused columns).
- *   iters[nE]        or NULL: doublings used. */
+ *   wfac[nE*2*m*m]   or NULL: W with Gamma = W diag(sgn) W^H per side
+ *                    (method 1: the flux-normalised injection of the
+ *                    incoming travelling modes, one per column);
+ *   sgn[nE*2*m]      or NULL: the signs (+1, -1, or 0 for unused columns);
+ *   iters[nE]        or NULL: doublings used (method 1: QR iterations). */
 qtx_status qtx_self_energy(qtx_ctx* ctx, const double* E, int nE, double eta,
                            qtx_c128* sigma, qtx_c128* wfac, double* sgn, int* iters);
 
@@ -220,6 +223,25 @@ qtx_status qtx_self_energy(qtx_ctx* ctx, const double* E, int nE, double eta,
  *                           replaced oldest first, never one the current
  *                           call uses); 0 disables the cache.  Changing eta
  *                           or a decimation option empties it;
+ *   "self_energy_method"    0 or 1        0      how the lead self-energies
+ *                           and the injection are obtained: 0 by decimation
+ *                           at z = E + i eta with the full broadening
+ *                           injected; 1 from the complex band structure of
+ *                           each lead (the direct method of Sec. "Contact
+ *                           self-energies": eq. linearized_eigenvalue_symmetric,
+ *                           the Hellmann-Feynman split, Sigma = [H' - E M']
+ *                           B Lambda B^-1) with only the incoming travelling
+ *                           modes injected, flux-normalised (eq. qtbm_system,
+ *                           the paper's mode-space QTBM).  Method 1 solves at
+ *                           eta = 0 exactly (other eta: QTX_EINVAL), with
+ *                           QTX_FP64 (QTX_MIXED: QTX_EINVAL), for qtx_solve,
+ *                           qtx_solve_device, qtx_self_energy and
+ *                           qtx_density_matrix; qtx_solve_batch rejects it.
+ *                           It needs H01 - E S01 invertible at every energy
+ *                           (else the energy is flagged QTX_FLAG_DEC_NOTCONV);
+ *                           qtx_info.dec_iters then counts QR iterations;
+ *   "mode_tol"              (0, 1e-2]     1e-8   method 1: modes with
+ *                           ||lambda| - 1| <= mode_tol travel;
  *   "density_matrix_bytes"  [0, 1e13]     64 GiB device memory for the
  *                           per-workgroup accumulators of qtx_density_matrix
  *                           (fewer workgroups run when they do not all fit);

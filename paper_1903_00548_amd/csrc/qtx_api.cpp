@@ -70,6 +70,9 @@ struct qtx_ctx {
   DevBuf redo, elist, ecount;                  // mixed: energies re-solved in FP64
   DevBuf dmw, rho, dmout;                      // density-matrix blocks: weights, accumulators, sums
   double dm_bytes = 64.0 * (1ull << 30);       // cap on the per-workgroup accumulators
+  int se_method = 0;                           // 0 decimation, 1 complex band structure (mode space)
+  double mode_tol = 1e-8;                      // |lambda| tolerance of travelling modes
+  DevBuf mscr;                                 // complex-band-structure workspace
 
   uint64_t lead_hash[2] = {0, 0};
 
@@ -214,11 +217,39 @@ qtx::Prob make_prob(const qtx_ctx* c) {
   return P;
 }
 
-// decimation for energies E_dev[0..nE) into ctx->sig / wf / sgn / iters
+// The complex-band-structure self-energies are defined at eta = 0 and feed
+// the FP64 sweep only.
+qtx_status check_method(qtx_ctx* c, double eta, bool mixed) {
+  if (c->se_method != 1) return QTX_OK;
+  if (eta != 0.0) return fail(c, QTX_EINVAL, "self_energy_method 1 (complex band structure) solves at eta = 0");
+  if (mixed) return fail(c, QTX_EINVAL, "self_energy_method 1 runs with QTX_FP64 only");
+  return QTX_OK;
+}
+
+// lead self-energies, injection factors and signs for energies E_dev[0..nE)
+// into ctx->sig / wf / sgn / iters / nheavy: by decimation, or from the
+// complex band structure of the leads (option self_energy_method)
 qtx_status stage_decimate(qtx_ctx* c, const double* E_dev, int nE, double eta, bool mixed) {
   const int M = c->M;
   const size_t MM = (size_t)M * M;
   const int sides = leads_identical(c) ? 1 : 2;
+  if (c->se_method == 1) {
+    qtx_status s = check_method(c, eta, mixed);
+    if (s != QTX_OK) return s;
+    const int grid = std::max(1, std::min(nE * sides, c->num_cu * 4));
+    QTX_HIP(c, c->sig.ensure((size_t)nE * 2 * MM * sizeof(double2)));
+    QTX_HIP(c, c->wf.ensure((size_t)nE * 2 * MM * sizeof(double2)));
+    QTX_HIP(c, c->sgn.ensure((size_t)nE * 2 * M * sizeof(double)));
+    QTX_HIP(c, c->iters.ensure((size_t)nE * 2 * sizeof(int)));
+    QTX_HIP(c, c->nheavy.ensure((size_t)nE * 2 * sizeof(int)));
+    QTX_HIP(c, c->mscr.ensure((size_t)grid * qtx::modes_ws_elems(M) * sizeof(double2)));
+    QTX_HIP(c, record(c, c->ev_dec, c->n_dec));
+    QTX_HIP(c, qtx::run_modes(M, make_prob(c), E_dev, nE, eta, sides, c->mode_tol, c->m, c->mscr.as<double2>(), grid,
+                              c->sig.as<double2>(), c->wf.as<double2>(), c->sgn.as<double>(), c->iters.as<int>(),
+                              c->nheavy.as<int>(), c->stream));
+    QTX_HIP(c, record(c, c->ev_dec, c->n_dec));
+    return QTX_OK;
+  }
   const int grid = std::max(1, std::min(nE * sides, c->num_cu * wgs_per_cu(c, M, mixed)));
   QTX_HIP(c, c->sig.ensure((size_t)nE * 2 * MM * sizeof(double2)));
   QTX_HIP(c, c->wf.ensure((size_t)nE * 2 * MM * sizeof(double2)));
@@ -244,6 +275,8 @@ qtx_status solve_device_core(qtx_ctx* c, const double* E_dev, int nE, double eta
   if (!E_dev || !T_dev) return fail(c, QTX_EINVAL, "E and T must not be NULL");
   if (prec != QTX_FP64 && prec != QTX_MIXED) return fail(c, QTX_EINVAL, "precision must be QTX_FP64 or QTX_MIXED");
   const bool mixed = (prec == QTX_MIXED);
+  s = check_method(c, eta, mixed);
+  if (s != QTX_OK) return s;
   const int M = c->M, N = c->N;
   for (int e0 = 0; e0 < nE; e0 += c->chunk) {
     const int ne = std::min(c->chunk, nE - e0);
@@ -308,6 +341,8 @@ qtx_status density_matrix_core(qtx_ctx* c, const double* E_dev, const double* wL
   if (nE < 0 || !(eta >= 0.0)) return fail(c, QTX_EINVAL, "nE must be >= 0 and eta >= 0");
   const int N = c->N, m = c->m, M = c->M;
   if (!out_d || (N > 1 && !out_o)) return fail(c, QTX_EINVAL, "rho_diag (and rho_off when N > 1) must not be NULL");
+  s = check_method(c, eta, false);
+  if (s != QTX_OK) return s;
   const size_t mm = (size_t)m * m, nblk = 2 * (size_t)N - 1;
   if (nE == 0) {
     QTX_HIP(c, hipMemsetAsync(out_d, 0, (size_t)N * mm * sizeof(double2), c->stream));
@@ -634,6 +669,7 @@ qtx_status qtx_self_energy(qtx_ctx* c, const double* E, int nE, double eta, qtx_
   if (nE == 0) return QTX_OK;
   if (!E || !sigma) return fail(c, QTX_EINVAL, "E and sigma must not be NULL");
   if (!c->lead_set[0] || !c->lead_set[1]) return fail(c, QTX_ESTATE, "both leads must be set");
+  if (check_method(c, eta, false) != QTX_OK) return QTX_EINVAL;
   hipSetDevice(c->device);
   const int m = c->m, M = c->M;
   const size_t MM = (size_t)M * M;
@@ -741,6 +777,12 @@ qtx_status qtx_set_option(qtx_ctx* c, const char* name, double value) {
   } else if (n == "density_matrix_bytes") {
     if (!(value >= 0.0 && value <= 1e13)) return fail(c, QTX_EINVAL, "density_matrix_bytes must be in [0, 1e13]");
     c->dm_bytes = value;
+  } else if (n == "self_energy_method") {
+    if (!(value == 0.0 || value == 1.0)) return fail(c, QTX_EINVAL, "self_energy_method must be 0 or 1");
+    c->se_method = (int)value;
+  } else if (n == "mode_tol") {
+    if (!(value > 0.0 && value <= 1e-2)) return fail(c, QTX_EINVAL, "mode_tol must be in (0, 1e-2]");
+    c->mode_tol = value;
   } else if (n == "energies_per_launch") {
     if (!integral || value < 1 || value > (1 << 20)) return fail(c, QTX_EINVAL, "energies_per_launch must be in [1, 2^20]");
     c->chunk = (int)value;
@@ -766,6 +808,9 @@ qtx_status qtx_problem_create(qtx_ctx* parent, qtx_ctx** problem) {
   c->refine_max = parent->refine_max;
   c->heavy_tol = parent->heavy_tol;
   c->use_graph = parent->use_graph;
+  c->dm_bytes = parent->dm_bytes;
+  c->se_method = parent->se_method;
+  c->mode_tol = parent->mode_tol;
   c->stream = parent->stream;
   c->own_stream = false;
   c->parent = parent;
@@ -906,6 +951,9 @@ qtx_status qtx_solve_batch(qtx_ctx* c, int nprob, qtx_ctx* const* probs, const d
     for (int e = 0; e < nE[p]; ++e)
       if (!std::isfinite(E[p][e])) return fail(c, QTX_EINVAL, "energies must be finite");
   }
+  for (int p = 0; p < nprob; ++p)
+    if (probs[p]->se_method != 0 || c->se_method != 0)
+      return fail(c, QTX_EINVAL, "batched solves use the decimation (self_energy_method 0)");
   hipSetDevice(c->device);
   const bool mixed = (prec == QTX_MIXED);
 

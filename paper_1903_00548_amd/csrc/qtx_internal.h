@@ -150,6 +150,17 @@ hipError_t run_sweep_dm(int M, const Prob& P, const SweepArgs& a, int grid, hipS
 hipError_t run_dm_reduce(const double2* rho, int nwg, size_t stride, int N, int M, int m, double2* out_d,
                          double2* out_o, hipStream_t st);
 
+// Self-energies, injection factors and signs from the complex band
+// structure of the leads (the decimation's outputs, same layout) for nE
+// energies; sides = 1 when both leads are the same.  m: physical block
+// size; tol: |lambda| tolerance of travelling modes at eta = 0.  scratch:
+// grid * modes_ws_elems(M) complex doubles.  iters: QR iterations per
+// surface, -1 on failure.
+hipError_t run_modes(int M, const Prob& P, const double* E, int nE, double eta, int sides, double tol, int m,
+                     double2* scratch, int grid, double2* sig, double2* wf, double* sgn, int* iters, int* nheavy,
+                     hipStream_t st);
+inline size_t modes_ws_elems(int M) { return 16 * (size_t)M * M; }
+
 // Band energies of one lead (padded blocks, physical size m) at nk Bloch
 // phases: E[q * m + n] = E_n(k_q) + V.  work: grid * 2 M (M + 1) complex
 // doubles when M > 64 (else unused).

@@ -1,0 +1,524 @@
+// Contact self-energies and mode-space injection from the complex band
+// structure of the leads (Sec. "Contact self-energies", the direct method):
+//
+//   1. the quadratic eigenvalue problem (L lambda^-1 + D0 + lambda U) c = 0
+//      of a lead (A = zS - H convention: D0 = z S00 - H00, U = z S01 - H01,
+//      L = z S01^H - H01^H) in the symmetric linearisation of
+//      eq. linearized_eigenvalue_symmetric, [[D0, L], [U, 0]] x =
+//      lambda [[-U, 0], [0, U]] x with x = [lambda c; c], brought to the
+//      standard problem C x = lambda x by the block-diagonal right-hand
+//      matrix: C = [[-U^-1 D0, -U^-1 L], [I, 0]];
+//   2. all 2m eigenpairs of C: Householder reduction to Hessenberg form,
+//      complex single-shift QR (Wilkinson shifts, Givens bulge chase) to
+//      the Schur form T = Q^H C Q, eigenvectors of T by back substitution,
+//      x = Q y;
+//   3. the mode split of eq. hellmann-feynman: at eta = 0 a mode with
+//      ||lambda| - 1| <= tol travels, in the direction of the sign of its
+//      flux J = 2 Im(lambda c^H U c) (the numerator of the generalised
+//      Hellmann-Feynman velocity); other modes decay to the right iff
+//      |lambda| < 1; at eta > 0 the split is |lambda| < 1 alone;
+//   4. Sigma_R = -U B+ Lambda+ B+^-1 and Sigma_L = -L B- Lambda-^-1 B-^-1
+//      from the right- and left-going Bloch matrices;
+//   5. injection of the incoming travelling modes only, eq. qtbm_system with
+//      B_gamma = (-L lambda^-1 - Sigma_L) c (source) or
+//      (-U lambda - Sigma_R) c (drain), each scaled by 1/sqrt|J_gamma|.
+//      With modes normalised as in eq. normalization and g = 2/|v| this
+//      is the same injection: sum_gamma W_gamma W_gamma^H = Gamma at eta = 0,
+//      so the sweep takes W with signs +1 (and 0 on unused columns).
+//
+// One workgroup per (energy, lead) job, the matrices in its global
+// workspace (16 M^2 complex doubles).  The outputs have the layout of the
+// decimation's: Sigma, W (padded M x M), signs (M), iteration count (the QR
+// iterations; -1 if the QR did not converge, a matrix was singular or the
+// split did not give m modes each way).
+#include "qtx_device.h"
+#include "qtx_internal.h"
+
+namespace qtx {
+namespace {
+
+typedef cpx<double> cd;
+
+__device__ __forceinline__ void sto(double2* p, cd v) { *p = make_double2(v.re, v.im); }
+__device__ __forceinline__ cd cdivx(cd a, cd b) {
+  // a / b with IEEE division (used where accuracy matters more than speed)
+  const double s = fabs(b.re) + fabs(b.im);
+  const double br = b.re / s, bi = b.im / s, ar = a.re / s, ai = a.im / s;
+  const double d = br * br + bi * bi;
+  return mk<double>((ar * br + ai * bi) / d, (ai * br - ar * bi) / d);
+}
+__device__ __forceinline__ double cabsx(cd a) { return hypot(a.re, a.im); }
+__device__ __forceinline__ cd csqrtx(cd z) {
+  const double r = cabsx(z);
+  if (r == 0.0) return mk<double>(0.0, 0.0);
+  const double a = sqrt(0.5 * (r + fabs(z.re)));
+  if (z.re >= 0.0) return mk<double>(a, z.im / (2.0 * a));
+  return mk<double>(fabs(z.im) / (2.0 * a), z.im >= 0.0 ? a : -a);
+}
+__device__ __forceinline__ cd cscl(cd a, double s) { return mk<double>(a.re * s, a.im * s); }
+
+// Inverse of the n x n matrix in columns [0, n) of A (row stride ld) by
+// Gauss-Jordan elimination with partial pivoting on [A | I]; the inverse is
+// left in columns [n, 2n).  fcol: n complex values of LDS.  Returns false
+// (uniformly) if a pivot is zero or not finite.
+__device__ bool gj_invert(double2* A, int n, int ld, cd* fcol, double* sd, int* si) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  for (int idx = t; idx < n * n; idx += NT) {
+    const int r = idx / n, c = idx - r * n;
+    A[(size_t)r * ld + n + c] = make_double2(r == c ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    if (w == 0) {
+      double best = -1.0;
+      int bi = k;
+      for (int i = k + lane; i < n; i += 64) {
+        const double a = cabs1(ldd(A + (size_t)i * ld + k));
+        if (a > best) { best = a; bi = i; }
+      }
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) {
+        const double ob = __shfl_xor(best, off, 64);
+        const int oi = __shfl_xor(bi, off, 64);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
+      if (lane == 0) { si[0] = bi; sd[0] = best; }
+    }
+    __syncthreads();
+    const int p = si[0];
+    const double pv = sd[0];
+    if (!(pv > 0.0) || !isfinite(pv)) return false;
+    if (p != k)
+      for (int j = t; j < 2 * n; j += NT) {
+        const double2 a = A[(size_t)k * ld + j];
+        A[(size_t)k * ld + j] = A[(size_t)p * ld + j];
+        A[(size_t)p * ld + j] = a;
+      }
+    __syncthreads();
+    for (int i = t; i < n; i += NT) fcol[i] = ldd(A + (size_t)i * ld + k);
+    __syncthreads();
+    const cd pinv = cdivx(mk<double>(1.0, 0.0), fcol[k]);
+    for (int j = t; j < 2 * n; j += NT) sto(A + (size_t)k * ld + j, cmul(pinv, ldd(A + (size_t)k * ld + j)));
+    __syncthreads();
+    for (int idx = t; idx < n * 2 * n; idx += NT) {
+      const int i = idx / (2 * n), j = idx - i * 2 * n;
+      if (i == k) continue;
+      const cd f = fcol[i];
+      sto(A + (size_t)i * ld + j, cfms(ldd(A + (size_t)i * ld + j), f, ldd(A + (size_t)k * ld + j)));
+    }
+    __syncthreads();
+  }
+  return true;
+}
+
+struct ModeShared {
+  cd vec[256];          // Householder vector / Gauss-Jordan factor column
+  cd lam[256];          // eigenvalues
+  double J[256];        // fluxes
+  int kind[256];        // 1 right-going, 0 left-going; +2 if travelling
+  int ridx[128], lidx[128];
+  double sd[4];
+  int si[8];
+};
+
+}  // namespace
+
+template <int M>
+__global__ __launch_bounds__(NT) void k_modes(Prob P, const double* E, int nE, double eta, int sides, double tol,
+                                              int m, double2* ws, double2* sig, double2* wf, double* sgn,
+                                              int* iters, int* nheavy) {
+  constexpr int LD = 2 * M, MM = M * M;
+  constexpr size_t WS = 16 * (size_t)M * M;
+  __shared__ ModeShared sh;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int n = 2 * m;
+  double2* Cm = ws + (size_t)blockIdx.x * WS;   // C, then its Schur form T (n x n, stride LD)
+  double2* Qm = Cm + 4 * (size_t)MM;           // Schur vectors
+  double2* Yv = Qm + 4 * (size_t)MM;           // [D0 | L], then eigenvectors of T, then products
+  double2* Ui = Yv + 4 * (size_t)MM;           // Gauss-Jordan work (m x 2m)
+  double2* Cv = Ui + 2 * (size_t)MM;           // mode vectors c (m x n)
+  const int njobs = nE * sides;
+  const double eps = 2.220446049250313e-16;
+  for (int job = blockIdx.x; job < njobs; job += gridDim.x) {
+    const int e = job / sides;
+    const int side = sides == 2 ? job - 2 * e : -1;       // -1: both surfaces from the left lead
+    const double2* lead = side == 1 ? P.leadR : P.leadL;
+    const double V = side == 1 ? P.VR : P.VL;
+    const cd zx = mk<double>(E[e] - V, eta);
+    const double2* H00 = lead;
+    const double2* H01 = lead + MM;
+    const double2* S00 = lead + 2 * MM;
+    const double2* S01 = lead + 3 * MM;
+    auto Uel = [&](int r, int c) {             // z S01 - H01
+      const cd s = ldd(S01 + r * M + c), h = ldd(H01 + r * M + c);
+      return mk<double>(zx.re * s.re - zx.im * s.im - h.re, zx.re * s.im + zx.im * s.re - h.im);
+    };
+    auto Lel = [&](int r, int c) {             // z S01^H - H01^H
+      const cd s = ldd(S01 + c * M + r), h = ldd(H01 + c * M + r);
+      return mk<double>(zx.re * s.re + zx.im * s.im - h.re, zx.im * s.re - zx.re * s.im + h.im);
+    };
+    auto D0el = [&](int r, int c) {            // z S00 - H00
+      const cd s = ldd(S00 + r * M + c), h = ldd(H00 + r * M + c);
+      return mk<double>(zx.re * s.re - zx.im * s.im - h.re, zx.re * s.im + zx.im * s.re - h.im);
+    };
+    bool ok = true;
+    int total = 0;
+    __syncthreads();
+    // ---- 1. C = [[-U^-1 D0, -U^-1 L], [I, 0]]
+    for (int idx = t; idx < m * m; idx += NT) {
+      const int r = idx / m, c = idx - r * m;
+      sto(Ui + (size_t)r * LD + c, Uel(r, c));
+      sto(Yv + (size_t)r * LD + c, D0el(r, c));
+      sto(Yv + (size_t)r * LD + m + c, Lel(r, c));
+    }
+    __syncthreads();
+    ok = gj_invert(Ui, m, LD, sh.vec, sh.sd, sh.si);
+    if (ok) {
+      for (int idx = t; idx < m * n; idx += NT) {
+        const int r = idx / n, c = idx - r * n;
+        cd s = mk<double>(0.0, 0.0);
+        for (int j = 0; j < m; ++j) s = cadd(s, cmul(ldd(Ui + (size_t)r * LD + m + j), ldd(Yv + (size_t)j * LD + c)));
+        sto(Cm + (size_t)r * LD + c, mk<double>(-s.re, -s.im));
+        sto(Cm + (size_t)(m + r) * LD + c, mk<double>(c == r ? 1.0 : 0.0, 0.0));
+      }
+      for (int idx = t; idx < n * n; idx += NT) {
+        const int r = idx / n, c = idx - r * n;
+        sto(Qm + (size_t)r * LD + c, mk<double>(r == c ? 1.0 : 0.0, 0.0));
+      }
+      __syncthreads();
+      // ---- 2a. Hessenberg form C <- P C P, Q <- Q P, P = I - g u u^H
+      for (int k = 0; k + 2 < n; ++k) {
+        if (w == 0) {
+          double a2 = 0.0;
+          for (int i = k + 1 + lane; i < n; i += 64) {
+            const cd x = ldd(Cm + (size_t)i * LD + k);
+            a2 += x.re * x.re + x.im * x.im;
+            sh.vec[i] = x;
+          }
+          a2 = wave_sum(a2);
+          if (lane == 0) {
+            const double al = sqrt(a2);
+            const cd x0 = ldd(Cm + (size_t)(k + 1) * LD + k);
+            const double ax0 = cabsx(x0);
+            const cd ph = ax0 > 0.0 ? mk<double>(x0.re / ax0, x0.im / ax0) : mk<double>(1.0, 0.0);
+            sh.vec[k + 1] = cadd(x0, cscl(ph, al));
+            sh.sd[0] = al > 0.0 ? 1.0 / (al * (al + ax0)) : 0.0;
+            sh.sd[1] = -ph.re * al;
+            sh.sd[2] = -ph.im * al;
+          }
+        }
+        __syncthreads();
+        const double g = sh.sd[0];
+        if (g != 0.0) {
+          // from the left, rows k+1..n-1: thread per column j >= k
+          for (int j = k + t; j < n; j += NT) {
+            cd s = mk<double>(0.0, 0.0);
+            for (int i = k + 1; i < n; ++i) s = cadd(s, cmul(cconj(sh.vec[i]), ldd(Cm + (size_t)i * LD + j)));
+            s = cscl(s, g);
+            if (j == k) {
+              sto(Cm + (size_t)(k + 1) * LD + k, mk<double>(sh.sd[1], sh.sd[2]));
+              for (int i = k + 2; i < n; ++i) sto(Cm + (size_t)i * LD + k, mk<double>(0.0, 0.0));
+            } else {
+              for (int i = k + 1; i < n; ++i)
+                sto(Cm + (size_t)i * LD + j, cfms(ldd(Cm + (size_t)i * LD + j), sh.vec[i], s));
+            }
+          }
+          __syncthreads();
+          // from the right, columns k+1..n-1: thread per row, C and Q
+          for (int i = t; i < n; i += NT) {
+            cd s = mk<double>(0.0, 0.0), q = mk<double>(0.0, 0.0);
+            for (int j = k + 1; j < n; ++j) {
+              s = cadd(s, cmul(ldd(Cm + (size_t)i * LD + j), sh.vec[j]));
+              q = cadd(q, cmul(ldd(Qm + (size_t)i * LD + j), sh.vec[j]));
+            }
+            s = cscl(s, g);
+            q = cscl(q, g);
+            for (int j = k + 1; j < n; ++j) {
+              const cd uc = cconj(sh.vec[j]);
+              sto(Cm + (size_t)i * LD + j, cfms(ldd(Cm + (size_t)i * LD + j), s, uc));
+              sto(Qm + (size_t)i * LD + j, cfms(ldd(Qm + (size_t)i * LD + j), q, uc));
+            }
+          }
+        }
+        __syncthreads();
+      }
+      // ---- 2b. Schur form by single-shift QR with Givens bulge chasing
+      const int maxit = 30 * n;
+      int hi = n - 1, its = 0;
+      while (hi > 0) {
+        if (w == 0) {
+          int found = 0;
+          for (int l = 1 + lane; l <= hi; l += 64) {
+            const double h = cabs1(ldd(Cm + (size_t)l * LD + l - 1));
+            const double tst = cabs1(ldd(Cm + (size_t)(l - 1) * LD + l - 1)) + cabs1(ldd(Cm + (size_t)l * LD + l));
+            if (h <= eps * tst || h == 0.0) found = l > found ? l : found;
+          }
+#pragma unroll
+          for (int off = 32; off >= 1; off >>= 1) {
+            const int o = __shfl_xor(found, off, 64);
+            found = o > found ? o : found;
+          }
+          if (lane == 0) {
+            sh.si[1] = found;
+            if (found > 0) sto(Cm + (size_t)found * LD + found - 1, mk<double>(0.0, 0.0));
+          }
+        }
+        __syncthreads();
+        const int l = sh.si[1];
+        if (l == hi) {
+          --hi;
+          its = 0;
+          __syncthreads();      // every thread has read the deflation index
+          continue;
+        }
+        if (++total > maxit) {
+          ok = false;
+          break;
+        }
+        ++its;
+        // shift: the eigenvalue of the trailing 2 x 2 block nearer its corner
+        const cd a = ldd(Cm + (size_t)(hi - 1) * LD + hi - 1), b = ldd(Cm + (size_t)(hi - 1) * LD + hi);
+        const cd c = ldd(Cm + (size_t)hi * LD + hi - 1), d = ldd(Cm + (size_t)hi * LD + hi);
+        cd sigma;
+        if (its % 10 == 0) {
+          sigma = mk<double>(d.re + 0.75 * fabs(c.re), d.im);     // exceptional shift
+        } else {
+          const cd hm = cscl(csub(a, d), 0.5);
+          const cd r = csqrtx(cadd(cmul(hm, hm), cmul(b, c)));
+          const cd mid = cscl(cadd(a, d), 0.5);
+          const cd s1 = cadd(mid, r), s2 = csub(mid, r);
+          sigma = cabs1(csub(s1, d)) <= cabs1(csub(s2, d)) ? s1 : s2;
+        }
+        __syncthreads();        // every thread has read the 2 x 2 block
+        for (int k = l; k < hi; ++k) {
+          cd x, y;
+          if (k == l) {
+            x = csub(ldd(Cm + (size_t)l * LD + l), sigma);
+            y = ldd(Cm + (size_t)(l + 1) * LD + l);
+          } else {
+            x = ldd(Cm + (size_t)k * LD + k - 1);
+            y = ldd(Cm + (size_t)(k + 1) * LD + k - 1);
+          }
+          const double ax = cabsx(x), ay = cabsx(y), r = hypot(ax, ay);
+          double cs = 1.0;
+          cd sn = mk<double>(0.0, 0.0);
+          if (r > 0.0) {
+            if (ax == 0.0) {
+              cs = 0.0;
+              sn = mk<double>(y.re / ay, -y.im / ay);
+            } else {
+              cs = ax / r;
+              const cd ph = mk<double>(x.re / ax, x.im / ax);
+              sn = cscl(cmul(ph, cconj(y)), 1.0 / r);
+            }
+          }
+          __syncthreads();      // every thread has read x, y
+          // rows k, k+1 from the left by G = [[c, s], [-conj(s), c]]
+          const int j0 = k == l ? l : k - 1;
+          for (int j = j0 + t; j < n; j += NT) {
+            const cd p = ldd(Cm + (size_t)k * LD + j), q = ldd(Cm + (size_t)(k + 1) * LD + j);
+            cd np = cadd(cscl(p, cs), cmul(sn, q));
+            cd nq = csub(cscl(q, cs), cmul(cconj(sn), p));
+            if (j == k - 1 && k > l) nq = mk<double>(0.0, 0.0);
+            sto(Cm + (size_t)k * LD + j, np);
+            sto(Cm + (size_t)(k + 1) * LD + j, nq);
+          }
+          __syncthreads();
+          // columns k, k+1 from the right by G^H, and the Schur vectors
+          const int i1 = k + 2 < hi ? k + 2 : hi;
+          for (int i = t; i < n; i += NT) {
+            if (i <= i1) {
+              const cd p = ldd(Cm + (size_t)i * LD + k), q = ldd(Cm + (size_t)i * LD + k + 1);
+              sto(Cm + (size_t)i * LD + k, cadd(cscl(p, cs), cmul(cconj(sn), q)));
+              sto(Cm + (size_t)i * LD + k + 1, csub(cscl(q, cs), cmul(sn, p)));
+            }
+            const cd p = ldd(Qm + (size_t)i * LD + k), q = ldd(Qm + (size_t)i * LD + k + 1);
+            sto(Qm + (size_t)i * LD + k, cadd(cscl(p, cs), cmul(cconj(sn), q)));
+            sto(Qm + (size_t)i * LD + k + 1, csub(cscl(q, cs), cmul(sn, p)));
+          }
+          __syncthreads();
+        }
+      }
+    }
+    __syncthreads();
+    // ---- 2c. eigenvectors of T (thread per eigenvalue), then c = (Q y) rows m..2m-1
+    if (ok) {
+      for (int k = t; k < n; k += NT) {
+        const cd lk = ldd(Cm + (size_t)k * LD + k);
+        sh.lam[k] = lk;
+        const double smin = fmax(eps * cabs1(lk), 1e-290);
+        for (int i = k + 1; i < n; ++i) sto(Yv + (size_t)i * LD + k, mk<double>(0.0, 0.0));
+        sto(Yv + (size_t)k * LD + k, mk<double>(1.0, 0.0));
+        double big = 1.0;
+        for (int i = k - 1; i >= 0; --i) {
+          cd s = mk<double>(0.0, 0.0);
+          for (int j = i + 1; j <= k; ++j) s = cadd(s, cmul(ldd(Cm + (size_t)i * LD + j), ldd(Yv + (size_t)j * LD + k)));
+          cd dd = csub(ldd(Cm + (size_t)i * LD + i), lk);
+          if (cabs1(dd) < smin) dd = mk<double>(smin, 0.0);
+          const cd y = cdivx(mk<double>(-s.re, -s.im), dd);
+          sto(Yv + (size_t)i * LD + k, y);
+          big = fmax(big, cabs1(y));
+          if (big > 1e150) {                  // rescale the partial vector
+            for (int q = i; q <= k; ++q) sto(Yv + (size_t)q * LD + k, cscl(ldd(Yv + (size_t)q * LD + k), 1e-150));
+            big *= 1e-150;
+          }
+        }
+      }
+      __syncthreads();
+      for (int idx = t; idx < m * n; idx += NT) {
+        const int r = idx / n, k = idx - r * n;
+        cd s = mk<double>(0.0, 0.0);
+        for (int j = 0; j <= k; ++j) s = cadd(s, cmul(ldd(Qm + (size_t)(m + r) * LD + j), ldd(Yv + (size_t)j * LD + k)));
+        sto(Cv + (size_t)r * LD + k, s);
+      }
+      __syncthreads();
+      // ---- 3. unit mode vectors, fluxes and the split
+      for (int k = t; k < n; k += NT) {
+        double nn = 0.0;
+        for (int r = 0; r < m; ++r) {
+          const cd v = ldd(Cv + (size_t)r * LD + k);
+          nn += v.re * v.re + v.im * v.im;
+        }
+        const double sc = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
+        for (int r = 0; r < m; ++r) sto(Cv + (size_t)r * LD + k, cscl(ldd(Cv + (size_t)r * LD + k), sc));
+        cd q = mk<double>(0.0, 0.0);                   // c^H U c
+        for (int r = 0; r < m; ++r) {
+          cd uc = mk<double>(0.0, 0.0);
+          for (int j = 0; j < m; ++j) uc = cadd(uc, cmul(Uel(r, j), ldd(Cv + (size_t)j * LD + k)));
+          q = cadd(q, cmul(cconj(ldd(Cv + (size_t)r * LD + k)), uc));
+        }
+        const cd lk = sh.lam[k];
+        const double J = 2.0 * cmul(lk, q).im;
+        const double al = cabsx(lk);
+        int kind;
+        if (eta > 0.0) {
+          kind = al < 1.0 ? 1 : 0;
+        } else {
+          const bool trav = fabs(al - 1.0) <= tol;
+          kind = trav ? (J > 0.0 ? 3 : 2) : (al < 1.0 ? 1 : 0);
+        }
+        sh.J[k] = J;
+        sh.kind[k] = (nn > 0.0 && isfinite(nn)) ? kind : -1;
+      }
+      __syncthreads();
+      if (t == 0) {
+        int nr = 0, nl = 0, bad = 0;
+        for (int k = 0; k < n; ++k) {
+          const int kd = sh.kind[k];
+          if (kd < 0) { bad = 1; continue; }
+          if (kd & 1) { if (nr < m) sh.ridx[nr] = k; ++nr; }
+          else { if (nl < m) sh.lidx[nl] = k; ++nl; }
+        }
+        sh.si[2] = (bad || nr != m || nl != m) ? 0 : 1;
+      }
+      __syncthreads();
+      ok = sh.si[2] != 0;
+    }
+    // ---- 4./5. self-energies and injection of each requested surface
+    for (int s = 0; s < 2; ++s) {
+      if (side >= 0 && s != side) continue;
+      const int slot = 2 * e + s;
+      double2* So = sig + (size_t)slot * MM;
+      double2* Wo = wf + (size_t)slot * MM;
+      bool sok = ok;
+      const int* idx = s == 0 ? sh.lidx : sh.ridx;     // Sigma_L: left-going, Sigma_R: right-going
+      if (sok) {
+        for (int q = t; q < m * m; q += NT) {
+          const int r = q / m, c = q - r * m;
+          sto(Ui + (size_t)r * LD + c, ldd(Cv + (size_t)r * LD + idx[c]));
+        }
+        __syncthreads();
+        sok = gj_invert(Ui, m, LD, sh.vec, sh.sd, sh.si);
+      }
+      if (sok) {
+        // F = B Lambda^(+-1) B^-1 into Yv, then Sigma = -{L, U} F
+        for (int q = t; q < m * m; q += NT) {
+          const int r = q / m, c = q - r * m;
+          cd acc = mk<double>(0.0, 0.0);
+          for (int j = 0; j < m; ++j) {
+            const cd lj = sh.lam[idx[j]];
+            const cd f = s == 0 ? cdivx(mk<double>(1.0, 0.0), lj) : lj;
+            acc = cadd(acc, cmul(cmul(ldd(Cv + (size_t)r * LD + idx[j]), f), ldd(Ui + (size_t)j * LD + m + c)));
+          }
+          sto(Yv + (size_t)r * LD + c, acc);
+        }
+        __syncthreads();
+        for (int q = t; q < MM; q += NT) {
+          const int r = q / M, c = q - r * M;
+          cd acc = mk<double>(0.0, 0.0);
+          if (r < m && c < m)
+            for (int j = 0; j < m; ++j)
+              acc = cadd(acc, cmul(s == 0 ? Lel(r, j) : Uel(r, j), ldd(Yv + (size_t)j * LD + c)));
+          sto(So + q, mk<double>(-acc.re, -acc.im));
+        }
+        __syncthreads();
+        // column g of W: the g-th incoming travelling mode in index order
+        // (right-going of the source's lead, left-going of the drain's)
+        for (int q = t; q < MM; q += NT) {
+          const int r = q / M, g = q - r * M;
+          int k = -1, cnt = 0;
+          for (int kk = 0; kk < n && k < 0; ++kk) {
+            const int kd = sh.kind[kk];
+            if ((s == 0 && kd == 3) || (s == 1 && kd == 2)) {
+              if (cnt == g) k = kk;
+              ++cnt;
+            }
+          }
+          cd v = mk<double>(0.0, 0.0);
+          if (r < m && k >= 0) {
+            const cd lk = sh.lam[k];
+            const cd f = s == 0 ? cdivx(mk<double>(-1.0, 0.0), lk) : mk<double>(-lk.re, -lk.im);
+            cd acc = mk<double>(0.0, 0.0);
+            for (int j = 0; j < m; ++j) {
+              const cd cj = ldd(Cv + (size_t)j * LD + k);
+              const cd op = cadd(cmul(f, s == 0 ? Lel(r, j) : Uel(r, j)), mk<double>(-ldd(So + r * M + j).re,
+                                                                                   -ldd(So + r * M + j).im));
+              acc = cadd(acc, cmul(op, cj));
+            }
+            v = cscl(acc, 1.0 / sqrt(fabs(sh.J[k])));
+          }
+          sto(Wo + q, v);
+        }
+        for (int c = t; c < M; c += NT) {
+          int cnt = 0;
+          for (int kk = 0; kk < n; ++kk) {
+            const int kd = sh.kind[kk];
+            cnt += (s == 0 && kd == 3) || (s == 1 && kd == 2);
+          }
+          sgn[(size_t)slot * M + c] = c < cnt ? 1.0 : 0.0;
+          if (c == 0) nheavy[slot] = cnt;
+        }
+      } else {
+        for (int q = t; q < MM; q += NT) {
+          So[q] = make_double2(0.0, 0.0);
+          Wo[q] = make_double2(0.0, 0.0);
+        }
+        for (int c = t; c < M; c += NT) sgn[(size_t)slot * M + c] = 0.0;
+        if (t == 0) nheavy[slot] = 0;
+      }
+      if (t == 0) iters[slot] = sok ? (total > 0 ? total : 1) : -1;
+      __syncthreads();
+    }
+  }
+}
+
+hipError_t run_modes(int M, const Prob& P, const double* E, int nE, double eta, int sides, double tol, int m,
+                     double2* scratch, int grid, double2* sig, double2* wf, double* sgn, int* iters, int* nheavy,
+                     hipStream_t st) {
+#define QTX_MODES(MM)                                                                                          \
+  hipLaunchKernelGGL(k_modes<MM>, dim3(grid), dim3(NT), 0, st, P, E, nE, eta, sides, tol, m, scratch, sig, wf, \
+                     sgn, iters, nheavy);                                                                      \
+  return hipGetLastError()
+  switch (M) {
+    case 16: QTX_MODES(16);
+    case 32: QTX_MODES(32);
+    case 48: QTX_MODES(48);
+    case 64: QTX_MODES(64);
+    case 96: QTX_MODES(96);
+    case 128: QTX_MODES(128);
+    default: return hipErrorInvalidValue;
+  }
+#undef QTX_MODES
+}
+
+}  // namespace qtx
