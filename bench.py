@@ -333,6 +333,60 @@ def bench_density_matrix(args):
     }))
 
 
+def bench_modes(args):
+    """The N=200, m=64 grid of 2048 energies in the paper's mode-space form
+    at eta = 0 (self-energies from the complex band structure of the lead on
+    the GPU, travelling-mode injection), next to the decimation path at
+    eta = 1e-6.  Energies and outputs stay in HBM."""
+    import torch
+    from paper_1903_00548_amd import _lib, workloads
+    import oracle
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    wl = workloads.config1()
+    dev = wl.device
+    N, m, nE = dev.N, dev.m, len(wl.E)
+    cpu = None
+    if not args.no_cpu_baseline:
+        sub = np.linspace(0, nE - 1, 8).astype(int)
+        a = time.perf_counter()
+        for k in sub:
+            oracle.solve_energy(dev, float(wl.E[k]), 0.0)
+        dt = time.perf_counter() - a
+        cpu = {"value": len(sub) / dt, "unit": "energy-solves/s", "cores": 1, "kind": "oracle",
+               "sample": f"{len(sub)} of the {nE} energies at eta = 0 (QZ self-energies), one process"}
+    ctx = _lib.context_for(dev, 0)
+    stream = torch.cuda.current_stream()
+    ctx.set_stream(stream.cuda_stream)
+    E_t = torch.tensor(wl.E, dtype=torch.float64, device="cuda")
+    T_t = torch.empty(nE, dtype=torch.float64, device="cuda")
+    L_t = torch.empty((nE, 2, N), dtype=torch.float64, device="cuda")
+    I_t = torch.empty(nE * _lib.INFO_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+    dec = time_path(ctx, torch, E_t, T_t, L_t, I_t, wl.eta, _lib.FP64, args.steps, args.warmup)
+    ctx.set_option("self_energy_method", 1)
+    md = time_path(ctx, torch, E_t, T_t, L_t, I_t, 0.0, _lib.FP64, args.steps, args.warmup)
+    rate = args.steps * nE / md["s"]
+    sweep_flops = nE * N * (152.0 / 3.0) * m ** 3
+    ach = sweep_flops / (md["sweep_ms"] * 1e-3) / 1e12
+    info = md["info"]
+    print(json.dumps({
+        "metric": "energy-solves/s, mode-space QTBM at eta = 0 (N=200 slabs, m=64, FP64)",
+        "value": rate, "unit": "energy-solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * md["s"] / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "cfg1_N200_m64_E2048_mode_space_eta0", "N": N, "m": m, "energies_per_step": nE},
+        "roofline": {"bound": "mfma", "achieved": ach, "peak": PEAK["fp64"], "unit": "TFLOP/s",
+                     "frac": ach / PEAK["fp64"], "traffic": None, "kernel": "k_sweep<double, 64> at eta = 0"},
+        "cpu_baseline": cpu,
+        "modes_kernel_ms_per_step": md["dec_ms"], "sweep_kernel_ms_per_step": md["sweep_ms"],
+        "mean_qr_iterations": float(np.mean(info["dec_iters"])), "flagged": int((info["flags"] != 0).sum()),
+        "max_T": float(np.max(md["T"])),
+        "decimation_path_eta_1e-6": {"energy_solves_per_s": args.steps * nE / dec["s"],
+                                     "decimation_kernel_ms_per_step": dec["dec_ms"],
+                                     "sweep_kernel_ms_per_step": dec["sweep_ms"]},
+        "max_abs_dT_eta0_vs_eta1e-6": float(np.abs(md["T"] - dec["T"]).max()),
+    }))
+
+
 def bench_batch(args):
     """64 devices of uneven slab count (50..400) and block size (32..128),
     256 energies each: the batched launch (FP64 and mixed) against the
@@ -467,7 +521,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration)")
-    ap.add_argument("--workload", choices=("cfg1", "cfg2", "batch64", "serve", "bands", "density_matrix"),
+    ap.add_argument("--workload", choices=("cfg1", "cfg2", "batch64", "serve", "bands", "density_matrix", "modes"),
                     default="cfg1",
                     help="cfg1: the headline N=200, m=64 grid (default); batch64: the uneven 64-device "
                          "batch; serve: the Poisson request loop")
@@ -476,6 +530,12 @@ def main():
     args = ap.parse_args()
     if args.workload == "bands":
         bench_bands(args)
+        return
+    if args.workload == "modes":
+        if args.gpus != 1:
+            print("bench.py: one GPU only", file=sys.stderr)
+            sys.exit(2)
+        bench_modes(args)
         return
     if args.workload == "density_matrix":
         if args.gpus != 1:

@@ -72,7 +72,7 @@ struct qtx_ctx {
   double dm_bytes = 64.0 * (1ull << 30);       // cap on the per-workgroup accumulators
   int se_method = 0;                           // 0 decimation, 1 complex band structure (mode space)
   double mode_tol = 1e-8;                      // |lambda| tolerance of travelling modes
-  DevBuf mscr;                                 // complex-band-structure workspace
+  DevBuf mscr, mjst;                           // complex-band-structure workspace, per-job status
 
   uint64_t lead_hash[2] = {0, 0};
 
@@ -236,17 +236,18 @@ qtx_status stage_decimate(qtx_ctx* c, const double* E_dev, int nE, double eta, b
   if (c->se_method == 1) {
     qtx_status s = check_method(c, eta, mixed);
     if (s != QTX_OK) return s;
-    const int grid = std::max(1, std::min(nE * sides, c->num_cu * 4));
+    const int jb = qtx::modes_batch_jobs(M, nE * sides);
     QTX_HIP(c, c->sig.ensure((size_t)nE * 2 * MM * sizeof(double2)));
     QTX_HIP(c, c->wf.ensure((size_t)nE * 2 * MM * sizeof(double2)));
     QTX_HIP(c, c->sgn.ensure((size_t)nE * 2 * M * sizeof(double)));
     QTX_HIP(c, c->iters.ensure((size_t)nE * 2 * sizeof(int)));
     QTX_HIP(c, c->nheavy.ensure((size_t)nE * 2 * sizeof(int)));
-    QTX_HIP(c, c->mscr.ensure((size_t)grid * qtx::modes_ws_elems(M) * sizeof(double2)));
+    QTX_HIP(c, c->mscr.ensure((size_t)jb * qtx::modes_ws_elems(M) * sizeof(double2)));
+    QTX_HIP(c, c->mjst.ensure((size_t)jb * sizeof(int)));
     QTX_HIP(c, record(c, c->ev_dec, c->n_dec));
-    QTX_HIP(c, qtx::run_modes(M, make_prob(c), E_dev, nE, eta, sides, c->mode_tol, c->m, c->mscr.as<double2>(), grid,
-                              c->sig.as<double2>(), c->wf.as<double2>(), c->sgn.as<double>(), c->iters.as<int>(),
-                              c->nheavy.as<int>(), c->stream));
+    QTX_HIP(c, qtx::run_modes(M, make_prob(c), E_dev, nE, eta, sides, c->mode_tol, c->m, c->num_cu,
+                              c->mscr.as<double2>(), c->mjst.as<int>(), c->sig.as<double2>(), c->wf.as<double2>(),
+                              c->sgn.as<double>(), c->iters.as<int>(), c->nheavy.as<int>(), c->stream));
     QTX_HIP(c, record(c, c->ev_dec, c->n_dec));
     return QTX_OK;
   }

@@ -153,13 +153,19 @@ hipError_t run_dm_reduce(const double2* rho, int nwg, size_t stride, int N, int 
 // Self-energies, injection factors and signs from the complex band
 // structure of the leads (the decimation's outputs, same layout) for nE
 // energies; sides = 1 when both leads are the same.  m: physical block
-// size; tol: |lambda| tolerance of travelling modes at eta = 0.  scratch:
-// grid * modes_ws_elems(M) complex doubles.  iters: QR iterations per
-// surface, -1 on failure.
+// size; tol: |lambda| tolerance of travelling modes at eta = 0.  The jobs
+// (energy, lead) run in batches of modes_batch_jobs(M, nE * sides), each
+// through three kernels (Hessenberg form, Schur form, modes and outputs);
+// scratch: that many times modes_ws_elems(M) complex doubles, jst: that
+// many ints.  iters: QR sweeps per surface, -1 on failure.
 hipError_t run_modes(int M, const Prob& P, const double* E, int nE, double eta, int sides, double tol, int m,
-                     double2* scratch, int grid, double2* sig, double2* wf, double* sgn, int* iters, int* nheavy,
-                     hipStream_t st);
+                     int num_cu, double2* scratch, int* jst, double2* sig, double2* wf, double* sgn, int* iters,
+                     int* nheavy, hipStream_t st);
 inline size_t modes_ws_elems(int M) { return 16 * (size_t)M * M; }
+inline int modes_batch_jobs(int M, int njobs) {
+  const int jb = M <= 64 ? 2048 : 512;
+  return njobs < jb ? njobs : jb;
+}
 
 // Band energies of one lead (padded blocks, physical size m) at nk Bloch
 // phases: E[q * m + n] = E_n(k_q) + V.  work: grid * 2 M (M + 1) complex

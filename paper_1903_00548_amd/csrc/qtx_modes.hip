@@ -57,6 +57,35 @@ __device__ __forceinline__ cd csqrtx(cd z) {
 }
 __device__ __forceinline__ cd cscl(cd a, double s) { return mk<double>(a.re * s, a.im * s); }
 
+// 1/sqrt(a), a > 0: hardware estimate and two Newton steps
+// y <- y (3 - a y^2) / 2 (each roughly doubles the correct bits).
+__device__ __forceinline__ double rsqrt_nr(double a) {
+  double y = __builtin_amdgcn_rsq(a);
+  y = y * fma(-0.5 * a, y * y, 1.5);
+  return y * fma(-0.5 * a, y * y, 1.5);
+}
+
+// Givens rotation G = [[c, s], [-conj(s), c]] (c real >= 0) with
+// G [x; y] = [r x / |x|; 0], r = sqrt(|x|^2 + |y|^2):
+// c = |x| / r, s = (x / |x|) conj(y) / r; for x = 0, c = 0, s = conj(y) / |y|.
+__device__ __forceinline__ void givens(cd x, cd y, double* c, cd* s) {
+  const double ax2 = x.re * x.re + x.im * x.im, ay2 = y.re * y.re + y.im * y.im;
+  const double r2 = ax2 + ay2;
+  if (!(r2 > 0.0)) {
+    *c = 1.0;
+    *s = mk<double>(0.0, 0.0);
+  } else if (ax2 == 0.0) {
+    const double iy = rsqrt_nr(ay2);
+    *c = 0.0;
+    *s = mk<double>(y.re * iy, -y.im * iy);
+  } else {
+    const double ix = rsqrt_nr(ax2), ir = rsqrt_nr(r2);
+    *c = ax2 * ix * ir;
+    const double f = ix * ir;
+    *s = cscl(cmul(x, cconj(y)), f);
+  }
+}
+
 // Inverse of the n x n matrix in columns [0, n) of A (row stride ld) by
 // Gauss-Jordan elimination with partial pivoting on [A | I]; the inverse is
 // left in columns [n, 2n).  fcol: n complex values of LDS.  Returns false
@@ -117,29 +146,323 @@ struct ModeShared {
   double J[256];        // fluxes
   int kind[256];        // 1 right-going, 0 left-going; +2 if travelling
   int ridx[128], lidx[128];
+  double rc[256];       // rotations of one QR sweep (cosine, sine)
+  cd rs[256];
+  cd xy[2][2];          // the next rotation's pair, from the column update
+  cd bulge;             // the entry below the subdiagonal during a sweep
   double sd[4];
   int si[8];
 };
 
+// Upper Hessenberg matrix with row stride ld in global memory.
+struct HGlob {
+  double2* p; int ld;
+  __device__ __forceinline__ cd get(int i, int j) const { return ldd(p + (size_t)i * ld + j); }
+  __device__ __forceinline__ void put(int i, int j, cd v) const { sto(p + (size_t)i * ld + j, v); }
+};
+
+// Upper Hessenberg matrix packed by rows in LDS: row i holds columns
+// max(i - 1, 0) .. n - 1, n + (n - 1)(n + 2)/2 entries in all.
+struct HLds {
+  cd* p; int n;
+  __device__ __forceinline__ int at(int i, int j) const {
+    return i == 0 ? j : n + (i - 1) * (n + 1) - ((i - 1) * i) / 2 + j - (i - 1);
+  }
+  __device__ __forceinline__ cd get(int i, int j) const { return p[at(i, j)]; }
+  __device__ __forceinline__ void put(int i, int j, cd v) const { p[at(i, j)] = v; }
+};
+constexpr int hpack(int n) { return n + (n - 1) * (n + 2) / 2; }
+
+// Complex Schur form of the n x n upper Hessenberg matrix H by single-shift
+// QR: deflation where a subdiagonal entry falls below eps times its
+// neighbouring diagonal, Wilkinson shifts (an exceptional shift every tenth
+// iteration on one eigenvalue), and an implicit sweep of Givens rotations
+// G = [[c, s], [-conj(s), c]] that chases the bulge down the window.  Only
+// H itself is updated inside a sweep (two barriers per rotation; the bulge
+// and the next rotation's pair are passed through LDS); the sweep's
+// rotations are applied to the Schur vectors Q (global, stride ld) after it,
+// row by row without barriers.  Returns false if more than 30 n sweeps were
+// needed; *total counts the sweeps.
+template <class HA>
+__device__ bool schur_qr(const HA& H, int n, double2* Qm, int ld, ModeShared& sh, int* total) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const double eps = 2.220446049250313e-16;
+  const int maxit = 30 * n;
+  int hi = n - 1, its = 0;
+  *total = 0;
+  while (hi > 0) {
+    if (w == 0) {
+      int found = 0;
+      for (int l = 1 + lane; l <= hi; l += 64) {
+        const double h = cabs1(H.get(l, l - 1));
+        const double tst = cabs1(H.get(l - 1, l - 1)) + cabs1(H.get(l, l));
+        if (h <= eps * tst || h == 0.0) found = l > found ? l : found;
+      }
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) {
+        const int o = __shfl_xor(found, off, 64);
+        found = o > found ? o : found;
+      }
+      if (lane == 0) {
+        sh.si[1] = found;
+        if (found > 0) H.put(found, found - 1, mk<double>(0.0, 0.0));
+      }
+    }
+    __syncthreads();
+    const int l = sh.si[1];
+    if (l == hi) {
+      --hi;
+      its = 0;
+      __syncthreads();          // every thread has read the deflation index
+      continue;
+    }
+    if (++*total > maxit) return false;
+    ++its;
+    // shift: the eigenvalue of the trailing 2 x 2 block nearer its corner
+    const cd a = H.get(hi - 1, hi - 1), b = H.get(hi - 1, hi), c = H.get(hi, hi - 1), d = H.get(hi, hi);
+    cd sigma;
+    if (its % 10 == 0) {
+      sigma = mk<double>(d.re + 0.75 * fabs(c.re), d.im);       // exceptional shift
+    } else {
+      const cd hm = cscl(csub(a, d), 0.5);
+      const cd r = csqrtx(cadd(cmul(hm, hm), cmul(b, c)));
+      const cd mid = cscl(cadd(a, d), 0.5);
+      const cd s1 = cadd(mid, r), s2 = csub(mid, r);
+      sigma = cabs1(csub(s1, d)) <= cabs1(csub(s2, d)) ? s1 : s2;
+    }
+    const cd x0 = csub(H.get(l, l), sigma), y0 = H.get(l + 1, l);
+    __syncthreads();            // every thread has read what the sweep overwrites
+    for (int k = l; k < hi; ++k) {
+      const cd x = k == l ? x0 : sh.xy[k & 1][0];
+      const cd y = k == l ? y0 : sh.xy[k & 1][1];
+      double cs;
+      cd sn;
+      givens(x, y, &cs, &sn);
+      if (t == 0) {
+        sh.rc[k - l] = cs;
+        sh.rs[k - l] = sn;
+      }
+      // rows k, k+1 from the left by G (column k-1 of row k+1 is the bulge)
+      const int j0 = k == l ? l : k - 1;
+      for (int j = j0 + t; j < n; j += NT) {
+        const cd p = H.get(k, j);
+        const cd q = j == k - 1 ? sh.bulge : H.get(k + 1, j);
+        H.put(k, j, cadd(cscl(p, cs), cmul(sn, q)));
+        if (j >= k) H.put(k + 1, j, csub(cscl(q, cs), cmul(cconj(sn), p)));
+      }
+      __syncthreads();
+      // columns k, k+1 from the right by G^H; row k+2 gets the new bulge
+      const int i1 = k + 2 < hi ? k + 2 : hi;
+      for (int i = t; i <= i1; i += NT) {
+        const cd p = i <= k + 1 ? H.get(i, k) : mk<double>(0.0, 0.0);
+        const cd q = H.get(i, k + 1);
+        const cd np = cadd(cscl(p, cs), cmul(cconj(sn), q));
+        H.put(i, k + 1, csub(cscl(q, cs), cmul(sn, p)));
+        if (i <= k + 1) H.put(i, k, np);
+        else sh.bulge = np;
+        if (i == k + 1) sh.xy[(k + 1) & 1][0] = np;
+        if (i == k + 2) sh.xy[(k + 1) & 1][1] = np;
+      }
+      __syncthreads();
+    }
+    // the sweep's rotations on the Schur vectors: Q <- Q G^H, row by row
+    // (columns l+1..hi are loaded eight at a time so that their latencies overlap)
+    for (int i = t; i < n; i += NT) {
+      double2* Qi = Qm + (size_t)i * ld;
+      cd carry = ldd(Qi + l);
+      for (int k0 = l; k0 < hi; k0 += 8) {
+        cd v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = k0 + u < hi ? ldd(Qi + k0 + u + 1) : mk<double>(0.0, 0.0);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int k = k0 + u;
+          if (k < hi) {
+            const double cs = sh.rc[k - l];
+            const cd sn = sh.rs[k - l];
+            sto(Qi + k, cadd(cscl(carry, cs), cmul(cconj(sn), v[u])));
+            carry = csub(cscl(v[u], cs), cmul(sn, carry));
+          }
+        }
+      }
+      sto(Qi + hi, carry);
+    }
+  }
+  return true;
+}
+
+// Cross-lane ordering of LDS accesses inside one wave (LDS executes a
+// wave's accesses in order; this keeps the compiler from reordering them).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// schur_qr for n <= 128 with H in LDS: wave 0 runs the deflation tests and
+// the bulge chase alone (lane-parallel rows and columns, no block barrier
+// inside a sweep), writing each sweep's rotations to one of two buffers;
+// meanwhile waves 1..3 apply the previous sweep's rotations to Q.  One
+// block barrier per sweep.
+__device__ bool schur_qr_wave(const HLds& H, int n, double2* Qm, int ld, ModeShared& sh, int* total) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const double eps = 2.220446049250313e-16;
+  const int maxit = 30 * n;
+  // wave 0 state (uniform within the wave)
+  int hi = n - 1, its = 0, tot = 0, buf = 0;
+  // block state: sh.si[3] = 1 while sweeps come, 0 when converged, -1 failed;
+  // sh.si[4 + b], sh.si[6 + b]: window (l, hi) of the sweep in buffer b
+  bool pending = false;                 // waves 1..3: a sweep waits in buffer buf ^ 1
+  for (;;) {
+    if (w == 0) {
+      int state = 0;
+      while (hi > 0) {
+        int found = 0;
+        for (int l = 1 + lane; l <= hi; l += 64) {
+          const double h = cabs1(H.get(l, l - 1));
+          const double tst = cabs1(H.get(l - 1, l - 1)) + cabs1(H.get(l, l));
+          if (h <= eps * tst || h == 0.0) found = l > found ? l : found;
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+          const int o = __shfl_xor(found, off, 64);
+          found = o > found ? o : found;
+        }
+        const int l = found;
+        if (l > 0 && lane == 0) H.put(l, l - 1, mk<double>(0.0, 0.0));
+        wave_sync();
+        if (l == hi) {
+          --hi;
+          its = 0;
+          continue;
+        }
+        if (++tot > maxit) {
+          state = -1;
+          break;
+        }
+        ++its;
+        const cd a = H.get(hi - 1, hi - 1), b = H.get(hi - 1, hi), c = H.get(hi, hi - 1), d = H.get(hi, hi);
+        cd sigma;
+        if (its % 10 == 0) {
+          sigma = mk<double>(d.re + 0.75 * fabs(c.re), d.im);
+        } else {
+          const cd hm = cscl(csub(a, d), 0.5);
+          const cd r = csqrtx(cadd(cmul(hm, hm), cmul(b, c)));
+          const cd mid = cscl(cadd(a, d), 0.5);
+          const cd s1 = cadd(mid, r), s2 = csub(mid, r);
+          sigma = cabs1(csub(s1, d)) <= cabs1(csub(s2, d)) ? s1 : s2;
+        }
+        cd x = csub(H.get(l, l), sigma), y = H.get(l + 1, l);
+        wave_sync();
+        double* rc = sh.rc + 128 * buf;
+        cd* rs = sh.rs + 128 * buf;
+        for (int k = l; k < hi; ++k) {
+          if (k > l) {
+            x = sh.xy[0][0];
+            y = sh.xy[0][1];
+          }
+          double cs;
+          cd sn;
+          givens(x, y, &cs, &sn);
+          if (lane == 0) {
+            rc[k - l] = cs;
+            rs[k - l] = sn;
+          }
+          const int j0 = k == l ? l : k - 1;
+          for (int j = j0 + lane; j < n; j += 64) {
+            const cd p = H.get(k, j);
+            const cd q = j == k - 1 ? sh.bulge : H.get(k + 1, j);
+            H.put(k, j, cadd(cscl(p, cs), cmul(sn, q)));
+            if (j >= k) H.put(k + 1, j, csub(cscl(q, cs), cmul(cconj(sn), p)));
+          }
+          wave_sync();
+          const int i1 = k + 2 < hi ? k + 2 : hi;
+          for (int i = lane; i <= i1; i += 64) {
+            const cd p = i <= k + 1 ? H.get(i, k) : mk<double>(0.0, 0.0);
+            const cd q = H.get(i, k + 1);
+            const cd np = cadd(cscl(p, cs), cmul(cconj(sn), q));
+            H.put(i, k + 1, csub(cscl(q, cs), cmul(sn, p)));
+            if (i <= k + 1) H.put(i, k, np);
+            else sh.bulge = np;
+            if (i == k + 1) sh.xy[0][0] = np;
+            if (i == k + 2) sh.xy[0][1] = np;
+          }
+          wave_sync();
+        }
+        if (lane == 0) {
+          sh.si[4 + buf] = l;
+          sh.si[6 + buf] = hi;
+        }
+        state = 1;
+        break;
+      }
+      if (lane == 0) sh.si[3] = state;
+    } else if (pending) {
+      // the previous sweep's rotations on the Schur vectors: Q <- Q G^H
+      const int b = buf ^ 1;
+      const int l = sh.si[4 + b], h = sh.si[6 + b];
+      const double* rc = sh.rc + 128 * b;
+      const cd* rs = sh.rs + 128 * b;
+      for (int i = t - 64; i < n; i += NT - 64) {
+        double2* Qi = Qm + (size_t)i * ld;
+        cd carry = ldd(Qi + l);
+        for (int k0 = l; k0 < h; k0 += 8) {
+          cd v[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) v[u] = k0 + u < h ? ldd(Qi + k0 + u + 1) : mk<double>(0.0, 0.0);
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int k = k0 + u;
+            if (k < h) {
+              const double cs = rc[k - l];
+              const cd sn = rs[k - l];
+              sto(Qi + k, cadd(cscl(carry, cs), cmul(cconj(sn), v[u])));
+              carry = csub(cscl(v[u], cs), cmul(sn, carry));
+            }
+          }
+        }
+        sto(Qi + h, carry);
+      }
+    }
+    __syncthreads();
+    const int state = sh.si[3];
+    __syncthreads();                    // every thread has read the state
+    if (state == 1) {                   // waves 1..3 apply this sweep in the next round
+      pending = true;
+      buf ^= 1;
+      continue;
+    }
+    // converged (the last sweep was applied in this round) or failed
+    *total = tot;
+    return state == 0;
+  }
+}
+
 }  // namespace
 
+// Stage 1 (per job): C = [[-U^-1 D0, -U^-1 L], [I, 0]] and its Hessenberg
+// form with the accumulated reflectors.  jst[jl] = 0, or -1 if U is singular.
 template <int M>
-__global__ __launch_bounds__(NT) void k_modes(Prob P, const double* E, int nE, double eta, int sides, double tol,
-                                              int m, double2* ws, double2* sig, double2* wf, double* sgn,
-                                              int* iters, int* nheavy) {
+__global__ __launch_bounds__(NT) void k_modes_hess(Prob P, const double* E, double eta, int sides, double tol, int m, int j0, int nb, double2* ws, int* jst) {
+  __shared__ ModeShared sh;
   constexpr int LD = 2 * M, MM = M * M;
   constexpr size_t WS = 16 * (size_t)M * M;
-  __shared__ ModeShared sh;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  (void)lane;
+  (void)w;
   const int n = 2 * m;
-  double2* Cm = ws + (size_t)blockIdx.x * WS;   // C, then its Schur form T (n x n, stride LD)
-  double2* Qm = Cm + 4 * (size_t)MM;           // Schur vectors
-  double2* Yv = Qm + 4 * (size_t)MM;           // [D0 | L], then eigenvectors of T, then products
-  double2* Ui = Yv + 4 * (size_t)MM;           // Gauss-Jordan work (m x 2m)
-  double2* Cv = Ui + 2 * (size_t)MM;           // mode vectors c (m x n)
-  const int njobs = nE * sides;
   const double eps = 2.220446049250313e-16;
-  for (int job = blockIdx.x; job < njobs; job += gridDim.x) {
+  (void)eps;
+  for (int jl = blockIdx.x; jl < nb; jl += gridDim.x) {
+    const int job = j0 + jl;
+    double2* Cm = ws + (size_t)jl * WS;          // C, then its Schur form T (n x n, stride LD)
+    double2* Qm = Cm + 4 * (size_t)MM;           // Schur vectors
+    double2* Yv = Qm + 4 * (size_t)MM;           // [D0 | L], then eigenvectors of T, then products
+    double2* Ui = Yv + 4 * (size_t)MM;           // Gauss-Jordan work (m x 2m)
+    double2* Cv = Ui + 2 * (size_t)MM;           // mode vectors c (m x n)
+    (void)Yv;
+    (void)Ui;
+    (void)Cv;
     const int e = job / sides;
     const int side = sides == 2 ? job - 2 * e : -1;       // -1: both surfaces from the left lead
     const double2* lead = side == 1 ? P.leadR : P.leadL;
@@ -161,9 +484,11 @@ __global__ __launch_bounds__(NT) void k_modes(Prob P, const double* E, int nE, d
       const cd s = ldd(S00 + r * M + c), h = ldd(H00 + r * M + c);
       return mk<double>(zx.re * s.re - zx.im * s.im - h.re, zx.re * s.im + zx.im * s.re - h.im);
     };
-    bool ok = true;
-    int total = 0;
+    (void)Uel;
+    (void)Lel;
+    (void)D0el;
     __syncthreads();
+    bool ok = true;
     // ---- 1. C = [[-U^-1 D0, -U^-1 L], [I, 0]]
     for (int idx = t; idx < m * m; idx += NT) {
       const int r = idx / m, c = idx - r * m;
@@ -242,109 +567,140 @@ __global__ __launch_bounds__(NT) void k_modes(Prob P, const double* E, int nE, d
         }
         __syncthreads();
       }
-      // ---- 2b. Schur form by single-shift QR with Givens bulge chasing
-      const int maxit = 30 * n;
-      int hi = n - 1, its = 0;
-      while (hi > 0) {
-        if (w == 0) {
-          int found = 0;
-          for (int l = 1 + lane; l <= hi; l += 64) {
-            const double h = cabs1(ldd(Cm + (size_t)l * LD + l - 1));
-            const double tst = cabs1(ldd(Cm + (size_t)(l - 1) * LD + l - 1)) + cabs1(ldd(Cm + (size_t)l * LD + l));
-            if (h <= eps * tst || h == 0.0) found = l > found ? l : found;
-          }
-#pragma unroll
-          for (int off = 32; off >= 1; off >>= 1) {
-            const int o = __shfl_xor(found, off, 64);
-            found = o > found ? o : found;
-          }
-          if (lane == 0) {
-            sh.si[1] = found;
-            if (found > 0) sto(Cm + (size_t)found * LD + found - 1, mk<double>(0.0, 0.0));
-          }
-        }
-        __syncthreads();
-        const int l = sh.si[1];
-        if (l == hi) {
-          --hi;
-          its = 0;
-          __syncthreads();      // every thread has read the deflation index
-          continue;
-        }
-        if (++total > maxit) {
-          ok = false;
-          break;
-        }
-        ++its;
-        // shift: the eigenvalue of the trailing 2 x 2 block nearer its corner
-        const cd a = ldd(Cm + (size_t)(hi - 1) * LD + hi - 1), b = ldd(Cm + (size_t)(hi - 1) * LD + hi);
-        const cd c = ldd(Cm + (size_t)hi * LD + hi - 1), d = ldd(Cm + (size_t)hi * LD + hi);
-        cd sigma;
-        if (its % 10 == 0) {
-          sigma = mk<double>(d.re + 0.75 * fabs(c.re), d.im);     // exceptional shift
-        } else {
-          const cd hm = cscl(csub(a, d), 0.5);
-          const cd r = csqrtx(cadd(cmul(hm, hm), cmul(b, c)));
-          const cd mid = cscl(cadd(a, d), 0.5);
-          const cd s1 = cadd(mid, r), s2 = csub(mid, r);
-          sigma = cabs1(csub(s1, d)) <= cabs1(csub(s2, d)) ? s1 : s2;
-        }
-        __syncthreads();        // every thread has read the 2 x 2 block
-        for (int k = l; k < hi; ++k) {
-          cd x, y;
-          if (k == l) {
-            x = csub(ldd(Cm + (size_t)l * LD + l), sigma);
-            y = ldd(Cm + (size_t)(l + 1) * LD + l);
-          } else {
-            x = ldd(Cm + (size_t)k * LD + k - 1);
-            y = ldd(Cm + (size_t)(k + 1) * LD + k - 1);
-          }
-          const double ax = cabsx(x), ay = cabsx(y), r = hypot(ax, ay);
-          double cs = 1.0;
-          cd sn = mk<double>(0.0, 0.0);
-          if (r > 0.0) {
-            if (ax == 0.0) {
-              cs = 0.0;
-              sn = mk<double>(y.re / ay, -y.im / ay);
-            } else {
-              cs = ax / r;
-              const cd ph = mk<double>(x.re / ax, x.im / ax);
-              sn = cscl(cmul(ph, cconj(y)), 1.0 / r);
-            }
-          }
-          __syncthreads();      // every thread has read x, y
-          // rows k, k+1 from the left by G = [[c, s], [-conj(s), c]]
-          const int j0 = k == l ? l : k - 1;
-          for (int j = j0 + t; j < n; j += NT) {
-            const cd p = ldd(Cm + (size_t)k * LD + j), q = ldd(Cm + (size_t)(k + 1) * LD + j);
-            cd np = cadd(cscl(p, cs), cmul(sn, q));
-            cd nq = csub(cscl(q, cs), cmul(cconj(sn), p));
-            if (j == k - 1 && k > l) nq = mk<double>(0.0, 0.0);
-            sto(Cm + (size_t)k * LD + j, np);
-            sto(Cm + (size_t)(k + 1) * LD + j, nq);
-          }
-          __syncthreads();
-          // columns k, k+1 from the right by G^H, and the Schur vectors
-          const int i1 = k + 2 < hi ? k + 2 : hi;
-          for (int i = t; i < n; i += NT) {
-            if (i <= i1) {
-              const cd p = ldd(Cm + (size_t)i * LD + k), q = ldd(Cm + (size_t)i * LD + k + 1);
-              sto(Cm + (size_t)i * LD + k, cadd(cscl(p, cs), cmul(cconj(sn), q)));
-              sto(Cm + (size_t)i * LD + k + 1, csub(cscl(q, cs), cmul(sn, p)));
-            }
-            const cd p = ldd(Qm + (size_t)i * LD + k), q = ldd(Qm + (size_t)i * LD + k + 1);
-            sto(Qm + (size_t)i * LD + k, cadd(cscl(p, cs), cmul(cconj(sn), q)));
-            sto(Qm + (size_t)i * LD + k + 1, csub(cscl(q, cs), cmul(sn, p)));
-          }
-          __syncthreads();
-        }
-      }
     }
+    if (t == 0) jst[jl] = ok ? 0 : -1;
+  }
+}
+
+// Stage 2 (per job): complex Schur form T = Q^H C Q (T back in the job's C
+// slot, upper triangle).  jst[jl] = QR sweeps, or -1.
+template <int M>
+__global__ __launch_bounds__(NT) void k_modes_qr(Prob P, const double* E, double eta, int sides, double tol, int m, int j0, int nb, double2* ws, int* jst) {
+  __shared__ ModeShared sh;
+  __shared__ cd Hs[M <= 64 ? hpack(2 * M) : 1];   // packed Hessenberg / Schur form (M <= 64)
+  constexpr int LD = 2 * M, MM = M * M;
+  constexpr size_t WS = 16 * (size_t)M * M;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  (void)lane;
+  (void)w;
+  const int n = 2 * m;
+  const double eps = 2.220446049250313e-16;
+  (void)eps;
+  for (int jl = blockIdx.x; jl < nb; jl += gridDim.x) {
+    const int job = j0 + jl;
+    double2* Cm = ws + (size_t)jl * WS;          // C, then its Schur form T (n x n, stride LD)
+    double2* Qm = Cm + 4 * (size_t)MM;           // Schur vectors
+    double2* Yv = Qm + 4 * (size_t)MM;           // [D0 | L], then eigenvectors of T, then products
+    double2* Ui = Yv + 4 * (size_t)MM;           // Gauss-Jordan work (m x 2m)
+    double2* Cv = Ui + 2 * (size_t)MM;           // mode vectors c (m x n)
+    (void)Yv;
+    (void)Ui;
+    (void)Cv;
+    const int e = job / sides;
+    const int side = sides == 2 ? job - 2 * e : -1;       // -1: both surfaces from the left lead
+    const double2* lead = side == 1 ? P.leadR : P.leadL;
+    const double V = side == 1 ? P.VR : P.VL;
+    const cd zx = mk<double>(E[e] - V, eta);
+    const double2* H00 = lead;
+    const double2* H01 = lead + MM;
+    const double2* S00 = lead + 2 * MM;
+    const double2* S01 = lead + 3 * MM;
+    auto Uel = [&](int r, int c) {             // z S01 - H01
+      const cd s = ldd(S01 + r * M + c), h = ldd(H01 + r * M + c);
+      return mk<double>(zx.re * s.re - zx.im * s.im - h.re, zx.re * s.im + zx.im * s.re - h.im);
+    };
+    auto Lel = [&](int r, int c) {             // z S01^H - H01^H
+      const cd s = ldd(S01 + c * M + r), h = ldd(H01 + c * M + r);
+      return mk<double>(zx.re * s.re + zx.im * s.im - h.re, zx.im * s.re - zx.re * s.im + h.im);
+    };
+    auto D0el = [&](int r, int c) {            // z S00 - H00
+      const cd s = ldd(S00 + r * M + c), h = ldd(H00 + r * M + c);
+      return mk<double>(zx.re * s.re - zx.im * s.im - h.re, zx.re * s.im + zx.im * s.re - h.im);
+    };
+    (void)Uel;
+    (void)Lel;
+    (void)D0el;
+    __syncthreads();
+    if (jst[jl] < 0) continue;          // uniform
+    int total = 0;
+    bool ok;
+    if constexpr (M <= 64) {
+      const HLds HL{Hs, n};
+      for (int q = t; q < n * n; q += NT) {
+        const int i = q / n, j = q - i * n;
+        if (j >= i - 1) Hs[HL.at(i, j)] = ldd(Cm + (size_t)i * LD + j);
+      }
+      __syncthreads();
+      ok = schur_qr_wave(HL, n, Qm, LD, sh, &total);
+      __syncthreads();
+      for (int q = t; q < n * n; q += NT) {
+        const int i = q / n, j = q - i * n;
+        if (j >= i) sto(Cm + (size_t)i * LD + j, Hs[HL.at(i, j)]);
+      }
+    } else {
+      ok = schur_qr(HGlob{Cm, LD}, n, Qm, LD, sh, &total);
+    }
+    if (t == 0) jst[jl] = ok ? total : -1;
+    __syncthreads();
+  }
+}
+
+// Stage 3 (per job): eigenvectors, the mode split, self-energies, injection
+// and the outputs of both or one surface.
+template <int M>
+__global__ __launch_bounds__(NT) void k_modes_post(Prob P, const double* E, double eta, int sides, double tol, int m, int j0, int nb, double2* ws, int* jst, double2* sig, double2* wf,
+                                                   double* sgn, int* iters, int* nheavy) {
+  __shared__ ModeShared sh;
+  constexpr int LD = 2 * M, MM = M * M;
+  constexpr size_t WS = 16 * (size_t)M * M;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  (void)lane;
+  (void)w;
+  const int n = 2 * m;
+  const double eps = 2.220446049250313e-16;
+  (void)eps;
+  for (int jl = blockIdx.x; jl < nb; jl += gridDim.x) {
+    const int job = j0 + jl;
+    double2* Cm = ws + (size_t)jl * WS;          // C, then its Schur form T (n x n, stride LD)
+    double2* Qm = Cm + 4 * (size_t)MM;           // Schur vectors
+    double2* Yv = Qm + 4 * (size_t)MM;           // [D0 | L], then eigenvectors of T, then products
+    double2* Ui = Yv + 4 * (size_t)MM;           // Gauss-Jordan work (m x 2m)
+    double2* Cv = Ui + 2 * (size_t)MM;           // mode vectors c (m x n)
+    (void)Yv;
+    (void)Ui;
+    (void)Cv;
+    const int e = job / sides;
+    const int side = sides == 2 ? job - 2 * e : -1;       // -1: both surfaces from the left lead
+    const double2* lead = side == 1 ? P.leadR : P.leadL;
+    const double V = side == 1 ? P.VR : P.VL;
+    const cd zx = mk<double>(E[e] - V, eta);
+    const double2* H00 = lead;
+    const double2* H01 = lead + MM;
+    const double2* S00 = lead + 2 * MM;
+    const double2* S01 = lead + 3 * MM;
+    auto Uel = [&](int r, int c) {             // z S01 - H01
+      const cd s = ldd(S01 + r * M + c), h = ldd(H01 + r * M + c);
+      return mk<double>(zx.re * s.re - zx.im * s.im - h.re, zx.re * s.im + zx.im * s.re - h.im);
+    };
+    auto Lel = [&](int r, int c) {             // z S01^H - H01^H
+      const cd s = ldd(S01 + c * M + r), h = ldd(H01 + c * M + r);
+      return mk<double>(zx.re * s.re + zx.im * s.im - h.re, zx.im * s.re - zx.re * s.im + h.im);
+    };
+    auto D0el = [&](int r, int c) {            // z S00 - H00
+      const cd s = ldd(S00 + r * M + c), h = ldd(H00 + r * M + c);
+      return mk<double>(zx.re * s.re - zx.im * s.im - h.re, zx.re * s.im + zx.im * s.re - h.im);
+    };
+    (void)Uel;
+    (void)Lel;
+    (void)D0el;
     __syncthreads();
     // ---- 2c. eigenvectors of T (thread per eigenvalue), then c = (Q y) rows m..2m-1
+    auto Tel = [&](int i, int j) -> cd { return ldd(Cm + (size_t)i * LD + j); };
+    const int total = jst[jl];
+    bool ok = total >= 0;
     if (ok) {
       for (int k = t; k < n; k += NT) {
-        const cd lk = ldd(Cm + (size_t)k * LD + k);
+        const cd lk = Tel(k, k);
         sh.lam[k] = lk;
         const double smin = fmax(eps * cabs1(lk), 1e-290);
         for (int i = k + 1; i < n; ++i) sto(Yv + (size_t)i * LD + k, mk<double>(0.0, 0.0));
@@ -352,8 +708,8 @@ __global__ __launch_bounds__(NT) void k_modes(Prob P, const double* E, int nE, d
         double big = 1.0;
         for (int i = k - 1; i >= 0; --i) {
           cd s = mk<double>(0.0, 0.0);
-          for (int j = i + 1; j <= k; ++j) s = cadd(s, cmul(ldd(Cm + (size_t)i * LD + j), ldd(Yv + (size_t)j * LD + k)));
-          cd dd = csub(ldd(Cm + (size_t)i * LD + i), lk);
+          for (int j = i + 1; j <= k; ++j) s = cadd(s, cmul(Tel(i, j), ldd(Yv + (size_t)j * LD + k)));
+          cd dd = csub(Tel(i, i), lk);
           if (cabs1(dd) < smin) dd = mk<double>(smin, 0.0);
           const cd y = cdivx(mk<double>(-s.re, -s.im), dd);
           sto(Yv + (size_t)i * LD + k, y);
@@ -502,13 +858,37 @@ __global__ __launch_bounds__(NT) void k_modes(Prob P, const double* E, int nE, d
   }
 }
 
+template <int M>
+hipError_t launch_modes(const Prob& P, const double* E, int nE, double eta, int sides, double tol, int m, int num_cu,
+                        double2* scratch, int* jst, double2* sig, double2* wf, double* sgn, int* iters, int* nheavy,
+                        hipStream_t st) {
+  int o1 = 0, o2 = 0, o3 = 0;
+  hipError_t err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&o1, k_modes_hess<M>, NT, 0);
+  if (err == hipSuccess) err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&o2, k_modes_qr<M>, NT, 0);
+  if (err == hipSuccess) err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&o3, k_modes_post<M>, NT, 0);
+  if (err != hipSuccess) return err;
+  const int njobs = nE * sides;
+  const int jb = modes_batch_jobs(M, njobs);
+  for (int j0 = 0; j0 < njobs; j0 += jb) {
+    const int nb = njobs - j0 < jb ? njobs - j0 : jb;
+    auto grid = [&](int occ) { const int g = num_cu * (occ > 0 ? occ : 1); return g < nb ? g : nb; };
+    hipLaunchKernelGGL(k_modes_hess<M>, dim3(grid(o1)), dim3(NT), 0, st, P, E, eta, sides, tol, m, j0, nb, scratch,
+                       jst);
+    hipLaunchKernelGGL(k_modes_qr<M>, dim3(grid(o2)), dim3(NT), 0, st, P, E, eta, sides, tol, m, j0, nb, scratch,
+                       jst);
+    hipLaunchKernelGGL(k_modes_post<M>, dim3(grid(o3)), dim3(NT), 0, st, P, E, eta, sides, tol, m, j0, nb, scratch,
+                       jst, sig, wf, sgn, iters, nheavy);
+    err = hipGetLastError();
+    if (err != hipSuccess) return err;
+  }
+  return hipSuccess;
+}
+
 hipError_t run_modes(int M, const Prob& P, const double* E, int nE, double eta, int sides, double tol, int m,
-                     double2* scratch, int grid, double2* sig, double2* wf, double* sgn, int* iters, int* nheavy,
-                     hipStream_t st) {
-#define QTX_MODES(MM)                                                                                          \
-  hipLaunchKernelGGL(k_modes<MM>, dim3(grid), dim3(NT), 0, st, P, E, nE, eta, sides, tol, m, scratch, sig, wf, \
-                     sgn, iters, nheavy);                                                                      \
-  return hipGetLastError()
+                     int num_cu, double2* scratch, int* jst, double2* sig, double2* wf, double* sgn, int* iters,
+                     int* nheavy, hipStream_t st) {
+#define QTX_MODES(MM) \
+  return launch_modes<MM>(P, E, nE, eta, sides, tol, m, num_cu, scratch, jst, sig, wf, sgn, iters, nheavy, st)
   switch (M) {
     case 16: QTX_MODES(16);
     case 32: QTX_MODES(32);
