@@ -872,7 +872,10 @@ hipError_t launch_modes(const Prob& P, const double* E, int nE, double eta, int 
   for (int j0 = 0; j0 < njobs; j0 += jb) {
     const int nb = njobs - j0 < jb ? njobs - j0 : jb;
     auto grid = [&](int occ) { const int g = num_cu * (occ > 0 ? occ : 1); return g < nb ? g : nb; };
-    hipLaunchKernelGGL(k_modes_hess<M>, dim3(grid(o1)), dim3(NT), 0, st, P, E, eta, sides, tol, m, j0, nb, scratch,
+    // at most two Hessenberg jobs per CU: their matrices (C and Q, 8 M^2
+    // complex doubles each) then stay in the last-level cache, which the
+    // reduction re-reads once per column
+    hipLaunchKernelGGL(k_modes_hess<M>, dim3(grid(o1 < 2 ? o1 : 2)), dim3(NT), 0, st, P, E, eta, sides, tol, m, j0, nb, scratch,
                        jst);
     hipLaunchKernelGGL(k_modes_qr<M>, dim3(grid(o2)), dim3(NT), 0, st, P, E, eta, sides, tol, m, j0, nb, scratch,
                        jst);

@@ -46,6 +46,8 @@ DEVICES = [
                                           VL=0.02, VR=-0.03)),
     ("m64", lambda: W.small_random_device(7, 4, 64, uniform=False, same_leads=False, pot_mode=W.POT_LINEAR_FE)),
     ("pad-80", lambda: W.small_random_device(9, 3, 80, uniform=True, same_leads=True, pot_mode=W.POT_DIAG)),
+    ("m128", lambda: W.small_random_device(10, 2, 128, uniform=False, same_leads=False, pot_mode=W.POT_DIAG,
+                                           VL=0.01, VR=-0.02)),
 ]
 ENERGIES = np.array([-2.31, -1.07, -0.413, 0.2718, 0.977, 1.618, 2.49])
 
@@ -89,8 +91,7 @@ def test_transport_against_mode_space_qtbm(gpu_lib, name, make):
 @pytest.mark.parametrize("m,N", [(8, 6), (64, 200)])
 def test_perfect_wire_integer_transmission(gpu_lib, m, N):
     """A device that copies its lead: T equals the number of open channels
-    exactly (no broadening), and the two injections give equal densities
-    on every slab of a symmetric wire."""
+    exactly (no broadening at eta = 0)."""
     lead = W.random_lead(np.random.default_rng(17 + m), m)
     dev = W.Device(N=N, m=m, lead_L=lead, lead_R=lead, V=np.zeros(N), pot_mode=W.POT_DIAG)
     ctx = _mode_ctx(dev)
