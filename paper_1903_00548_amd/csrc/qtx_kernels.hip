@@ -27,15 +27,23 @@ template <typename R, int M> struct BGJ {
   int ppanel[M];     // panel in which row r became a pivot, -1 before
 };
 
+// Panel width of the Gauss-Jordan elimination: 16 columns when the matrix
+// is in LDS; 32 when it lives in global memory (M > 64), which halves the
+// read-modify-write passes of the trailing update over the matrix and
+// doubles the MFMA work per tile loaded.
+template <int M> constexpr int gj_pw() { return M > 64 ? 32 : 16; }
+
 // LDS scratch (complex elements) that gj_inverse needs beside the matrix:
 // the compacted pivot rows of the panel update, and during the panel the
 // double-buffered row multipliers.
 template <int M> constexpr int gj_scratch() {
-  return 16 * (M - 16) > 2 * 64 * ((M + 63) / 64) ? 16 * (M - 16) : 2 * 64 * ((M + 63) / 64);
+  return gj_pw<M>() * (M - gj_pw<M>()) > 2 * 64 * ((M + 63) / 64) ? gj_pw<M>() * (M - gj_pw<M>())
+                                                                    : 2 * 64 * ((M + 63) / 64);
 }
 
-// Elimination of panel k (columns 16k..16k+15) of the matrix; wave w holds
-// columns 16k+4w .. 16k+4w+3 of every row (rows lane, lane + 64, ...).
+// Elimination of panel k (columns PW k .. PW k + PW - 1, PW = gj_pw<M>())
+// of the matrix; wave w holds columns PW k + CW w .. PW k + CW w + CW - 1
+// (CW = PW / 4) of every row (rows lane, lane + 64, ...).
 // Step jj: the wave owning column jj finds the pivot row p (DPP max over
 // the unused rows), forms the row multipliers m_r = x_rj / x_pj (the pivot
 // row takes -1 / x_pj) and publishes them and p through LDS; after one
@@ -48,23 +56,24 @@ template <int M> constexpr int gj_scratch() {
 template <typename R, int M>
 __device__ __forceinline__ void gj_panel(cpx<R>* mat, int S, int k, BGJ<R, M>& sc, cpx<R>* mb) {
   constexpr int RL = (M + 63) / 64;             // rows per lane
+  constexpr int PW = gj_pw<M>(), CW = PW / NWAVE;
   static_assert(M <= 128, "pivot keys carry 8-bit row indices");
   const int lane = lane_id(), w = threadIdx.x >> 6;
-  const int c0 = 16 * k + 4 * w;
-  cpx<R> pr[RL][4];
+  const int c0 = PW * k + CW * w;
+  cpx<R> pr[RL][CW];
   bool used[RL];
 #pragma unroll
   for (int q = 0; q < RL; ++q) {
     const int r = lane + 64 * q;
     const bool ok = r < M;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) pr[q][c] = ok ? mat[r * S + c0 + c] : mk<R>(0, 0);
+    for (int c = 0; c < CW; ++c) pr[q][c] = ok ? mat[r * S + c0 + c] : mk<R>(0, 0);
     used[q] = true;
     if (ok) used[q] = sc.ppanel[r] >= 0;
   }
 #pragma unroll
-  for (int jj = 0; jj < 16; ++jj) {
-    const int owner = jj >> 2, cj = jj & 3;
+  for (int jj = 0; jj < PW; ++jj) {
+    const int owner = jj / CW, cj = jj % CW;
     cpx<R>* mbj = mb + (jj & 1) * 64 * RL;
     if (w == owner) {
       uint32_t key = 0;
@@ -85,19 +94,19 @@ __device__ __forceinline__ void gj_panel(cpx<R>* mat, int S, int k, BGJ<R, M>& s
       for (int q = 0; q < RL; ++q)
         mbj[lane + 64 * q] = (q == pq && lane == pl) ? mk<R>(-inv.re, -inv.im) : cmul(pr[q][cj], inv);
       if (lane == 0) {
-        sc.piv[16 * k + jj] = p;
+        sc.piv[PW * k + jj] = p;
         sc.ppanel[p] = k;
       }
     }
     __syncthreads();
-    const int p = __builtin_amdgcn_readfirstlane(sc.piv[16 * k + jj]);
+    const int p = __builtin_amdgcn_readfirstlane(sc.piv[PW * k + jj]);
     const int pl = RL == 1 ? p : p & 63, pq = RL == 1 ? 0 : p >> 6;
     cpx<R> m[RL];
 #pragma unroll
     for (int q = 0; q < RL; ++q) m[q] = mbj[lane + 64 * q];
-    cpx<R> prow[4];
+    cpx<R> prow[CW];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
+    for (int c = 0; c < CW; ++c) {
       prow[c] = mk<R>(0, 0);
 #pragma unroll
       for (int q = 0; q < RL; ++q)
@@ -107,7 +116,7 @@ __device__ __forceinline__ void gj_panel(cpx<R>* mat, int S, int k, BGJ<R, M>& s
     for (int q = 0; q < RL; ++q) {
       const bool isp = (q == pq) && (lane == pl);
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
+      for (int c = 0; c < CW; ++c) {
         if (c == cj && w == owner) {
           pr[q][c] = mk<R>(-m[q].re, -m[q].im);
         } else {
@@ -123,19 +132,20 @@ __device__ __forceinline__ void gj_panel(cpx<R>* mat, int S, int k, BGJ<R, M>& s
     const int r = lane + 64 * q;
     if (r < M)
 #pragma unroll
-      for (int c = 0; c < 4; ++c) mat[r * S + c0 + c] = pr[q][c];
+      for (int c = 0; c < CW; ++c) mat[r * S + c0 + c] = pr[q][c];
   }
 }
 
 // Panel update x' = (x with the panel's pivot rows zeroed) + G y for every
-// 16x16 tile outside panel k (G: the panel columns, y: the compacted pivot
-// rows in Y, row stride M - 16).  The tiles are dealt round-robin to the
+// 16x16 tile outside panel k (G: the PW panel columns, y: the compacted
+// pivot rows in Y, row stride M - PW).  The tiles are dealt round-robin to the
 // waves; each wave runs its tiles in groups of at most four through one
 // interleaved MFMA loop, so that up to eight accumulator chains are in
 // flight.  A group's surplus slots recompute a valid tile and do not store.
 template <typename R, int M>
 __device__ __forceinline__ void gj_update(cpx<R>* mat, int S, int k, const cpx<R>* Y, const BGJ<R, M>& sc) {
-  constexpr int MT = M / 16, NTILE = MT * (MT - 1), TPW = (NTILE + NWAVE - 1) / NWAVE, WY = M - 16;
+  constexpr int PW = gj_pw<M>(), PT = PW / 16;
+  constexpr int MT = M / 16, NTILE = MT * (MT - PT), TPW = (NTILE + NWAVE - 1) / NWAVE, WY = M - PW;
   constexpr int GRP = TPW < 4 ? TPW : 4;
   if constexpr (NTILE > 0) {
     const int w = threadIdx.x >> 6, lane = lane_id(), g = lane >> 4, c = lane & 15;
@@ -149,7 +159,7 @@ __device__ __forceinline__ void gj_update(cpx<R>* mat, int S, int k, const cpx<R
         int tile = w + NWAVE * (q0 + q);
         keep[q] = (q0 + q < TPW) && tile < NTILE;
         tile = keep[q] ? tile : 0;
-        const int ti = tile % MT, tcx = tile / MT, tc = tcx + (tcx >= k ? 1 : 0);
+        const int ti = tile % MT, tcx = tile / MT, tc = tcx + (tcx >= PT * k ? PT : 0);
         arow[q] = 16 * ti;
         bcol[q] = 16 * tcx + c;
         xcol[q] = 16 * tc + c;
@@ -162,12 +172,12 @@ __device__ __forceinline__ void gj_update(cpx<R>* mat, int S, int k, const cpx<R
         }
       }
 #pragma unroll
-      for (int sl = 0; sl < 4; ++sl) {
-        const int kk = 4 * g + sl;
+      for (int sl = 0; sl < 4 * PT; ++sl) {
+        const int kk = 16 * (sl >> 2) + 4 * g + (sl & 3);
         cpx<R> av[GRP], bv[GRP];
 #pragma unroll
         for (int q = 0; q < GRP; ++q) {
-          av[q] = mat[(arow[q] + c) * S + 16 * k + kk];
+          av[q] = mat[(arow[q] + c) * S + PW * k + kk];
           bv[q] = Y[kk * WY + bcol[q]];
         }
 #pragma unroll
@@ -201,7 +211,7 @@ __device__ __forceinline__ void gj_update(cpx<R>* mat, int S, int k, const cpx<R
 // workgroup resident on the CU (which is then mostly in MFMA phases).
 template <typename R, int M>
 __device__ __forceinline__ void gj_inverse(cpx<R>* mat, int S, cpx<R>* Y, BGJ<R, M>& sc) {
-  constexpr int NP = M / 16;
+  constexpr int PW = gj_pw<M>(), NP = M / PW;
   const int t = threadIdx.x;
   __builtin_amdgcn_s_setprio(2);
   if (t < M) sc.ppanel[t] = -1;
@@ -209,12 +219,12 @@ __device__ __forceinline__ void gj_inverse(cpx<R>* mat, int S, cpx<R>* Y, BGJ<R,
   for (int k = 0; k < NP; ++k) {
     gj_panel<R, M>(mat, S, k, sc, Y);
     __syncthreads();
-    // pivot rows of the columns outside the panel, compacted (16 x (M-16))
-    constexpr int WY = M - 16;
-    for (int idx = t; idx < 16 * WY; idx += NT) {
+    // pivot rows of the columns outside the panel, compacted (PW x (M-PW))
+    constexpr int WY = M - PW;
+    for (int idx = t; idx < PW * WY; idx += NT) {
       const int jj = idx / WY, cx = idx - jj * WY;
-      const int c = cx + (cx >= 16 * k ? 16 : 0);
-      Y[idx] = mat[sc.piv[16 * k + jj] * S + c];
+      const int c = cx + (cx >= PW * k ? PW : 0);
+      Y[idx] = mat[sc.piv[PW * k + jj] * S + c];
     }
     __syncthreads();
     gj_update<R, M>(mat, S, k, Y, sc);
