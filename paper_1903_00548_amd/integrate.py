@@ -13,7 +13,12 @@ Panel [a, b] with midpoint m and quarter points l, r: S1 = Simpson on
 (a, m, b), S2 = Simpson on (a, l, m) + (m, r, b); the panel is accepted
 when max|S2 - S1| / 15 <= tol (b - a) / (B - A) (the absolute tolerance
 spread over the interval [A, B]) and contributes the Richardson value
-S2 + (S2 - S1) / 15; otherwise it is split at m.
+S2 + (S2 - S1) / 15; otherwise it is split at m.  That value is linear in
+the samples, (b - a)/90 (7, 32, 12, 32, 7) on (a, l, m, r, b), so the
+driver also returns one quadrature weight per abscissa: the integral is
+sum_k w_k F(E_k).  Sec. "Density" keeps exactly these energies and weights
+of the node-density integration to build the density matrix in one more
+pass (density_matrix below).
 
 Quantities (n^L_i, n^R_i: slab densities of states per injecting contact,
 T: transmission; f: Fermi function):
@@ -54,6 +59,7 @@ class Result:
     evaluations: int                  # distinct abscissae evaluated
     rounds: int                       # solver calls
     energies: np.ndarray              # all abscissae, sorted
+    weights: np.ndarray               # quadrature weight of each abscissa (value = weights @ F(energies))
 
 
 def adaptive_simpson(F: Callable[[np.ndarray], np.ndarray], A: float, B: float, tol: float,
@@ -82,6 +88,11 @@ def adaptive_simpson(F: Callable[[np.ndarray], np.ndarray], A: float, B: float, 
     pending = [(float(edges[k]), float(edges[k + 1])) for k in range(n0)]
     total = None
     err_total = 0.0
+    wts: Dict[float, float] = {}
+
+    def add_weights(points, factors, h):
+        for p, f in zip(points, factors):
+            wts[p] = wts.get(p, 0.0) + h * f
     while pending and rounds < max_rounds:
         pts = set()
         for a, b in pending:
@@ -100,6 +111,7 @@ def adaptive_simpson(F: Callable[[np.ndarray], np.ndarray], A: float, B: float, 
                 v = s2 + (s2 - s1) / 15.0
                 total = v if total is None else total + v
                 err_total += err
+                add_weights((a, l, m, r, b), (7.0, 32.0, 12.0, 32.0, 7.0), (b - a) / 90.0)
             else:
                 nxt.extend(((a, m), (m, b)))
         pending = nxt
@@ -109,11 +121,15 @@ def adaptive_simpson(F: Callable[[np.ndarray], np.ndarray], A: float, B: float, 
         l, r = 0.5 * (a + m), 0.5 * (m + b)
         if all(p in vals for p in (a, l, m, r, b)):
             s2 = (m - a) / 6.0 * (vals[a] + 4.0 * vals[l] + vals[m]) + (b - m) / 6.0 * (vals[m] + 4.0 * vals[r] + vals[b])
+            add_weights((a, l, m, r, b), (1.0, 4.0, 2.0, 4.0, 1.0), (b - a) / 12.0)
         else:
             s2 = (b - a) / 6.0 * (vals[a] + 4.0 * vals[m] + vals[b])
+            add_weights((a, m, b), (1.0, 4.0, 1.0), (b - a) / 6.0)
         total = s2 if total is None else total + s2
+    energies = np.array(sorted(vals))
     return Result(value=np.asarray(total), error_estimate=err_total, converged=converged,
-                  evaluations=len(vals), rounds=rounds, energies=np.array(sorted(vals)))
+                  evaluations=len(vals), rounds=rounds, energies=energies,
+                  weights=np.array([wts.get(e, 0.0) for e in energies]))
 
 
 def integrand(quantity: str, solve: Callable, muL: float, muR: float, kT: float):
@@ -135,6 +151,19 @@ def integrate(solve: Callable, quantity: str, A: float, B: float, muL: float, mu
     """Adaptive integral of a quantity over [A, B] (see the module docstring)
     with the transport solve as integrand."""
     return adaptive_simpson(integrand(quantity, solve, muL, muR, kT), A, B, tol, n0=n0, max_rounds=max_rounds)
+
+
+def density_matrix(ctx, result: Result, muL: float, muR: float, kT: float, eta: float):
+    """Nearest-neighbour density-matrix blocks rho_ii (N, m, m) and
+    rho_{i,i+1} (N-1, m, m) over the energies and quadrature weights of an
+    adaptive integration (eq. density_matrices: weight times occupation of
+    each contact, one pass of the HIP library's density-matrix solve).  For
+    the result of a "density" integration, the trace of rho_ii equals its
+    value up to rounding."""
+    E = np.asarray(result.energies, dtype=np.float64)
+    q = np.asarray(result.weights, dtype=np.float64)
+    rd, ro, _, _, _, _ = ctx.density_matrix(E, q * fermi(E - muL, kT), q * fermi(E - muR, kT), eta)
+    return rd, ro
 
 
 def qtx_solver(ctx, eta: float, precision: int = 0):

@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 
 from oracle import integrals as oint
+from oracle.density_matrix import density_matrix_blocks
 from paper_1903_00548_amd import _lib
 from paper_1903_00548_amd import integrate as I
 from paper_1903_00548_amd import workloads as W
@@ -50,3 +51,21 @@ def test_density_jacobian_current(setup):
     assert abs(rc.value[0] - cur) <= bar, (rc.value[0], cur, bar)
     # each round is one batched solve of new energies only
     assert rc.rounds <= 40 and len(np.unique(rc.energies)) == rc.evaluations
+
+
+def test_density_matrix_on_the_adaptive_grid(setup):
+    """The density matrix from the energies and quadrature weights of the
+    adaptive node-density integration (Sec. "Density": the same points,
+    one more pass): the trace of rho_ii equals the integrated density, and
+    the blocks equal the oracle's on those energies and weights."""
+    dev, ctx = setup
+    solve = I.qtx_solver(ctx, ETA)
+    A, B = -7.0, MUL + 20 * KT
+    r = I.integrate(solve, "density", A, B, MUL, MUR, KT, tol=1e-7)
+    rd, ro = I.density_matrix(ctx, r, MUL, MUR, KT, ETA)
+    tr = np.real(np.einsum("iaa->i", rd))
+    assert np.abs(tr - r.value).max() <= 1e-12 * max(1.0, np.abs(r.value).max())
+    E, q = r.energies, r.weights
+    ref_d, ref_o = density_matrix_blocks(dev, E, q * I.fermi(E - MUL, KT), q * I.fermi(E - MUR, KT), ETA)
+    scale = max(1.0, np.abs(ref_d).max())
+    assert np.abs(rd - ref_d).max() <= 1e-9 * scale and np.abs(ro - ref_o).max() <= 1e-9 * scale

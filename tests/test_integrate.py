@@ -93,3 +93,15 @@ def test_unconverged_is_reported():
     r = I.adaptive_simpson(lambda E: (1.0 / np.sqrt(np.abs(E - 0.123456) + 1e-14))[:, None], 0.0, 1.0, 1e-14,
                            max_rounds=3)
     assert not r.converged and np.isfinite(r.value).all()
+
+
+def test_weights_reproduce_the_value():
+    """The returned quadrature weights give the integral of every component,
+    accepted panels (Boole weights) and unconverged ones alike."""
+    F = lambda E: np.stack([np.sqrt(np.abs(E - 0.3)), np.cos(3 * E), E ** 3], axis=1)
+    for rounds in (40, 2):
+        r = I.adaptive_simpson(F, -1.0, 2.0, 1e-9, n0=8, max_rounds=rounds)
+        assert r.weights.shape == r.energies.shape
+        direct = r.weights @ F(r.energies)
+        assert np.allclose(direct, r.value, rtol=1e-13, atol=1e-15), (direct, r.value)
+    assert abs(r.weights.sum() - 3.0) < 1e-12           # the constant 1 integrates exactly
