@@ -20,12 +20,18 @@
 
 namespace {
 
+// Device buffer that grows on demand and is freed with its owner (the
+// context is destroyed with its device current); not copyable.
 struct DevBuf {
   void* p = nullptr;
   size_t n = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
   hipError_t ensure(size_t bytes) {
     if (bytes <= n) return hipSuccess;
-    if (p) hipFree(p);
+    if (p) (void)hipFree(p);
     p = nullptr;
     n = 0;
     hipError_t e = hipMalloc(&p, bytes);
@@ -33,7 +39,7 @@ struct DevBuf {
     return e;
   }
   void release() {
-    if (p) hipFree(p);
+    if (p) (void)hipFree(p);
     p = nullptr;
     n = 0;
   }
@@ -424,12 +430,12 @@ qtx_status qtx_create(int hip_device, qtx_ctx** out) {
 
 void qtx_destroy(qtx_ctx* c) {
   if (!c) return;
-  hipSetDevice(c->device);
-  if (c->stream) hipStreamSynchronize(c->stream);
-  for (hipEvent_t e : c->ev_dec) hipEventDestroy(e);
-  for (hipEvent_t e : c->ev_sw) hipEventDestroy(e);
-  if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
-  if (c->graph) hipGraphDestroy(c->graph);
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (hipEvent_t e : c->ev_dec) (void)hipEventDestroy(e);
+  for (hipEvent_t e : c->ev_sw) (void)hipEventDestroy(e);
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
   for (auto& kv : c->sigcache) {
     DevBuf* cb[] = {&kv.second.sig, &kv.second.wf, &kv.second.sgn, &kv.second.iters, &kv.second.nheavy};
     for (DevBuf* b : cb) b->release();
@@ -442,7 +448,7 @@ void qtx_destroy(qtx_ctx* c) {
                     &c->redo, &c->elist, &c->ecount, &c->bprobs, &c->bitem_prob, &c->bitem_ldos,
                     &c->bjob_item, &c->bjob_side, &c->bE, &c->bT, &c->bldos, &c->binfo};
   for (DevBuf* b : bufs) b->release();
-  if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
 
@@ -451,8 +457,8 @@ const char* qtx_last_error(const qtx_ctx* c) { return c ? c->err.c_str() : "null
 qtx_status qtx_set_stream(qtx_ctx* c, void* st) {
   if (!c) return QTX_EINVAL;
   if (c->own_stream && c->stream) {
-    hipStreamSynchronize(c->stream);
-    hipStreamDestroy(c->stream);
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipStreamDestroy(c->stream);
     c->stream = nullptr;
     c->own_stream = false;
   }
@@ -477,7 +483,7 @@ qtx_status qtx_set_lead(qtx_ctx* c, qtx_side side, int m, const qtx_c128* H00, c
   if ((c->lead_set[other] || c->dev_set) && c->m != m) return fail(c, QTX_EINVAL, "m differs from the other lead / device");
   if (!hermitian(H00, m, 1e-12) || !hermitian(S00, m, 1e-12))
     return fail(c, QTX_EINVAL, "H00 and S00 must be Hermitian");
-  hipSetDevice(c->device);
+  QTX_HIP(c, hipSetDevice(c->device));
   c->m = m;
   c->M = qtx::padded_block(m);
   const int M = c->M;
@@ -513,7 +519,7 @@ qtx_status qtx_set_device(qtx_ctx* c, int N, int m, const qtx_c128* Hd, const qt
   const int given = (Hd != nullptr) + (Sd != nullptr) + ((Hu != nullptr) || N == 1) + ((Su != nullptr) || N == 1);
   const bool none = !Hd && !Hu && !Sd && !Su;
   if (!none && given != 4) return fail(c, QTX_EINVAL, "give all four device block arrays or none");
-  hipSetDevice(c->device);
+  QTX_HIP(c, hipSetDevice(c->device));
   c->m = m;
   c->M = qtx::padded_block(m);
   if (none) {
@@ -550,7 +556,7 @@ qtx_status qtx_set_potential(qtx_ctx* c, const double* V, qtx_pot_mode mode) {
   if (mode != QTX_POT_DIAG && mode != QTX_POT_LINEAR_FE) return fail(c, QTX_EINVAL, "unknown potential mode");
   for (int i = 0; i < c->N; ++i)
     if (!std::isfinite(V[i])) return fail(c, QTX_EINVAL, "potential must be finite");
-  hipSetDevice(c->device);
+  QTX_HIP(c, hipSetDevice(c->device));
   QTX_HIP(c, c->dV.ensure((size_t)c->N * sizeof(double)));
   QTX_HIP(c, hipMemcpy(c->dV.p, V, (size_t)c->N * sizeof(double), hipMemcpyHostToDevice));
   c->pot_mode = mode;
@@ -562,7 +568,7 @@ qtx_status qtx_solve_device(qtx_ctx* c, const double* E_dev, int nE, double eta,
                             double* T_dev, double* ldos_dev, qtx_info* info_dev) {
   if (!c) return QTX_EINVAL;
   if (prec != QTX_FP64 && prec != QTX_MIXED) return fail(c, QTX_EINVAL, "unknown precision");
-  hipSetDevice(c->device);
+  QTX_HIP(c, hipSetDevice(c->device));
   return solve_device_core(c, E_dev, nE, eta, prec, T_dev, ldos_dev, info_dev);
 }
 
@@ -577,7 +583,7 @@ qtx_status qtx_solve(qtx_ctx* c, const double* E, int nE, double eta, qtx_precis
     if (!std::isfinite(E[e])) return fail(c, QTX_EINVAL, "energies must be finite");
   qtx_status s = check_ready(c);
   if (s != QTX_OK) return s;
-  hipSetDevice(c->device);
+  QTX_HIP(c, hipSetDevice(c->device));
   const int N = c->N;
   QTX_HIP(c, c->wE.ensure((size_t)nE * sizeof(double)));
   QTX_HIP(c, c->wT.ensure((size_t)nE * sizeof(double)));
@@ -606,7 +612,7 @@ qtx_status qtx_density_matrix_device(qtx_ctx* c, const double* E_dev, const doub
                                      int nE, double eta, qtx_c128* rho_diag_dev, qtx_c128* rho_off_dev,
                                      double* T_dev, double* ldos_dev, qtx_info* info_dev) {
   if (!c) return QTX_EINVAL;
-  hipSetDevice(c->device);
+  QTX_HIP(c, hipSetDevice(c->device));
   return density_matrix_core(c, E_dev, wL_dev, wR_dev, nE, eta, (double2*)rho_diag_dev, (double2*)rho_off_dev,
                              T_dev, ldos_dev, info_dev);
 }
@@ -629,7 +635,7 @@ qtx_status qtx_density_matrix(qtx_ctx* c, const double* E, const double* wL, con
   for (int e = 0; e < nE; ++e)
     if (!std::isfinite(E[e]) || !std::isfinite(wL[e]) || !std::isfinite(wR[e]))
       return fail(c, QTX_EINVAL, "energies and weights must be finite");
-  hipSetDevice(c->device);
+  QTX_HIP(c, hipSetDevice(c->device));
   QTX_HIP(c, c->wE.ensure((size_t)nE * sizeof(double)));
   QTX_HIP(c, c->wT.ensure((size_t)nE * sizeof(double)));
   QTX_HIP(c, c->wldos.ensure((size_t)nE * 2 * N * sizeof(double)));
@@ -671,7 +677,7 @@ qtx_status qtx_self_energy(qtx_ctx* c, const double* E, int nE, double eta, qtx_
   if (!E || !sigma) return fail(c, QTX_EINVAL, "E and sigma must not be NULL");
   if (!c->lead_set[0] || !c->lead_set[1]) return fail(c, QTX_ESTATE, "both leads must be set");
   if (check_method(c, eta, false) != QTX_OK) return QTX_EINVAL;
-  hipSetDevice(c->device);
+  QTX_HIP(c, hipSetDevice(c->device));
   const int m = c->m, M = c->M;
   const size_t MM = (size_t)M * M;
   QTX_HIP(c, c->wE.ensure((size_t)nE * sizeof(double)));
@@ -717,7 +723,7 @@ qtx_status qtx_self_energy(qtx_ctx* c, const double* E, int nE, double eta, qtx_
 
 qtx_status qtx_kernel_times(qtx_ctx* c, int enable, double* decimate_ms, double* sweep_ms, int* launches) {
   if (!c) return QTX_EINVAL;
-  hipSetDevice(c->device);
+  QTX_HIP(c, hipSetDevice(c->device));
   QTX_HIP(c, hipStreamSynchronize(c->stream));
   double td = 0.0, ts = 0.0;
   for (size_t k = 0; k + 1 < c->n_dec; k += 2) {
@@ -835,8 +841,8 @@ struct DecGroup {
 };
 
 void drop_graph(qtx_ctx* c) {
-  if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
-  if (c->graph) hipGraphDestroy(c->graph);
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
   c->graph_exec = nullptr;
   c->graph = nullptr;
   c->batch_sig.clear();
@@ -955,7 +961,7 @@ qtx_status qtx_solve_batch(qtx_ctx* c, int nprob, qtx_ctx* const* probs, const d
   for (int p = 0; p < nprob; ++p)
     if (probs[p]->se_method != 0 || c->se_method != 0)
       return fail(c, QTX_EINVAL, "batched solves use the decimation (self_energy_method 0)");
-  hipSetDevice(c->device);
+  QTX_HIP(c, hipSetDevice(c->device));
   const bool mixed = (prec == QTX_MIXED);
 
   // problems grouped by padded block size, each group by decreasing slab
@@ -1242,7 +1248,7 @@ qtx_status qtx_solve_batch(qtx_ctx* c, int nprob, qtx_ctx* const* probs, const d
       hipGraph_t g = nullptr;
       hipError_t ce = hipStreamEndCapture(c->stream, &g);
       if (s != QTX_OK) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return s;
       }
       if (ce != hipSuccess) return hipfail(c, ce, "hipStreamEndCapture");
@@ -1283,7 +1289,7 @@ qtx_status qtx_autotune(qtx_ctx* c, const double* E, int nE, double eta, qtx_pre
     if (!std::isfinite(E[e])) return fail(c, QTX_EINVAL, "energies must be finite");
   qtx_status s = check_ready(c);
   if (s != QTX_OK) return s;
-  hipSetDevice(c->device);
+  QTX_HIP(c, hipSetDevice(c->device));
   const bool mixed = prec == QTX_MIXED;
   const int M = c->M, N = c->N;
   int occ_sweep = 0, occ_dec = 0;
@@ -1329,8 +1335,8 @@ qtx_status qtx_autotune(qtx_ctx* c, const double* E, int nE, double eta, qtx_pre
     }
   }
   c->timing = timing;
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (st != QTX_OK) {
     c->tuned_wg[mixed].erase(M);
     return st;
@@ -1350,7 +1356,7 @@ qtx_status qtx_bands(qtx_ctx* c, qtx_side side, const double* k, int nk, double*
   if (!k || !E) return fail(c, QTX_EINVAL, "k and E must not be NULL");
   for (int q = 0; q < nk; ++q)
     if (!std::isfinite(k[q])) return fail(c, QTX_EINVAL, "k must be finite");
-  hipSetDevice(c->device);
+  QTX_HIP(c, hipSetDevice(c->device));
   const int M = c->M, m = c->m;
   const int grid = std::max(1, std::min(nk, c->num_cu));
   QTX_HIP(c, c->wE.ensure((size_t)nk * sizeof(double)));

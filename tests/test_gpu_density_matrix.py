@@ -153,3 +153,24 @@ def test_cfg1_full_size(gpu_lib):
     rd_s, ro_s = ctx.density_matrix(wl.E, sL, sR, wl.eta)[:2]
     ref_d, ref_o = density_matrix_blocks(dev, wl.E[idx], sL[idx], sR[idx], wl.eta)
     _check_blocks(rd_s, ro_s, ref_d, ref_o, "cfg1 sampled")
+
+
+def test_context_destroy_frees_device_memory(gpu_lib):
+    """Closing a context returns its device memory, the density-matrix
+    accumulators included (13 GB for 512 workgroups at N=200, m=64)."""
+    import torch
+    wl = W.config1(nE=512)
+    wL, wR = _cfg1_weights(wl.E)
+
+    def cycle():
+        ctx = _lib.context_for(wl.device, 0)
+        ctx.density_matrix(wl.E, wL, wR, wl.eta)
+        ctx.close()
+        torch.cuda.synchronize()
+
+    cycle()
+    free0, _ = torch.cuda.mem_get_info()
+    for _ in range(3):
+        cycle()
+    free1, _ = torch.cuda.mem_get_info()
+    assert free0 - free1 < (1 << 30), (free0, free1)
