@@ -219,16 +219,19 @@ __device__ __forceinline__ void gj_inverse(cpx<R>* mat, int S, cpx<R>* Y, BGJ<R,
   for (int k = 0; k < NP; ++k) {
     gj_panel<R, M>(mat, S, k, sc, Y);
     __syncthreads();
-    // pivot rows of the columns outside the panel, compacted (PW x (M-PW))
+    // pivot rows of the columns outside the panel, compacted (PW x (M-PW));
+    // a single panel (M = PW) leaves nothing to update
     constexpr int WY = M - PW;
-    for (int idx = t; idx < PW * WY; idx += NT) {
-      const int jj = idx / WY, cx = idx - jj * WY;
-      const int c = cx + (cx >= PW * k ? PW : 0);
-      Y[idx] = mat[sc.piv[PW * k + jj] * S + c];
+    if constexpr (WY > 0) {
+      for (int idx = t; idx < PW * WY; idx += NT) {
+        const int jj = idx / WY, cx = idx - jj * WY;
+        const int c = cx + (cx >= PW * k ? PW : 0);
+        Y[idx] = mat[sc.piv[PW * k + jj] * S + c];
+      }
+      __syncthreads();
+      gj_update<R, M>(mat, S, k, Y, sc);
+      __syncthreads();
     }
-    __syncthreads();
-    gj_update<R, M>(mat, S, k, Y, sc);
-    __syncthreads();
   }
   if (t < M) sc.pinv[sc.piv[t]] = t;
   __syncthreads();
