@@ -352,15 +352,14 @@ __device__ bool schur_qr_wave(const HLds& H, int n, double2* Qm, int ld, ModeSha
           const cd s1 = cadd(mid, r), s2 = csub(mid, r);
           sigma = cabs1(csub(s1, d)) <= cabs1(csub(s2, d)) ? s1 : s2;
         }
+        // x, y: the pair the next rotation annihilates against (y is also
+        // the bulge below the subdiagonal), broadcast from the lanes that
+        // produced them
         cd x = csub(H.get(l, l), sigma), y = H.get(l + 1, l);
         wave_sync();
         double* rc = sh.rc + 128 * buf;
         cd* rs = sh.rs + 128 * buf;
         for (int k = l; k < hi; ++k) {
-          if (k > l) {
-            x = sh.xy[0][0];
-            y = sh.xy[0][1];
-          }
           double cs;
           cd sn;
           givens(x, y, &cs, &sn);
@@ -368,24 +367,49 @@ __device__ bool schur_qr_wave(const HLds& H, int n, double2* Qm, int ld, ModeSha
             rc[k - l] = cs;
             rs[k - l] = sn;
           }
+          // each lane owns columns j0 + lane and j0 + lane + 64 (n <= 128):
+          // both pairs are loaded before either is stored, so that the two
+          // LDS round trips overlap
           const int j0 = k == l ? l : k - 1;
-          for (int j = j0 + lane; j < n; j += 64) {
-            const cd p = H.get(k, j);
-            const cd q = j == k - 1 ? sh.bulge : H.get(k + 1, j);
-            H.put(k, j, cadd(cscl(p, cs), cmul(sn, q)));
-            if (j >= k) H.put(k + 1, j, csub(cscl(q, cs), cmul(cconj(sn), p)));
+          {
+            const int ja = j0 + lane, jb = ja + 64;
+            const bool va = ja < n, vb = jb < n;
+            const cd zero = mk<double>(0.0, 0.0);
+            const cd pa = va ? H.get(k, ja) : zero, pb = vb ? H.get(k, jb) : zero;
+            const cd qa = va ? (ja == k - 1 ? y : H.get(k + 1, ja)) : zero;
+            const cd qb = vb ? H.get(k + 1, jb) : zero;
+            if (va) {
+              H.put(k, ja, cadd(cscl(pa, cs), cmul(sn, qa)));
+              if (ja >= k) H.put(k + 1, ja, csub(cscl(qa, cs), cmul(cconj(sn), pa)));
+            }
+            if (vb) {
+              H.put(k, jb, cadd(cscl(pb, cs), cmul(sn, qb)));
+              H.put(k + 1, jb, csub(cscl(qb, cs), cmul(cconj(sn), pb)));
+            }
           }
           wave_sync();
+          // rows lane and lane + 64 of columns k, k+1 (row k+2 takes the bulge)
           const int i1 = k + 2 < hi ? k + 2 : hi;
-          for (int i = lane; i <= i1; i += 64) {
-            const cd p = i <= k + 1 ? H.get(i, k) : mk<double>(0.0, 0.0);
-            const cd q = H.get(i, k + 1);
-            const cd np = cadd(cscl(p, cs), cmul(cconj(sn), q));
-            H.put(i, k + 1, csub(cscl(q, cs), cmul(sn, p)));
-            if (i <= k + 1) H.put(i, k, np);
-            else sh.bulge = np;
-            if (i == k + 1) sh.xy[0][0] = np;
-            if (i == k + 2) sh.xy[0][1] = np;
+          {
+            const int ia = lane, ib = lane + 64;
+            const bool va = ia <= i1, vb = ib <= i1;
+            const cd zero = mk<double>(0.0, 0.0);
+            const cd pa = va && ia <= k + 1 ? H.get(ia, k) : zero, pb = vb && ib <= k + 1 ? H.get(ib, k) : zero;
+            const cd qa = va ? H.get(ia, k + 1) : zero, qb = vb ? H.get(ib, k + 1) : zero;
+            const cd npa = cadd(cscl(pa, cs), cmul(cconj(sn), qa));
+            const cd npb = cadd(cscl(pb, cs), cmul(cconj(sn), qb));
+            if (va) {
+              H.put(ia, k + 1, csub(cscl(qa, cs), cmul(sn, pa)));
+              if (ia <= k + 1) H.put(ia, k, npa);
+            }
+            if (vb) {
+              H.put(ib, k + 1, csub(cscl(qb, cs), cmul(sn, pb)));
+              if (ib <= k + 1) H.put(ib, k, npb);
+            }
+            // next pair: new (k+1, k) and the bulge (k+2, k), from their lanes
+            const cd xs = k + 1 < 64 ? npa : npb, ys = k + 2 < 64 ? npa : npb;
+            x = mk<double>(readlane_d(xs.re, (k + 1) & 63), readlane_d(xs.im, (k + 1) & 63));
+            y = mk<double>(readlane_d(ys.re, (k + 2) & 63), readlane_d(ys.im, (k + 2) & 63));
           }
           wave_sync();
         }
