@@ -266,8 +266,9 @@ __device__ bool schur_qr(const HA& H, int n, double2* Qm, int ld, ModeShared& sh
       __syncthreads();
     }
     // the sweep's rotations on the Schur vectors: Q <- Q G^H, row by row
-    // (columns l+1..hi are loaded eight at a time so that their latencies overlap)
-    for (int i = t; i < n; i += NT) {
+    // (rows n/2.. only, the ones the mode vectors use; columns l+1..hi are
+    // loaded eight at a time so that their latencies overlap)
+    for (int i = n / 2 + t; i < n; i += NT) {
       double2* Qi = Qm + (size_t)i * ld;
       cd carry = ldd(Qi + l);
       for (int k0 = l; k0 < hi; k0 += 8) {
@@ -427,7 +428,7 @@ __device__ bool schur_qr_wave(const HLds& H, int n, double2* Qm, int ld, ModeSha
       const int l = sh.si[4 + b], h = sh.si[6 + b];
       const double* rc = sh.rc + 128 * b;
       const cd* rs = sh.rs + 128 * b;
-      for (int i = t - 64; i < n; i += NT - 64) {
+      for (int i = n / 2 + t - 64; i < n; i += NT - 64) {   // rows the mode vectors use
         double2* Qi = Qm + (size_t)i * ld;
         cd carry = ldd(Qi + l);
         for (int k0 = l; k0 < h; k0 += 8) {
@@ -530,8 +531,10 @@ __global__ __launch_bounds__(NT) void k_modes_hess(Prob P, const double* E, doub
         sto(Cm + (size_t)r * LD + c, mk<double>(-s.re, -s.im));
         sto(Cm + (size_t)(m + r) * LD + c, mk<double>(c == r ? 1.0 : 0.0, 0.0));
       }
-      for (int idx = t; idx < n * n; idx += NT) {
-        const int r = idx / n, c = idx - r * n;
+      // only rows m..2m-1 of the Schur vectors are ever used (the c part of
+      // the eigenvectors), so only they are formed
+      for (int idx = t; idx < m * n; idx += NT) {
+        const int r = m + idx / n, c = idx - (r - m) * n;
         sto(Qm + (size_t)r * LD + c, mk<double>(r == c ? 1.0 : 0.0, 0.0));
       }
       __syncthreads();
@@ -573,20 +576,14 @@ __global__ __launch_bounds__(NT) void k_modes_hess(Prob P, const double* E, doub
             }
           }
           __syncthreads();
-          // from the right, columns k+1..n-1: thread per row, C and Q
-          for (int i = t; i < n; i += NT) {
-            cd s = mk<double>(0.0, 0.0), q = mk<double>(0.0, 0.0);
-            for (int j = k + 1; j < n; ++j) {
-              s = cadd(s, cmul(ldd(Cm + (size_t)i * LD + j), sh.vec[j]));
-              q = cadd(q, cmul(ldd(Qm + (size_t)i * LD + j), sh.vec[j]));
-            }
+          // from the right, columns k+1..n-1: thread per row of C (n) and
+          // of the used half of Q (m)
+          for (int q0 = t; q0 < n + m; q0 += NT) {
+            double2* Ri = q0 < n ? Cm + (size_t)q0 * LD : Qm + (size_t)(q0 - n + m) * LD;
+            cd s = mk<double>(0.0, 0.0);
+            for (int j = k + 1; j < n; ++j) s = cadd(s, cmul(ldd(Ri + j), sh.vec[j]));
             s = cscl(s, g);
-            q = cscl(q, g);
-            for (int j = k + 1; j < n; ++j) {
-              const cd uc = cconj(sh.vec[j]);
-              sto(Cm + (size_t)i * LD + j, cfms(ldd(Cm + (size_t)i * LD + j), s, uc));
-              sto(Qm + (size_t)i * LD + j, cfms(ldd(Qm + (size_t)i * LD + j), q, uc));
-            }
+            for (int j = k + 1; j < n; ++j) sto(Ri + j, cfms(ldd(Ri + j), s, cconj(sh.vec[j])));
           }
         }
         __syncthreads();
