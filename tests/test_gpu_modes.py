@@ -155,3 +155,25 @@ def test_errors(gpu_lib):
     ctx.set_option("self_energy_method", 0)
     T, _, _, st = ctx.solve(ENERGIES, 1e-6, _lib.FP64)     # the decimation path again
     assert st == _lib.OK
+
+
+def test_singular_device_block_is_flagged(gpu_lib):
+    """At eta = 0 a middle slab decoupled from its neighbours, with an
+    on-site level exactly at the energy, makes the sweep's block singular:
+    that energy is flagged non-finite (QTX_ENOTCONV overall) and the other
+    energies of the call are unaffected."""
+    lead = W.random_lead(np.random.default_rng(31), 2)
+    N, m = 3, 2
+    Hd = np.stack([lead.H00, np.diag([0.5, -0.7]).astype(complex), lead.H00])
+    Sd = np.stack([lead.S00, np.eye(2, dtype=complex), lead.S00])
+    Hu = np.zeros((N - 1, m, m), complex)
+    Su = np.zeros((N - 1, m, m), complex)
+    dev = W.Device(N=N, m=m, lead_L=lead, lead_R=lead, V=np.zeros(N), pot_mode=W.POT_DIAG,
+                   Hd=Hd, Hu=Hu, Sd=Sd, Su=Su)
+    ctx = _mode_ctx(dev)
+    E = np.array([0.3, 0.5, 0.9])
+    T, L, info, st = ctx.solve(E, 0.0, _lib.FP64)
+    assert st == _lib.ENOTCONV
+    assert info["flags"][1] & _lib.FLAG_NONFINITE
+    assert info["flags"][0] == 0 and info["flags"][2] == 0
+    assert np.all(np.isfinite(T[[0, 2]])) and np.all(np.abs(T[[0, 2]]) < 1e-12)   # decoupled: no transmission
