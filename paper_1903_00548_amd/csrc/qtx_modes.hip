@@ -26,11 +26,15 @@
 //      is the same injection: sum_gamma W_gamma W_gamma^H = Gamma at eta = 0,
 //      so the sweep takes W with signs +1 (and 0 on unused columns).
 //
-// One workgroup per (energy, lead) job, the matrices in its global
-// workspace (16 M^2 complex doubles).  The outputs have the layout of the
-// decimation's: Sigma, W (padded M x M), signs (M), iteration count (the QR
-// iterations; -1 if the QR did not converge, a matrix was singular or the
-// split did not give m modes each way).
+// Jobs (energy, lead) run in batches through three kernels that share one
+// workspace slot per job (16 M^2 complex doubles): k_modes_hess (steps 1
+// and the Hessenberg form), k_modes_qr (the Schur form; in LDS for M <= 64)
+// and k_modes_post (eigenvectors and steps 3-5).  Only rows m..2m-1 of the
+// Schur vectors are formed: the mode vectors c are that half of the
+// eigenvectors.  The outputs have the layout of the decimation's: Sigma, W
+// (padded M x M), signs (M), iteration count (the QR sweeps; -1 if the QR
+// did not converge, a matrix was singular or the split did not give m modes
+// each way).
 #include "qtx_device.h"
 #include "qtx_internal.h"
 
@@ -180,9 +184,10 @@ constexpr int hpack(int n) { return n + (n - 1) * (n + 2) / 2; }
 // G = [[c, s], [-conj(s), c]] that chases the bulge down the window.  Only
 // H itself is updated inside a sweep (two barriers per rotation; the bulge
 // and the next rotation's pair are passed through LDS); the sweep's
-// rotations are applied to the Schur vectors Q (global, stride ld) after it,
-// row by row without barriers.  Returns false if more than 30 n sweeps were
-// needed; *total counts the sweeps.
+// rotations are applied to rows n/2..n-1 of the Schur vectors Q (global,
+// stride ld; the only rows used later) after it, row by row without
+// barriers.  Returns false if more than 30 n sweeps were needed; *total
+// counts the sweeps.
 template <class HA>
 __device__ bool schur_qr(const HA& H, int n, double2* Qm, int ld, ModeShared& sh, int* total) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -303,8 +308,8 @@ __device__ __forceinline__ void wave_sync() {
 // schur_qr for n <= 128 with H in LDS: wave 0 runs the deflation tests and
 // the bulge chase alone (lane-parallel rows and columns, no block barrier
 // inside a sweep), writing each sweep's rotations to one of two buffers;
-// meanwhile waves 1..3 apply the previous sweep's rotations to Q.  One
-// block barrier per sweep.
+// meanwhile waves 1..3 apply the previous sweep's rotations to rows
+// n/2..n-1 of Q.  One block barrier per sweep.
 __device__ bool schur_qr_wave(const HLds& H, int n, double2* Qm, int ld, ModeShared& sh, int* total) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const double eps = 2.220446049250313e-16;
