@@ -199,6 +199,10 @@ qtx_status qtx_self_energy(qtx_ctx* ctx, const double* E, int nE, double eta,
  * same values).  name / accepted values / default:
  *   "decimation_tol"        (0, 1)        1e-14  doubling stops when the
  *                           couplings fall below this times |D0|;
+ *   "decimation_refine_cond" [0, inf]     1e4    a doubling refines its
+ *                           solve with e once (X += e^-1 ([a|b] - e X))
+ *                           when ||e||_F ||e^-1||_F exceeds this; 0 refines
+ *                           every doubling, inf none;
  *   "decimation_max_iters"  [1, 1000]     60     doublings before
  *                           QTX_FLAG_DEC_NOTCONV;
  *   "refine_tol"            (0, 1)        1e-12  QTX_MIXED: refinement stops

@@ -114,6 +114,7 @@ struct qtx_ctx {
 
   // tunables
   double dec_tol = 1e-14;
+  double dec_rcond = 1e4;         // refine g [a | b] when ||e||_F ||e^-1||_F exceeds this
   int dec_maxit = 60;
   int chunk = 4096;
   int wg_per_cu = 2;
@@ -200,6 +201,8 @@ int wgs_per_cu(const qtx_ctx* c, int M, bool mixed) {
   return M > 64 ? 1 : c->wg_per_cu;
 }
 
+qtx::DecOpts dec_opts(const qtx_ctx* c) { return qtx::DecOpts{c->dec_tol, c->dec_rcond, c->dec_maxit, c->heavy_tol}; }
+
 qtx::Prob make_prob(const qtx_ctx* c) {
   qtx::Prob P;
   P.N = c->N;
@@ -266,9 +269,9 @@ qtx_status stage_decimate(qtx_ctx* c, const double* E_dev, int nE, double eta, b
   QTX_HIP(c, c->dscr.ensure((size_t)grid * qtx::dec_ws_elems(M) * sizeof(double2)));
   qtx::Prob P = make_prob(c);
   QTX_HIP(c, record(c, c->ev_dec, c->n_dec));
-  QTX_HIP(c, qtx::run_decimate(M, P, qtx::BatchDesc{}, E_dev, nE, eta, sides, c->dec_tol, c->dec_maxit, c->heavy_tol,
-                               c->dscr.as<double2>(), grid, c->sig.as<double2>(), c->wf.as<double2>(),
-                               c->sgn.as<double>(), c->iters.as<int>(), c->nheavy.as<int>(), c->stream));
+  QTX_HIP(c, qtx::run_decimate(M, P, qtx::BatchDesc{}, E_dev, nE, eta, sides, dec_opts(c), c->dscr.as<double2>(),
+                               grid, c->sig.as<double2>(), c->wf.as<double2>(), c->sgn.as<double>(),
+                               c->iters.as<int>(), c->nheavy.as<int>(), c->stream));
   QTX_HIP(c, record(c, c->ev_dec, c->n_dec));
   return QTX_OK;
 }
@@ -752,6 +755,9 @@ qtx_status qtx_set_option(qtx_ctx* c, const char* name, double value) {
   if (n == "decimation_tol") {
     if (!(value > 0.0 && value < 1.0)) return fail(c, QTX_EINVAL, "decimation_tol must be in (0, 1)");
     c->dec_tol = value;
+  } else if (n == "decimation_refine_cond") {
+    if (!(value >= 0.0)) return fail(c, QTX_EINVAL, "decimation_refine_cond must be >= 0");
+    c->dec_rcond = value;
   } else if (n == "decimation_max_iters") {
     if (!integral || value < 1 || value > 1000) return fail(c, QTX_EINVAL, "decimation_max_iters must be in [1, 1000]");
     c->dec_maxit = (int)value;
@@ -806,6 +812,7 @@ qtx_status qtx_problem_create(qtx_ctx* parent, qtx_ctx** problem) {
   c->device = parent->device;
   c->num_cu = parent->num_cu;
   c->dec_tol = parent->dec_tol;
+  c->dec_rcond = parent->dec_rcond;
   c->dec_maxit = parent->dec_maxit;
   c->chunk = parent->chunk;
   c->wg_per_cu = parent->wg_per_cu;
@@ -866,9 +873,9 @@ qtx_status enqueue_batch(qtx_ctx* c, const std::vector<BatchChunk>& chunks, cons
     qtx::Prob P0{};
     P0.M = g.M;
     const int gdec = std::max(1, std::min(g.njobs, c->num_cu * wg));
-    QTX_HIP(c, qtx::run_decimate(g.M, P0, b, b.job_E, g.njobs, eta, 2, c->dec_tol, c->dec_maxit, c->heavy_tol,
-                                 c->dscr.as<double2>(), gdec, sc.sig.as<double2>(), sc.wf.as<double2>(),
-                                 sc.sgn.as<double>(), sc.iters.as<int>(), sc.nheavy.as<int>(), c->stream));
+    QTX_HIP(c, qtx::run_decimate(g.M, P0, b, b.job_E, g.njobs, eta, 2, dec_opts(c), c->dscr.as<double2>(), gdec,
+                                 sc.sig.as<double2>(), sc.wf.as<double2>(), sc.sgn.as<double>(), sc.iters.as<int>(),
+                                 sc.nheavy.as<int>(), c->stream));
   }
   for (const BatchChunk& k : chunks) {
     const int M = k.M;
@@ -886,10 +893,9 @@ qtx_status enqueue_batch(qtx_ctx* c, const std::vector<BatchChunk>& chunks, cons
     P0.M = M;
     if (!cached) {
       const int gdec = std::max(1, std::min(k.njobs, c->num_cu * wg));
-      QTX_HIP(c, qtx::run_decimate(M, P0, b, c->bE.as<double>() + k.item0, k.nitems, eta, 2, c->dec_tol,
-                                   c->dec_maxit, c->heavy_tol, c->dscr.as<double2>(), gdec, c->sig.as<double2>(),
-                                   c->wf.as<double2>(), c->sgn.as<double>(), c->iters.as<int>(),
-                                   c->nheavy.as<int>(), c->stream));
+      QTX_HIP(c, qtx::run_decimate(M, P0, b, c->bE.as<double>() + k.item0, k.nitems, eta, 2, dec_opts(c),
+                                   c->dscr.as<double2>(), gdec, c->sig.as<double2>(), c->wf.as<double2>(),
+                                   c->sgn.as<double>(), c->iters.as<int>(), c->nheavy.as<int>(), c->stream));
     }
     const int grid = std::max(1, std::min(k.nitems, c->num_cu * wg));
     qtx::SweepArgs a{};
@@ -1045,7 +1051,7 @@ qtx_status qtx_solve_batch(qtx_ctx* c, int nprob, qtx_ctx* const* probs, const d
     }
   } guard{c};
   if (cached) {
-    const std::vector<double> params = {eta, c->dec_tol, (double)c->dec_maxit, c->heavy_tol};
+    const std::vector<double> params = {eta, c->dec_tol, c->dec_rcond, (double)c->dec_maxit, c->heavy_tol};
     if (params != c->cache_params) {
       for (auto& kv : c->sigcache) {
         kv.second.index.clear();
@@ -1222,6 +1228,8 @@ qtx_status qtx_solve_batch(qtx_ctx* c, int nprob, qtx_ctx* const* probs, const d
   std::memcpy(&eb, &c->heavy_tol, sizeof(eb));
   sig.push_back(eb);
   std::memcpy(&eb, &c->dec_tol, sizeof(eb));
+  sig.push_back(eb);
+  std::memcpy(&eb, &c->dec_rcond, sizeof(eb));
   sig.push_back(eb);
   sig.push_back(c->dec_maxit);
   for (void* bp : {c->sig.p, c->wf.p, c->sgn.p, c->dscr.p, c->sws.p, c->part.p, c->bprobs.p, c->bE.p, c->bT.p,

@@ -130,9 +130,20 @@ __host__ __device__ constexpr size_t dec_ws_elems(int M) {
 // Padded block size for a physical block size m (1 <= m <= 128).
 inline int padded_block(int m) { return m <= 64 ? ((m + 15) / 16) * 16 : (m <= 96 ? 96 : 128); }
 
+// Decimation settings: stop when the couplings fall below tol |D0| (at most
+// maxit doublings); refine g [a | b] when ||e||_F ||e^-1||_F > rcond (every
+// doubling for rcond = 0); heavy_tol sets the count of leading broadening
+// columns reported per contact.
+struct DecOpts {
+  double tol;
+  double rcond;
+  int maxit;
+  double heavy_tol;
+};
+
 hipError_t run_decimate(int M, const Prob& P, const BatchDesc& b, const double* E, int nE, double eta, int sides,
-                        double tol, int maxit, double heavy_tol, double2* scratch, int grid, double2* sig,
-                        double2* wf, double* sgn, int* iters, int* nheavy, hipStream_t st);
+                        const DecOpts& o, double2* scratch, int grid, double2* sig, double2* wf, double* sgn,
+                        int* iters, int* nheavy, hipStream_t st);
 
 // mixed = false: FP64 sweep (with a.elist: re-solve of the listed energies).
 // mixed = true: FP32 sweep plus refinement of the heavy columns.

@@ -363,14 +363,17 @@ __device__ __forceinline__ Prob load_prob(const Prob* pp) {
 // gives e' = e - a g b - b g a, a' = -a g a, b' = -b g b with g = e^-1; the
 // surface of a right lead keeps only -a g b and that of a left lead only
 // -b g a.  Sigma = D0 - (converged surface block).
-// g [a | b] comes from the blocked Gauss-Jordan inverse followed by one step
-// of iterative refinement, X <- X + e^-1 ([a | b] - e X): the explicit
-// inverse alone loses up to two digits when D0 is ill-conditioned, one
-// refinement step restores the accuracy of an LU solve.
+// g [a | b] comes from the blocked Gauss-Jordan inverse; the product with
+// the explicit inverse carries an error of order kappa(e) u, so when the
+// estimate kappa_F = ||e||_F ||e^-1||_F exceeds rcond (always for rcond = 0)
+// one step of iterative refinement, X <- X + e^-1 ([a | b] - e X), brings
+// it back to the accuracy of an LU solve.  Well-conditioned doublings, most
+// of them away from the lead's band edges, skip the step's two products.
 template <int M>
 __global__ __launch_bounds__(NT, M > 64 ? 1 : 2) void k_decimate(Prob P0, BatchDesc b, const double* E, int nE,
-                                                                 double eta, int sides, double tol, int maxit,
-                                                                 double heavy_tol, double2* scratch, double2* sig,
+                                                                 double eta, int sides, double tol, double rcond,
+                                                                 int maxit, double heavy_tol, double2* scratch,
+                                                                 double2* sig,
                                                                  double2* wf, double* sgn, int* iters, int* nheavy) {
   constexpr int MT = M / 16, MM = M * M, S = M + 1, LB = 2 * M;
   constexpr bool BIG = M > 64;                    // working matrix in the global workspace
@@ -441,14 +444,36 @@ __global__ __launch_bounds__(NT, M > 64 ? 1 : 2) void k_decimate(Prob P0, BatchD
     for (it = 1; it <= maxit; ++it) {
       const double2* AB = ab[cur];
       double2* ABn = ab[cur ^ 1];
+      double ne2 = 0.0;
       for (int idx = t; idx < MM; idx += NT) {
         const int r = idx / M, c = idx - r * M;
-        mat[r * S + c] = ldd(eps + idx);
+        const cpx<double> v = ldd(eps + idx);
+        mat[r * S + c] = v;
+        ne2 += v.re * v.re + v.im * v.im;
       }
       __syncthreads();
       gj_inverse<double, M>(mat, S, u.y, sc);
-      // X = e^-1 [a | b], then one refinement step; each wave owns whole
-      // column tiles of X, so the three products need no barrier
+      // kappa_F from the two sums of squares (the inverse is stored with its
+      // rows permuted, which leaves its norm unchanged); every thread sums
+      // the same partials in the same order, so the decision is uniform
+      bool refine_x = true;
+      if (rcond > 0.0) {
+        double ng2 = 0.0;
+        for (int idx = t; idx < MM; idx += NT) {
+          const int r = idx / M, c = idx - r * M;
+          const cpx<double> v = mat[r * S + c];
+          ng2 += v.re * v.re + v.im * v.im;
+        }
+        ne2 = wave_sum(ne2);
+        ng2 = wave_sum(ng2);
+        if (lane == 0) { red[0][w] = ne2; red[1][w] = ng2; }
+        __syncthreads();
+        ne2 = 0.0; ng2 = 0.0;
+        for (int q = 0; q < NWAVE; ++q) { ne2 += red[0][q]; ng2 += red[1][q]; }
+        refine_x = !(ne2 * ng2 <= rcond * rcond);      // a non-finite estimate refines
+      }
+      // X = e^-1 [a | b], then the refinement step if needed; each wave owns
+      // whole column tiles of X, so the three products need no barrier
 #pragma unroll 1
       for (int tj = w; tj < 2 * MT; tj += NWAVE) {
         ctile<double> acc[MT];
@@ -458,6 +483,7 @@ __global__ __launch_bounds__(NT, M > 64 ? 1 : 2) void k_decimate(Prob P0, BatchD
         tiles_foreach<double, MT>(acc, tj, [&](int row, int col, int ti, int r) {
           X[(unsigned)(sc.pinv[row] * LB + col)] = make_double2(acc[ti].re[r], acc[ti].im[r]);
         });
+        if (!refine_x) continue;
         __threadfence_block();
         // residual R = [a | b] - e X
         tiles_foreach<double, MT>(acc, tj, [&](int row, int col, int ti, int r) {
@@ -1358,10 +1384,10 @@ __global__ __launch_bounds__(NT, 1) void k_bands(const double2* lead, int m, dou
 // ------------------------------------------------------------- launchers
 template <int M>
 hipError_t launch_decimate(const Prob& P, const BatchDesc& b, const double* E, int nE, double eta, int sides,
-                           double tol, int maxit, double heavy_tol, double2* scratch, int grid, double2* sig,
-                           double2* wf, double* sgn, int* iters, int* nheavy, hipStream_t st) {
-  hipLaunchKernelGGL((k_decimate<M>), dim3(grid), dim3(NT), 0, st, P, b, E, nE, eta, sides, tol, maxit, heavy_tol,
-                     scratch, sig, wf, sgn, iters, nheavy);
+                           const DecOpts& o, double2* scratch, int grid, double2* sig, double2* wf, double* sgn,
+                           int* iters, int* nheavy, hipStream_t st) {
+  hipLaunchKernelGGL((k_decimate<M>), dim3(grid), dim3(NT), 0, st, P, b, E, nE, eta, sides, o.tol, o.rcond, o.maxit,
+                     o.heavy_tol, scratch, sig, wf, sgn, iters, nheavy);
   return hipGetLastError();
 }
 
@@ -1372,11 +1398,10 @@ hipError_t launch_sweep(const Prob& P, const SweepArgs& a, const BatchDesc& b, i
 }
 
 hipError_t run_decimate(int M, const Prob& P, const BatchDesc& b, const double* E, int nE, double eta, int sides,
-                        double tol, int maxit, double heavy_tol, double2* scratch, int grid, double2* sig,
-                        double2* wf, double* sgn, int* iters, int* nheavy, hipStream_t st) {
+                        const DecOpts& o, double2* scratch, int grid, double2* sig, double2* wf, double* sgn,
+                        int* iters, int* nheavy, hipStream_t st) {
 #define QTX_DEC(MM) \
-  return launch_decimate<MM>(P, b, E, nE, eta, sides, tol, maxit, heavy_tol, scratch, grid, sig, wf, sgn, iters, \
-                             nheavy, st)
+  return launch_decimate<MM>(P, b, E, nE, eta, sides, o, scratch, grid, sig, wf, sgn, iters, nheavy, st)
   switch (M) {
     case 16: QTX_DEC(16);
     case 32: QTX_DEC(32);

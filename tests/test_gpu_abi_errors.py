@@ -90,6 +90,7 @@ def test_solve_argument_validation(gpu_lib, ready):
 @pytest.mark.parametrize("name,bad,good", [
     ("decimation_tol", [0.0, 1.0, -1e-3, np.nan], 1e-14),
     ("decimation_max_iters", [0, 1001, 2.5], 60),
+    ("decimation_refine_cond", [-1.0, np.nan], 1e4),
     ("refine_tol", [0.0, 1.0], 1e-12),
     ("refine_max_steps", [-1, 21, 1.5], 3),
     ("refine_weight_tol", [-0.1, 1.1], 1e-8),
