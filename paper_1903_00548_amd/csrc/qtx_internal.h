@@ -120,11 +120,11 @@ inline size_t sweep_ws_bytes(int N, int M, bool mixed, bool dm = false) {
          (size_t)N * 2 * MM * sizeof(double2) + big;
 }
 
-// Per-workgroup decimation workspace (complex doubles): e, the two surface
-// blocks, [a | b] twice, g [a | b], the residual, and for M > 64 the working
-// matrix M x (M + 1).
+// Per-workgroup decimation workspace (complex doubles): e, the right surface
+// block, [a | b], g [a | b], the residual, and for M > 64 the working matrix
+// M x (M + 1).
 __host__ __device__ constexpr size_t dec_ws_elems(int M) {
-  return 13 * (size_t)M * M + (M > 64 ? (size_t)M * (M + 1) : 0);
+  return 8 * (size_t)M * M + (M > 64 ? (size_t)M * (M + 1) : 0);
 }
 
 // Padded block size for a physical block size m (1 <= m <= 128).

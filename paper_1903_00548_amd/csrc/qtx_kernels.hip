@@ -362,7 +362,9 @@ __device__ __forceinline__ Prob load_prob(const Prob* pp) {
 // couplings a (slab j -> j+1) and b (j+1 -> j), eliminating every other slab
 // gives e' = e - a g b - b g a, a' = -a g a, b' = -b g b with g = e^-1; the
 // surface of a right lead keeps only -a g b and that of a left lead only
-// -b g a.  Sigma = D0 - (converged surface block).
+// -b g a.  Sigma = D0 - (converged surface block).  Only e and the right
+// surface eR are stored: the left surface is e + D0 - eR, so Sigma_L =
+// eR - e and Sigma_R = D0 - eR.
 // g [a | b] comes from the blocked Gauss-Jordan inverse; the product with
 // the explicit inverse carries an error of order kappa(e) u, so when the
 // estimate kappa_F = ||e||_F ||e^-1||_F exceeds rcond (always for rcond = 0)
@@ -387,14 +389,16 @@ __global__ __launch_bounds__(NT, M > 64 ? 1 : 2) void k_decimate(Prob P0, BatchD
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   double2* ws = scratch + (size_t)blockIdx.x * dec_ws_elems(M);
   cpx<double>* mat;
-  if constexpr (BIG) mat = (cpx<double>*)(ws + 13 * MM);
+  if constexpr (BIG) mat = (cpx<double>*)(ws + 8 * MM);
   else mat = mat_l;
+  // the part touched by every doubling (e, eR, [a | b], X: 6 M^2) is kept
+  // together so that the resident workgroups' share fits the last-level
+  // cache; the residual is used only by the doublings that refine
   double2* eps = ws;
-  double2* esL = ws + MM;
-  double2* esR = ws + 2 * MM;
-  double2* ab[2] = {ws + 3 * MM, ws + 5 * MM};   // [a | b], M x 2M, ping-pong
-  double2* X = ws + 7 * MM;                       // [g a | g b]
-  double2* Rr = ws + 9 * MM;                      // residual
+  double2* esR = ws + MM;
+  double2* AB = ws + 2 * MM;                      // [a | b], M x 2M, updated in place
+  double2* X = ws + 4 * MM;                       // [g a | g b]
+  double2* Rr = ws + 6 * MM;                      // residual
   const int njobs = b.probs ? b.njobs : nE * sides;
   for (int job = blockIdx.x; job < njobs; job += gridDim.x) {
     // single problem: jobs (energy, side), or one job per energy when both
@@ -429,9 +433,9 @@ __global__ __launch_bounds__(NT, M > 64 ? 1 : 2) void k_decimate(Prob P0, BatchD
       double2 uu = make_double2(zx.re * s.re - zx.im * s.im - h.re, zx.re * s.im + zx.im * s.re - h.im);
       s = ldd(S01 + c * M + r); h = ldd(H01 + c * M + r);
       double2 ll = make_double2(zx.re * s.re + zx.im * s.im - h.re, zx.im * s.re - zx.re * s.im + h.im);
-      eps[idx] = d0; esL[idx] = d0; esR[idx] = d0;
-      ab[0][r * LB + c] = uu;
-      ab[0][r * LB + M + c] = ll;
+      eps[idx] = d0; esR[idx] = d0;
+      AB[r * LB + c] = uu;
+      AB[r * LB + M + c] = ll;
       scl = fmax(scl, fabs(d0.x) + fabs(d0.y));
     }
     scl = wave_maxd(scl);
@@ -439,11 +443,9 @@ __global__ __launch_bounds__(NT, M > 64 ? 1 : 2) void k_decimate(Prob P0, BatchD
     __syncthreads();
     scl = 0.0;
     for (int q = 0; q < NWAVE; ++q) scl = fmax(scl, red[0][q]);
-    int cur = 0, it = 0;
+    int it = 0;
     bool conv = false;
     for (it = 1; it <= maxit; ++it) {
-      const double2* AB = ab[cur];
-      double2* ABn = ab[cur ^ 1];
       double ne2 = 0.0;
       for (int idx = t; idx < MM; idx += NT) {
         const int r = idx / M, c = idx - r * M;
@@ -510,7 +512,8 @@ __global__ __launch_bounds__(NT, M > 64 ? 1 : 2) void k_decimate(Prob P0, BatchD
       // doubling update: output column tile tj reads column tiles tj (g a)
       // and MT + tj (g b) of X, written by other waves unless M/16 == NWAVE.
       // g is dead from here on: a, then b, is staged in its LDS buffer as
-      // the shared A operand of the two products that use it.
+      // the shared A operand of the two products that use it, so a' and b'
+      // overwrite a and b in global memory once their staging is done.
       __syncthreads();
       double na = 0.0, nb = 0.0;
 #pragma unroll 1
@@ -538,10 +541,9 @@ __global__ __launch_bounds__(NT, M > 64 ? 1 : 2) void k_decimate(Prob P0, BatchD
               if (q < 2) {
                 double2 v = eps[idx];
                 v.x -= re; v.y -= im; eps[idx] = v;
-                double2* es = q == 0 ? esR : esL;
-                v = es[idx]; v.x -= re; v.y -= im; es[idx] = v;
+                if (q == 0) { v = esR[idx]; v.x -= re; v.y -= im; esR[idx] = v; }
               } else {
-                ABn[(unsigned)(row * LB + col) + (q == 3 ? M : 0)] = make_double2(-re, -im);
+                AB[(unsigned)(row * LB + col) + (q == 3 ? M : 0)] = make_double2(-re, -im);
                 if (q == 2) na = fmax(na, fabs(re) + fabs(im));
                 else nb = fmax(nb, fabs(re) + fabs(im));
               }
@@ -556,17 +558,22 @@ __global__ __launch_bounds__(NT, M > 64 ? 1 : 2) void k_decimate(Prob P0, BatchD
       __syncthreads();
       na = 0.0; nb = 0.0;
       for (int q = 0; q < NWAVE; ++q) { na = fmax(na, red[0][q]); nb = fmax(nb, red[1][q]); }
-      cur ^= 1;
       __syncthreads();
       if (na + nb < tol * scl) { conv = true; break; }
     }
     if (!conv) it = -maxit;
-    // Sigma = D0 - surface block
+    // Sigma_L = eR - e, Sigma_R = D0 - eR
     for (int idx = t; idx < MM; idx += NT) {
-      cpx<double> s = ldd(S00 + idx), h = ldd(H00 + idx);
-      const double dr = zx.re * s.re - zx.im * s.im - h.re, di = zx.re * s.im + zx.im * s.re - h.im;
-      if (side != 1) { double2 v = esL[idx]; sig[(size_t)(2 * e) * MM + idx] = make_double2(dr - v.x, di - v.y); }
-      if (side != 0) { double2 v = esR[idx]; sig[(size_t)(2 * e + 1) * MM + idx] = make_double2(dr - v.x, di - v.y); }
+      const double2 vr = esR[idx];
+      if (side != 1) {
+        const double2 v = eps[idx];
+        sig[(size_t)(2 * e) * MM + idx] = make_double2(vr.x - v.x, vr.y - v.y);
+      }
+      if (side != 0) {
+        cpx<double> s = ldd(S00 + idx), h = ldd(H00 + idx);
+        const double dr = zx.re * s.re - zx.im * s.im - h.re, di = zx.re * s.im + zx.im * s.re - h.im;
+        sig[(size_t)(2 * e + 1) * MM + idx] = make_double2(dr - vr.x, di - vr.y);
+      }
     }
     __syncthreads();
     for (int s = 0; s < 2; ++s) {
