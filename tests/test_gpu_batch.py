@@ -182,3 +182,30 @@ def test_sigma_cache_replacement_across_calls(gpu_lib):
     # both contacts of an item share one entry (same lead, same potential):
     # per new call 10 misses and 10 hits, the repeat 20 hits
     assert (hits, misses) == (40, 20) and slots == 16
+
+
+def test_sigma_cache_emptied_by_decimation_options(gpu_lib):
+    """Changing a decimation option (the refinement threshold, then the
+    tolerance) empties the self-energy cache: the next batch decimates
+    every contact again, and its results equal a single-problem solve with
+    the same options bit for bit."""
+    lead = W.random_lead(np.random.default_rng(47), 16)
+    dev = W.Device(N=5, m=16, lead_L=lead, lead_R=lead, V=np.zeros(5), pot_mode=W.POT_DIAG)
+    E = np.linspace(-1.0, 1.0, 12)
+    ctx = _lib.Context(0)
+    p = _lib.fill(ctx.problem(), dev)
+    ref = _lib.context_for(dev, 0)
+    _lib.solve_batch(ctx, [p], [E], ETA)
+    _lib.solve_batch(ctx, [p], [E], ETA)
+    hits, misses, _ = ctx.sigma_cache_stats()
+    # both contacts of an item share one entry: 12 misses and 12 hits, then 24 hits
+    assert (hits, misses) == (36, 12)
+    for name, value in (("decimation_refine_cond", 0.0), ("decimation_tol", 1e-13)):
+        ctx.set_option(name, value)
+        ref.set_option(name, value)
+        Ts, Ls, _ = _lib.solve_batch(ctx, [p], [E], ETA)
+        h, m_, _ = ctx.sigma_cache_stats()
+        assert (h - hits, m_ - misses) == (12, 12), name
+        hits, misses = h, m_
+        Tr, Lr, _, _ = ref.solve(E, ETA, _lib.FP64)
+        assert np.array_equal(Ts[0], Tr) and np.array_equal(Ls[0], Lr), name
