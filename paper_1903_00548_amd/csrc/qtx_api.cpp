@@ -355,8 +355,9 @@ qtx_status density_matrix_core(qtx_ctx* c, const double* E_dev, const double* wL
   if (s != QTX_OK) return s;
   const size_t mm = (size_t)m * m, nblk = 2 * (size_t)N - 1;
   if (nE == 0) {
-    QTX_HIP(c, hipMemsetAsync(out_d, 0, (size_t)N * mm * sizeof(double2), c->stream));
-    if (N > 1) QTX_HIP(c, hipMemsetAsync(out_o, 0, (size_t)(N - 1) * mm * sizeof(double2), c->stream));
+    // the sum over no accumulators writes zeros (rho is not read); a kernel
+    // rather than memsets, so that a caller may capture the call in a graph
+    QTX_HIP(c, qtx::run_dm_reduce(out_d, 0, 0, N, M, m, out_d, out_o, c->stream));
     return QTX_OK;
   }
   if (!E_dev || !wL_dev || !wR_dev || !T_dev) return fail(c, QTX_EINVAL, "E, wL, wR and T must not be NULL");

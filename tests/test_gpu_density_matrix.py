@@ -174,3 +174,27 @@ def test_context_destroy_frees_device_memory(gpu_lib):
         cycle()
     free1, _ = torch.cuda.mem_get_info()
     assert free0 - free1 < (1 << 30), (free0, free1)
+
+
+@pytest.mark.parametrize("case", [small_cases.CASES[0], small_cases.CASES[2]], ids=["N5", "N1"])
+def test_device_entry_empty_grid_zeroes_outputs(gpu_lib, case):
+    """The device entry point with no energies writes zeros over whatever
+    the output blocks held (one slab: only the diagonal block exists)."""
+    import torch
+    dev = small_cases.device(*case)
+    ctx = _lib.context_for(dev, 0)
+    ctx.set_stream(torch.cuda.current_stream().cuda_stream)
+    N, m = dev.N, dev.m
+    rd = torch.full((N, m, m), 7.0 + 3.0j, dtype=torch.complex128, device="cuda")
+    ro = torch.full((max(N - 1, 1), m, m), -2.0 + 1.0j, dtype=torch.complex128, device="cuda")
+    E = torch.zeros(1, dtype=torch.float64, device="cuda")
+    T = torch.zeros(1, dtype=torch.float64, device="cuda")
+    st = ctx.density_matrix_device(E.data_ptr(), E.data_ptr(), E.data_ptr(), 0, 1e-6, rd.data_ptr(),
+                                   ro.data_ptr() if N > 1 else 0, T.data_ptr())
+    torch.cuda.synchronize()
+    assert st == _lib.OK
+    assert not rd.cpu().numpy().any()
+    if N > 1:
+        assert not ro.cpu().numpy().any()
+    else:
+        assert np.all(ro.cpu().numpy() == -2.0 + 1.0j)          # not an output at N = 1
