@@ -139,7 +139,13 @@ qtx_status qtx_solve(qtx_ctx* ctx, const double* E, int nE, double eta,
  * enqueued on the context stream without a host synchronisation.  info_dev
  * may be NULL; the other outputs as in qtx_solve.  The buffers must stay
  * alive until the stream has executed the work.  Per-energy convergence is
- * reported through info_dev only (the return value does not wait for it). */
+ * reported through info_dev only (the return value does not wait for it).
+ * The call may be captured in a HIP graph on the context stream once an
+ * earlier call with at least as many energies, the same precision and the
+ * same method has sized the context's workspaces.  It then issues only
+ * kernel launches; a replay reads the energies at E_dev and recomputes
+ * everything.  A context with several captured graphs shares one workspace
+ * among them, so their replays must not overlap. */
 qtx_status qtx_solve_device(qtx_ctx* ctx, const double* E_dev, int nE, double eta,
                             qtx_precision prec, double* T_dev, double* ldos_dev,
                             qtx_info* info_dev);
