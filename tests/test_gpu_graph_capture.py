@@ -2,7 +2,8 @@
 torch.cuda.CUDAGraph on the context's stream), once a first eager call has
 sized the context's workspaces.  Every replay, with the outputs poisoned
 and other eager library work and synchronisations in between, reproduces
-the eager result bit for bit, for both precisions."""
+the eager result bit for bit: FP64 and mixed precision with decimated
+self-energies, and the mode-space self-energies at eta = 0."""
 import numpy as np
 import pytest
 
@@ -12,13 +13,16 @@ from paper_1903_00548_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("prec", [_lib.FP64, _lib.MIXED], ids=["fp64", "mixed"])
-def test_solve_device_replays_in_a_graph(gpu_lib, prec):
+@pytest.mark.parametrize("prec,method", [(_lib.FP64, 0), (_lib.MIXED, 0), (_lib.FP64, 1)],
+                         ids=["fp64", "mixed", "modes"])
+def test_solve_device_replays_in_a_graph(gpu_lib, prec, method):
     import torch
     wl = W.config0()
     dev = wl.device
     nE = len(wl.E)
+    eta = wl.eta if method == 0 else 0.0
     ctx = _lib.context_for(dev, 0)
+    ctx.set_option("self_energy_method", method)
     s = torch.cuda.Stream()
     ctx.set_stream(s.cuda_stream)
     E_t = torch.tensor(wl.E, dtype=torch.float64, device="cuda")
@@ -27,7 +31,7 @@ def test_solve_device_replays_in_a_graph(gpu_lib, prec):
     I_t = torch.zeros(nE * _lib.INFO_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
 
     def solve():
-        ctx.solve_device(E_t.data_ptr(), nE, wl.eta, prec, T_t.data_ptr(), L_t.data_ptr(), I_t.data_ptr())
+        ctx.solve_device(E_t.data_ptr(), nE, eta, prec, T_t.data_ptr(), L_t.data_ptr(), I_t.data_ptr())
 
     torch.cuda.synchronize()
     with torch.cuda.stream(s):
