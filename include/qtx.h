@@ -252,6 +252,12 @@ qtx_status qtx_self_energy(qtx_ctx* ctx, const double* E, int nE, double eta,
  *                           qtx_info.dec_iters then counts QR iterations;
  *   "mode_tol"              (0, 1e-2]     1e-8   method 1: modes with
  *                           ||lambda| - 1| <= mode_tol travel;
+ *   "sweep_workspace_bytes" (0, 1e13]     160 GiB device memory for the
+ *                           sweep workspaces of the resident workgroups
+ *                           ((N + 1) 2 M^2 complex per workgroup in FP64):
+ *                           fewer workgroups run when they do not all fit,
+ *                           with the same results; a call whose single
+ *                           workgroup would not fit returns QTX_ENOMEM;
  *   "density_matrix_bytes"  [0, 1e13]     64 GiB device memory for the
  *                           per-workgroup accumulators of qtx_density_matrix
  *                           (fewer workgroups run when they do not all fit);

@@ -76,6 +76,7 @@ struct qtx_ctx {
   DevBuf redo, elist, ecount;                  // mixed: energies re-solved in FP64
   DevBuf dmw, rho, dmout;                      // density-matrix blocks: weights, accumulators, sums
   double dm_bytes = 64.0 * (1ull << 30);       // cap on the per-workgroup accumulators
+  double sweep_bytes = 160.0 * (1ull << 30);   // cap on the resident workgroups' sweep workspaces
   int se_method = 0;                           // 0 decimation, 1 complex band structure (mode space)
   double mode_tol = 1e-8;                      // |lambda| tolerance of travelling modes
   DevBuf mscr, mjst;                           // complex-band-structure workspace, per-job status
@@ -201,6 +202,16 @@ int wgs_per_cu(const qtx_ctx* c, int M, bool mixed) {
   return M > 64 ? 1 : c->wg_per_cu;
 }
 
+// Resident workgroups of a sweep launch over `items` energies of block size
+// M: the occupancy limit, lowered until their workspaces of wsb bytes each
+// fit in sweep_workspace_bytes; 0 if not even one fits.  Every energy is
+// solved by one workgroup, so the grid does not change the results.
+int sweep_grid(const qtx_ctx* c, int items, int M, bool mixed, size_t wsb) {
+  const int fit = (int)std::min<double>(1 << 20, std::floor(c->sweep_bytes / (double)wsb));
+  if (fit < 1) return 0;
+  return std::max(1, std::min({items, c->num_cu * wgs_per_cu(c, M, mixed), fit}));
+}
+
 qtx::DecOpts dec_opts(const qtx_ctx* c) { return qtx::DecOpts{c->dec_tol, c->dec_rcond, c->dec_maxit, c->heavy_tol}; }
 
 qtx::Prob make_prob(const qtx_ctx* c) {
@@ -292,8 +303,9 @@ qtx_status solve_device_core(qtx_ctx* c, const double* E_dev, int nE, double eta
     const int ne = std::min(c->chunk, nE - e0);
     s = stage_decimate(c, E_dev + e0, ne, eta, mixed);
     if (s != QTX_OK) return s;
-    const int grid = std::max(1, std::min(ne, c->num_cu * wgs_per_cu(c, M, mixed)));
     const size_t wsb = qtx::sweep_ws_bytes(N, M, mixed);
+    const int grid = sweep_grid(c, ne, M, mixed, wsb);
+    if (grid < 1) return fail(c, QTX_ENOMEM, "sweep_workspace_bytes is below one workgroup's sweep workspace");
     QTX_HIP(c, c->sws.ensure((size_t)grid * wsb));
     QTX_HIP(c, c->part.ensure((size_t)grid * 4 * 2 * N * (mixed ? 2 : 1) * sizeof(double)));
     if (mixed) {
@@ -368,8 +380,10 @@ qtx_status density_matrix_core(qtx_ctx* c, const double* E_dev, const double* wL
   // one accumulator per workgroup; every workgroup takes its first energy
   // in the first launch (grid <= the first launch's energies)
   const int first = std::min(c->chunk, nE);
-  const int grid = std::max(1, std::min({first, c->num_cu * wgs_per_cu(c, M, false), cap}));
   const size_t wsb = qtx::sweep_ws_bytes(N, M, false, true);
+  const int sgrid = sweep_grid(c, first, M, false, wsb);
+  if (sgrid < 1) return fail(c, QTX_ENOMEM, "sweep_workspace_bytes is below one workgroup's sweep workspace");
+  const int grid = std::min(sgrid, cap);
   QTX_HIP(c, c->rho.ensure((size_t)grid * per_wg));
   QTX_HIP(c, c->sws.ensure((size_t)grid * wsb));
   QTX_HIP(c, c->part.ensure((size_t)grid * 4 * 2 * N * sizeof(double)));
@@ -788,6 +802,9 @@ qtx_status qtx_set_option(qtx_ctx* c, const char* name, double value) {
   } else if (n == "use_graph") {
     if (!(value == 0.0 || value == 1.0)) return fail(c, QTX_EINVAL, "use_graph must be 0 or 1");
     c->use_graph = value != 0.0;
+  } else if (n == "sweep_workspace_bytes") {
+    if (!(value > 0.0 && value <= 1e13)) return fail(c, QTX_EINVAL, "sweep_workspace_bytes must be in (0, 1e13]");
+    c->sweep_bytes = value;
   } else if (n == "density_matrix_bytes") {
     if (!(value >= 0.0 && value <= 1e13)) return fail(c, QTX_EINVAL, "density_matrix_bytes must be in [0, 1e13]");
     c->dm_bytes = value;
@@ -824,6 +841,7 @@ qtx_status qtx_problem_create(qtx_ctx* parent, qtx_ctx** problem) {
   c->heavy_tol = parent->heavy_tol;
   c->use_graph = parent->use_graph;
   c->dm_bytes = parent->dm_bytes;
+  c->sweep_bytes = parent->sweep_bytes;
   c->se_method = parent->se_method;
   c->mode_tol = parent->mode_tol;
   c->stream = parent->stream;
@@ -898,7 +916,7 @@ qtx_status enqueue_batch(qtx_ctx* c, const std::vector<BatchChunk>& chunks, cons
                                    c->dscr.as<double2>(), gdec, c->sig.as<double2>(), c->wf.as<double2>(),
                                    c->sgn.as<double>(), c->iters.as<int>(), c->nheavy.as<int>(), c->stream));
     }
-    const int grid = std::max(1, std::min(k.nitems, c->num_cu * wg));
+    const int grid = sweep_grid(c, k.nitems, M, mixed, qtx::sweep_ws_bytes(k.nmax, M, mixed));
     qtx::SweepArgs a{};
     a.E = c->bE.as<double>() + k.item0;
     a.nE = k.nitems;
@@ -1155,11 +1173,14 @@ qtx_status qtx_solve_batch(qtx_ctx* c, int nprob, qtx_ctx* const* probs, const d
     const size_t MM = (size_t)k.M * k.M;
     const int wg = wgs_per_cu(c, k.M, mixed);
     const size_t gdec = std::max(1, std::min(k.njobs, c->num_cu * wg));
-    const size_t grid = std::max(1, std::min(k.nitems, c->num_cu * wg));
+    const size_t wsb = qtx::sweep_ws_bytes(k.nmax, k.M, mixed);
+    const int sgrid = sweep_grid(c, k.nitems, k.M, mixed, wsb);
+    if (sgrid < 1) return fail(c, QTX_ENOMEM, "sweep_workspace_bytes is below one workgroup's sweep workspace");
+    const size_t grid = (size_t)sgrid;
     sig_b = std::max(sig_b, (size_t)k.nitems * 2 * MM * sizeof(double2));
     per_b = std::max(per_b, (size_t)k.nitems);
     dscr_b = std::max(dscr_b, gdec * qtx::dec_ws_elems(k.M) * sizeof(double2));
-    sws_b = std::max(sws_b, grid * qtx::sweep_ws_bytes(k.nmax, k.M, mixed));
+    sws_b = std::max(sws_b, grid * wsb);
     part_b = std::max(part_b, grid * 4 * 2 * (size_t)k.nmax * (mixed ? 2 : 1) * sizeof(double));
   }
   int maxM = 16;
@@ -1231,6 +1252,8 @@ qtx_status qtx_solve_batch(qtx_ctx* c, int nprob, qtx_ctx* const* probs, const d
   std::memcpy(&eb, &c->dec_tol, sizeof(eb));
   sig.push_back(eb);
   std::memcpy(&eb, &c->dec_rcond, sizeof(eb));
+  sig.push_back(eb);
+  std::memcpy(&eb, &c->sweep_bytes, sizeof(eb));
   sig.push_back(eb);
   sig.push_back(c->dec_maxit);
   for (void* bp : {c->sig.p, c->wf.p, c->sgn.p, c->dscr.p, c->sws.p, c->part.p, c->bprobs.p, c->bE.p, c->bT.p,

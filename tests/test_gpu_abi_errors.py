@@ -98,6 +98,7 @@ def test_solve_argument_validation(gpu_lib, ready):
     ("sigma_cache_bytes", [-1.0, 2e13], 16.0 * (1 << 30)),
     ("use_graph", [2, 0.5], 1),
     ("density_matrix_bytes", [-1.0, 2e13], 64.0 * (1 << 30)),
+    ("sweep_workspace_bytes", [0.0, -1.0, 2e13, np.nan], 160.0 * (1 << 30)),
     ("self_energy_method", [2, -1], 0),
     ("mode_tol", [0.0, 0.5], 1e-8),
     ("energies_per_launch", [0, 2 ** 21, 3.5], 4096),
