@@ -186,13 +186,29 @@ def bench_cfg2(args):
     L_t = torch.empty((nE, 2, dev.N), dtype=torch.float64, device="cuda")
     I_t = torch.empty(nE * _lib.INFO_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
     res = {}
-    for name, prec in (("fp64", _lib.FP64), ("mixed", _lib.MIXED)):
+    runs = (("fp64", _lib.FP64),) if args.cfg2_fp64_only else (("fp64", _lib.FP64), ("mixed", _lib.MIXED))
+    for name, prec in runs:
         # warm up on a slice that already fills the grid (allocates the workspace)
         ctx.solve_device(E_t.data_ptr(), 512, wl.eta, prec, T_t.data_ptr(), L_t.data_ptr(), I_t.data_ptr())
         torch.cuda.synchronize()
         res[name] = time_path(ctx, torch, E_t, T_t, L_t, I_t, wl.eta, prec, 1, 0)
         print(json.dumps({name: {"s": res[name]["s"], "sweep_ms": res[name]["sweep_ms"],
                                  "dec_ms": res[name]["dec_ms"]}}), file=sys.stderr, flush=True)
+    flops = nE * (dev.N + float(np.mean(res["fp64"]["info"]["dec_iters"]))) * (152.0 / 3.0) * dev.m ** 3
+    if args.cfg2_fp64_only:
+        r = res["fp64"]
+        print(json.dumps({
+            "metric": "energy-solves/s (N=400 slabs, m=128, 4096 energies incl. 256 band-edge), FP64 path",
+            "value": nE / r["s"], "unit": "energy-solves/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+            "ms_per_step": 1e3 * r["s"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "cfg2_N400_m128_E4096_fp64", "N": dev.N, "m": dev.m, "energies": nE,
+                       "band_edge_energies": len(edges), "eta": wl.eta},
+            "paths": {"fp64": {"energy_solves_per_s": nE / r["s"], "s_per_grid": r["s"],
+                               "sweep_kernel_ms": r["sweep_ms"], "decimation_kernel_ms": r["dec_ms"],
+                               "whole_solve_frac_of_fp64_peak": flops / r["s"] / 78.6e12}},
+        }))
+        return
     T64, L64, Tm, Lm = res["fp64"]["T"], res["fp64"]["ldos"], res["mixed"]["T"], res["mixed"]["ldos"]
     scale = np.maximum(1.0, np.abs(L64).max(axis=2))
     dT = np.abs(Tm - T64)
@@ -205,7 +221,6 @@ def bench_cfg2(args):
         ora[name] = {"max_dT": float(np.abs(T[idx] - Tref).max()),
                      "max_rel_dn": float((np.abs(L[idx] - Lref).max(axis=2) / sref).max())}
     mi = res["mixed"]["info"]
-    flops = nE * (dev.N + float(np.mean(res["fp64"]["info"]["dec_iters"]))) * (152.0 / 3.0) * dev.m ** 3
     paths = {}
     for name in ("fp64", "mixed"):
         r = res[name]
@@ -554,6 +569,8 @@ def main():
                     help="cfg1: the headline N=200, m=64 grid (default); batch64: the uneven 64-device "
                          "batch; serve: the Poisson request loop")
     ap.add_argument("--serve-seconds", type=float, default=60.0)
+    ap.add_argument("--cfg2-fp64-only", action="store_true",
+                    help="N=400, m=128 workload: time the FP64 path only (no mixed run, no comparison)")
     ap.add_argument("--serve-precision", choices=("fp64", "mixed"), default="fp64")
     args = ap.parse_args()
     if args.workload == "bands":
