@@ -222,8 +222,9 @@ qtx_status qtx_self_energy(qtx_ctx* ctx, const double* E, int nE, double eta,
  *                           of 16 columns, at least one tile per contact);
  *                           0 refines every column;
  *   "workgroups_per_cu"     [1, 4]        2      resident energies per CU for
- *                           blocks up to 64 (blocks above 64 use one);
- *                           setting it discards autotuned values;
+ *                           blocks up to 64 (blocks of 96 and 128 use two,
+ *                           except one for QTX_MIXED at 128); setting it
+ *                           discards autotuned values;
  *   "energies_per_launch"   [1, 2^20]     4096   energies per launch chunk;
  *   "sigma_cache_bytes"     [0, 1e13]     16 GiB qtx_solve_batch keeps the lead
  *                           self-energies, broadening factors and signs of

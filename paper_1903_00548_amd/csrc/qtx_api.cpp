@@ -194,12 +194,15 @@ qtx_status check_ready(qtx_ctx* c) {
 }
 
 // Resident workgroups per CU for block size M: the autotuned value if there
-// is one, else blocks above 64 take a whole CU and smaller ones the
-// configured count (two by default).
+// is one.  Otherwise blocks up to 64 take the configured count (two by
+// default) and larger blocks two, except the mixed sweep at 128: its
+// workspace (about 0.5 GB per workgroup at N = 400) and its register spill
+// make one per CU faster there.
 int wgs_per_cu(const qtx_ctx* c, int M, bool mixed) {
   auto it = c->tuned_wg[mixed].find(M);
   if (it != c->tuned_wg[mixed].end()) return it->second;
-  return M > 64 ? 1 : c->wg_per_cu;
+  if (M > 64) return mixed && M > 96 ? 1 : 2;
+  return c->wg_per_cu;
 }
 
 // Resident workgroups of a sweep launch over `items` energies of block size
@@ -1326,9 +1329,9 @@ qtx_status qtx_autotune(qtx_ctx* c, const double* E, int nE, double eta, qtx_pre
   const int M = c->M, N = c->N;
   int occ_sweep = 0, occ_dec = 0;
   QTX_HIP(c, qtx::max_resident(M, mixed, &occ_sweep, &occ_dec));
-  // mixed sweeps of blocks above 64 keep one workgroup per CU: their
-  // workspace (about 0.5 GB per workgroup at N = 400) bounds the count
-  const int cand = std::max(1, std::min(M > 64 && mixed ? 1 : 4, occ_sweep));
+  // the mixed sweep at 128 keeps one workgroup per CU: its workspace (about
+  // 0.5 GB per workgroup at N = 400) bounds the count
+  const int cand = std::max(1, std::min(M > 96 && mixed ? 1 : 4, occ_sweep));
   QTX_HIP(c, c->wE.ensure((size_t)nE * sizeof(double)));
   QTX_HIP(c, c->wT.ensure((size_t)nE * sizeof(double)));
   QTX_HIP(c, c->wldos.ensure((size_t)nE * 2 * N * sizeof(double)));

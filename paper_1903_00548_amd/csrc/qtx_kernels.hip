@@ -742,8 +742,13 @@ __device__ __forceinline__ double refine(const Prob& P, const SweepArgs& a, cons
 //
 // With a.elist (FP64 sweep only) the launch re-solves the listed energies,
 // keeping the refinement diagnostics in info and marking the fallback.
+//
+// Two workgroups per CU at every block size.  Above 64 this caps the
+// registers at 256 per lane, and the FP64 sweep spills about 100 bytes per
+// lane at M = 128.  A second wave per SIMD issues MFMAs while the first
+// waits on its operands in L2, which more than pays for the spill.
 template <typename R, int M, bool MIX, bool DM>
-__global__ __launch_bounds__(NT, M > 64 ? 1 : 2) void k_sweep(Prob P0, SweepArgs a, BatchDesc b) {
+__global__ __launch_bounds__(NT, 2) void k_sweep(Prob P0, SweepArgs a, BatchDesc b) {
   static_assert(!DM || (!MIX && sizeof(R) == 8), "density-matrix blocks come from the FP64 sweep");
   typedef typename vec2t<R>::type V2;
   constexpr int MT = M / 16, MM = M * M, S = M + 1, LD = 2 * M;

@@ -10,7 +10,7 @@ from paper_1903_00548_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("m,N", [(8, 16), (32, 40), (64, 24)])
+@pytest.mark.parametrize("m,N", [(8, 16), (32, 40), (64, 24), (128, 10)])
 def test_autotune_picks_a_timed_candidate_and_keeps_results(gpu_lib, m, N):
     dev = W.small_random_device(61 + m, N, m, uniform=True, same_leads=True, pot_mode=W.POT_LINEAR_FE)
     E = np.linspace(-1.5, 1.5, 1024)
@@ -20,6 +20,7 @@ def test_autotune_picks_a_timed_candidate_and_keeps_results(gpu_lib, m, N):
     print(f"m={m}: chose {wg} workgroups per CU; ms per candidate {np.round(times, 2).tolist()}")
     assert 1 <= wg <= 4 and times[wg - 1] > 0
     assert times[wg - 1] == min(t for t in times if t > 0)
+    assert times[0] > 0 and times[1] > 0          # every block size runs two workgroups per CU
     T1, L1, _, _ = ctx.solve(E, 1e-6, _lib.FP64)
     assert np.array_equal(T0, T1) and np.array_equal(L0, L1)
 
