@@ -257,8 +257,12 @@ qtx_status qtx_self_energy(qtx_ctx* ctx, const double* E, int nE, double eta,
  *                           sweep workspaces of the resident workgroups
  *                           ((N + 1) 2 M^2 complex per workgroup in FP64):
  *                           fewer workgroups run when they do not all fit,
- *                           with the same results; a call whose single
- *                           workgroup would not fit returns QTX_ENOMEM;
+ *                           with the same results.  When the device runs
+ *                           out of memory for them, the context halves its
+ *                           budget until they fit and keeps the lowered
+ *                           value until this option is set again.  A call
+ *                           whose single workgroup does not fit returns
+ *                           QTX_ENOMEM;
  *   "density_matrix_bytes"  [0, 1e13]     64 GiB device memory for the
  *                           per-workgroup accumulators of qtx_density_matrix
  *                           (fewer workgroups run when they do not all fit);

@@ -77,6 +77,7 @@ struct qtx_ctx {
   DevBuf dmw, rho, dmout;                      // density-matrix blocks: weights, accumulators, sums
   double dm_bytes = 64.0 * (1ull << 30);       // cap on the per-workgroup accumulators
   double sweep_bytes = 160.0 * (1ull << 30);   // cap on the resident workgroups' sweep workspaces
+  double sweep_eff = -1.0;                      // lower cap after the device ran out of memory (< 0: none)
   int se_method = 0;                           // 0 decimation, 1 complex band structure (mode space)
   double mode_tol = 1e-8;                      // |lambda| tolerance of travelling modes
   DevBuf mscr, mjst;                           // complex-band-structure workspace, per-job status
@@ -210,9 +211,25 @@ int wgs_per_cu(const qtx_ctx* c, int M, bool mixed) {
 // fit in sweep_workspace_bytes; 0 if not even one fits.  Every energy is
 // solved by one workgroup, so the grid does not change the results.
 int sweep_grid(const qtx_ctx* c, int items, int M, bool mixed, size_t wsb) {
-  const int fit = (int)std::min<double>(1 << 20, std::floor(c->sweep_bytes / (double)wsb));
+  const double budget = c->sweep_eff >= 0.0 ? std::min(c->sweep_eff, c->sweep_bytes) : c->sweep_bytes;
+  const int fit = (int)std::min<double>(1 << 20, std::floor(budget / (double)wsb));
   if (fit < 1) return 0;
   return std::max(1, std::min({items, c->num_cu * wgs_per_cu(c, M, mixed), fit}));
+}
+
+// Allocates the sweep workspace (bytes).  When the device is out of memory
+// (other buffers of the call, the self-energy cache or other contexts hold
+// it), the context's budget drops to half of what was asked and *retry is
+// set: the caller recomputes its grids, each at most half as large, and
+// tries again.  The lowered budget stays until sweep_workspace_bytes is set.
+hipError_t alloc_sweep_ws(qtx_ctx* c, size_t bytes, bool* retry) {
+  *retry = false;
+  const hipError_t e = c->sws.ensure(bytes);
+  if (e != hipErrorOutOfMemory) return e;
+  (void)hipGetLastError();
+  c->sweep_eff = 0.5 * (double)bytes;
+  *retry = true;
+  return hipSuccess;
 }
 
 qtx::DecOpts dec_opts(const qtx_ctx* c) { return qtx::DecOpts{c->dec_tol, c->dec_rcond, c->dec_maxit, c->heavy_tol}; }
@@ -307,9 +324,12 @@ qtx_status solve_device_core(qtx_ctx* c, const double* E_dev, int nE, double eta
     s = stage_decimate(c, E_dev + e0, ne, eta, mixed);
     if (s != QTX_OK) return s;
     const size_t wsb = qtx::sweep_ws_bytes(N, M, mixed);
-    const int grid = sweep_grid(c, ne, M, mixed, wsb);
-    if (grid < 1) return fail(c, QTX_ENOMEM, "sweep_workspace_bytes is below one workgroup's sweep workspace");
-    QTX_HIP(c, c->sws.ensure((size_t)grid * wsb));
+    int grid = 0;
+    for (bool retry = true; retry;) {
+      grid = sweep_grid(c, ne, M, mixed, wsb);
+      if (grid < 1) return fail(c, QTX_ENOMEM, "no sweep workspace of one workgroup fits (sweep_workspace_bytes or device memory)");
+      QTX_HIP(c, alloc_sweep_ws(c, (size_t)grid * wsb, &retry));
+    }
     QTX_HIP(c, c->part.ensure((size_t)grid * 4 * 2 * N * (mixed ? 2 : 1) * sizeof(double)));
     if (mixed) {
       QTX_HIP(c, c->redo.ensure((size_t)ne * sizeof(int)));
@@ -384,11 +404,14 @@ qtx_status density_matrix_core(qtx_ctx* c, const double* E_dev, const double* wL
   // in the first launch (grid <= the first launch's energies)
   const int first = std::min(c->chunk, nE);
   const size_t wsb = qtx::sweep_ws_bytes(N, M, false, true);
-  const int sgrid = sweep_grid(c, first, M, false, wsb);
-  if (sgrid < 1) return fail(c, QTX_ENOMEM, "sweep_workspace_bytes is below one workgroup's sweep workspace");
-  const int grid = std::min(sgrid, cap);
+  int grid = 0;
+  for (bool retry = true; retry;) {
+    const int sgrid = sweep_grid(c, first, M, false, wsb);
+    if (sgrid < 1) return fail(c, QTX_ENOMEM, "no sweep workspace of one workgroup fits (sweep_workspace_bytes or device memory)");
+    grid = std::min(sgrid, cap);
+    QTX_HIP(c, alloc_sweep_ws(c, (size_t)grid * wsb, &retry));
+  }
   QTX_HIP(c, c->rho.ensure((size_t)grid * per_wg));
-  QTX_HIP(c, c->sws.ensure((size_t)grid * wsb));
   QTX_HIP(c, c->part.ensure((size_t)grid * 4 * 2 * N * sizeof(double)));
   for (int e0 = 0; e0 < nE; e0 += c->chunk) {
     const int ne = std::min(c->chunk, nE - e0);
@@ -808,6 +831,7 @@ qtx_status qtx_set_option(qtx_ctx* c, const char* name, double value) {
   } else if (n == "sweep_workspace_bytes") {
     if (!(value > 0.0 && value <= 1e13)) return fail(c, QTX_EINVAL, "sweep_workspace_bytes must be in (0, 1e13]");
     c->sweep_bytes = value;
+    c->sweep_eff = -1.0;
   } else if (n == "density_matrix_bytes") {
     if (!(value >= 0.0 && value <= 1e13)) return fail(c, QTX_EINVAL, "density_matrix_bytes must be in [0, 1e13]");
     c->dm_bytes = value;
@@ -1176,15 +1200,9 @@ qtx_status qtx_solve_batch(qtx_ctx* c, int nprob, qtx_ctx* const* probs, const d
     const size_t MM = (size_t)k.M * k.M;
     const int wg = wgs_per_cu(c, k.M, mixed);
     const size_t gdec = std::max(1, std::min(k.njobs, c->num_cu * wg));
-    const size_t wsb = qtx::sweep_ws_bytes(k.nmax, k.M, mixed);
-    const int sgrid = sweep_grid(c, k.nitems, k.M, mixed, wsb);
-    if (sgrid < 1) return fail(c, QTX_ENOMEM, "sweep_workspace_bytes is below one workgroup's sweep workspace");
-    const size_t grid = (size_t)sgrid;
     sig_b = std::max(sig_b, (size_t)k.nitems * 2 * MM * sizeof(double2));
     per_b = std::max(per_b, (size_t)k.nitems);
     dscr_b = std::max(dscr_b, gdec * qtx::dec_ws_elems(k.M) * sizeof(double2));
-    sws_b = std::max(sws_b, grid * wsb);
-    part_b = std::max(part_b, grid * 4 * 2 * (size_t)k.nmax * (mixed ? 2 : 1) * sizeof(double));
   }
   int maxM = 16;
   for (const BatchChunk& k : chunks) maxM = std::max(maxM, k.M);
@@ -1194,7 +1212,17 @@ qtx_status qtx_solve_batch(qtx_ctx* c, int nprob, qtx_ctx* const* probs, const d
   QTX_HIP(c, c->iters.ensure(per_b * 2 * sizeof(int)));
   QTX_HIP(c, c->nheavy.ensure(per_b * 2 * sizeof(int)));
   QTX_HIP(c, c->dscr.ensure(dscr_b));
-  QTX_HIP(c, c->sws.ensure(sws_b));
+  for (bool retry = true; retry;) {
+    sws_b = part_b = 0;
+    for (const BatchChunk& k : chunks) {
+      const size_t wsb = qtx::sweep_ws_bytes(k.nmax, k.M, mixed);
+      const int sgrid = sweep_grid(c, k.nitems, k.M, mixed, wsb);
+      if (sgrid < 1) return fail(c, QTX_ENOMEM, "no sweep workspace of one workgroup fits (sweep_workspace_bytes or device memory)");
+      sws_b = std::max(sws_b, (size_t)sgrid * wsb);
+      part_b = std::max(part_b, (size_t)sgrid * 4 * 2 * (size_t)k.nmax * (mixed ? 2 : 1) * sizeof(double));
+    }
+    QTX_HIP(c, alloc_sweep_ws(c, sws_b, &retry));
+  }
   QTX_HIP(c, c->part.ensure(part_b));
   QTX_HIP(c, c->redo.ensure(per_b * sizeof(int)));
   QTX_HIP(c, c->elist.ensure(per_b * sizeof(int)));
@@ -1257,6 +1285,8 @@ qtx_status qtx_solve_batch(qtx_ctx* c, int nprob, qtx_ctx* const* probs, const d
   std::memcpy(&eb, &c->dec_rcond, sizeof(eb));
   sig.push_back(eb);
   std::memcpy(&eb, &c->sweep_bytes, sizeof(eb));
+  sig.push_back(eb);
+  std::memcpy(&eb, &c->sweep_eff, sizeof(eb));
   sig.push_back(eb);
   sig.push_back(c->dec_maxit);
   for (void* bp : {c->sig.p, c->wf.p, c->sgn.p, c->dscr.p, c->sws.p, c->part.p, c->bprobs.p, c->bE.p, c->bT.p,

@@ -76,3 +76,34 @@ def test_capped_batch_same_results(gpu_lib):
         Ts, Ls, _ = _lib.solve_batch(ctx, probs, grids, ETA)
         for k in range(len(devs)):
             assert np.array_equal(Ts[k], Tr[k]) and np.array_equal(Ls[k], Lr[k]), k
+
+
+def test_out_of_memory_lowers_the_budget(gpu_lib):
+    """With the budget at its maximum, the full grid of a long m = 128 device
+    asks for more workspace than the device has. The first allocation runs
+    out of memory, and the context halves its budget until the workspace
+    fits. The results equal those of a context with an explicit smaller
+    budget bit for bit. That context is solved first and closed, so the two
+    workspaces never coexist. The lowered budget stays for the next call."""
+    import torch
+    N, m, nE = 1400, 128, 512
+    lead = W.random_lead(np.random.default_rng(71), m)
+    dev = W.Device(N=N, m=m, lead_L=lead, lead_R=lead, V=np.zeros(N), pot_mode=W.POT_DIAG)
+    E = np.linspace(-1.2, 1.2, nE)
+    ws = _ws_bytes(N, m)
+    total = torch.cuda.get_device_properties(0).total_memory
+    assert min(nE, 512) * ws > total                  # the full grid cannot be allocated
+
+    ref = _lib.context_for(dev, 0)
+    ref.set_option("sweep_workspace_bytes", 128.5 * ws)   # 128 workgroups
+    Tr, Lr = ref.solve(E, ETA, _lib.FP64)[:2]
+    ref.close()
+    torch.cuda.synchronize()
+
+    ctx = _lib.context_for(dev, 0)
+    ctx.set_option("sweep_workspace_bytes", 1e13)
+    T, L = ctx.solve(E, ETA, _lib.FP64)[:2]
+    assert np.array_equal(T, Tr) and np.array_equal(L, Lr)
+    T2 = ctx.solve(E[:64], ETA, _lib.FP64)[0]           # the lowered budget is kept
+    assert np.array_equal(T2, Tr[:64])
+    ctx.close()
