@@ -222,8 +222,8 @@ qtx_status qtx_self_energy(qtx_ctx* ctx, const double* E, int nE, double eta,
  *                           of 16 columns, at least one tile per contact);
  *                           0 refines every column;
  *   "workgroups_per_cu"     [1, 4]        2      resident energies per CU for
- *                           blocks up to 64 (blocks of 96 and 128 use two,
- *                           except one for QTX_MIXED at 128); setting it
+ *                           blocks up to 64 (blocks of 96 and 128 use two
+ *                           with QTX_FP64, one with QTX_MIXED); setting it
  *                           discards autotuned values;
  *   "energies_per_launch"   [1, 2^20]     4096   energies per launch chunk;
  *   "sigma_cache_bytes"     [0, 1e13]     16 GiB qtx_solve_batch keeps the lead
@@ -311,7 +311,9 @@ qtx_status qtx_solve_batch(qtx_ctx* ctx, int nprob, qtx_ctx* const* probs,
  * context (and in its parent, for batched solves) and used by later
  * solves.  *wg_out (or NULL) receives it; times_ms[4] (or NULL) the
  * measured milliseconds per candidate (0 where a count was not possible).
- * Takes about twice the solve time of the sample per candidate. */
+ * Takes about twice the solve time of the sample per candidate.  The sweep
+ * and decimation workspaces the timing allocated are released on return;
+ * the next solve on the context allocates what it needs. */
 qtx_status qtx_autotune(qtx_ctx* ctx, const double* E, int nE, double eta, qtx_precision prec,
                         int* wg_out, double* times_ms);
 

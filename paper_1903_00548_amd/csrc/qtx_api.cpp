@@ -196,13 +196,13 @@ qtx_status check_ready(qtx_ctx* c) {
 
 // Resident workgroups per CU for block size M: the autotuned value if there
 // is one.  Otherwise blocks up to 64 take the configured count (two by
-// default) and larger blocks two, except the mixed sweep at 128: its
-// workspace (about 0.5 GB per workgroup at N = 400) and its register spill
-// make one per CU faster there.
+// default); larger blocks take two in FP64 and one in the mixed path, whose
+// workspace (0.3-0.5 GB per workgroup at N = 400) would otherwise crowd the
+// self-energy cache and the batch buffers out of device memory.
 int wgs_per_cu(const qtx_ctx* c, int M, bool mixed) {
   auto it = c->tuned_wg[mixed].find(M);
   if (it != c->tuned_wg[mixed].end()) return it->second;
-  if (M > 64) return mixed && M > 96 ? 1 : 2;
+  if (M > 64) return mixed ? 1 : 2;
   return c->wg_per_cu;
 }
 
@@ -1359,9 +1359,9 @@ qtx_status qtx_autotune(qtx_ctx* c, const double* E, int nE, double eta, qtx_pre
   const int M = c->M, N = c->N;
   int occ_sweep = 0, occ_dec = 0;
   QTX_HIP(c, qtx::max_resident(M, mixed, &occ_sweep, &occ_dec));
-  // the mixed sweep at 128 keeps one workgroup per CU: its workspace (about
-  // 0.5 GB per workgroup at N = 400) bounds the count
-  const int cand = std::max(1, std::min(M > 96 && mixed ? 1 : 4, occ_sweep));
+  // mixed sweeps above 64 keep one workgroup per CU: their workspace (0.3-0.5
+  // GB per workgroup at N = 400) bounds the count
+  const int cand = std::max(1, std::min(M > 64 && mixed ? 1 : 4, occ_sweep));
   QTX_HIP(c, c->wE.ensure((size_t)nE * sizeof(double)));
   QTX_HIP(c, c->wT.ensure((size_t)nE * sizeof(double)));
   QTX_HIP(c, c->wldos.ensure((size_t)nE * 2 * N * sizeof(double)));
@@ -1402,6 +1402,12 @@ qtx_status qtx_autotune(qtx_ctx* c, const double* E, int nE, double eta, qtx_pre
   c->timing = timing;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  // the timed solves sized the workspaces for the largest candidate; release
+  // them (a later solve on this context allocates what it needs), so that a
+  // problem context tuned before a batch holds no workspace the batch needs
+  (void)hipStreamSynchronize(c->stream);
+  c->sws.release();
+  c->dscr.release();
   if (st != QTX_OK) {
     c->tuned_wg[mixed].erase(M);
     return st;
