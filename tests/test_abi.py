@@ -83,3 +83,16 @@ def test_charge_helper_matches_its_definition(lib):
     ref = (w * oint.fermi(E, muL, kT)) @ ldos[:, 0, :] + (w * oint.fermi(E, muR, kT)) @ ldos[:, 1, :]
     assert np.abs(out - ref).max() < 1e-13
     assert f(p(ldos), p(w), nE, N, p(E), muL, muR, 0.0, p(out)) == _lib.EINVAL       # kT must be > 0
+
+
+def test_every_option_is_documented_in_the_header():
+    """Every name qtx_set_option accepts appears in the header's option
+    table (quoted), and every quoted name in that table is accepted."""
+    src = open(os.path.join(ROOT, "paper_1903_00548_amd", "csrc", "qtx_api.cpp")).read()
+    hdr = open(os.path.join(ROOT, "include", "qtx.h")).read()
+    accepted = set(re.findall(r'n == "([a-z_]+)"', src))
+    table = hdr[hdr.index("Tuning parameters of a context"):]
+    table = table[:table.index("qtx_status qtx_set_option")]
+    documented = set(re.findall(r'\*\s+"([a-z_]+)"', table))
+    assert accepted, "no option names found in qtx_api.cpp"
+    assert accepted == documented, (sorted(accepted - documented), sorted(documented - accepted))
