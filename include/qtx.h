@@ -145,7 +145,13 @@ qtx_status qtx_solve(qtx_ctx* ctx, const double* E, int nE, double eta,
  * same method has sized the context's workspaces.  It then issues only
  * kernel launches; a replay reads the energies at E_dev and recomputes
  * everything.  A context with several captured graphs shares one workspace
- * among them, so their replays must not overlap. */
+ * among them, so their replays must not overlap.  A captured graph holds
+ * the workspace addresses of the moment of capture: any later call on the
+ * context that grows or releases a workspace (a larger energy grid or
+ * slab count, another precision, qtx_autotune, qtx_density_matrix, the
+ * options sweep_workspace_bytes or energies_per_launch) leaves the graph
+ * pointing at freed memory, and it must be captured again before its next
+ * replay. */
 qtx_status qtx_solve_device(qtx_ctx* ctx, const double* E_dev, int nE, double eta,
                             qtx_precision prec, double* T_dev, double* ldos_dev,
                             qtx_info* info_dev);

@@ -1289,18 +1289,23 @@ qtx_status qtx_solve_batch(qtx_ctx* c, int nprob, qtx_ctx* const* probs, const d
   std::memcpy(&eb, &c->sweep_eff, sizeof(eb));
   sig.push_back(eb);
   sig.push_back(c->dec_maxit);
-  for (void* bp : {c->sig.p, c->wf.p, c->sgn.p, c->dscr.p, c->sws.p, c->part.p, c->bprobs.p, c->bE.p, c->bT.p,
-                   c->bldos.p, c->binfo.p})
+  // every buffer the captured launches read or write (a buffer that grew or
+  // was released since the capture has moved, and the graph must not run)
+  for (void* bp : {c->sig.p, c->wf.p, c->sgn.p, c->iters.p, c->nheavy.p, c->dscr.p, c->sws.p, c->part.p,
+                   c->redo.p, c->elist.p, c->ecount.p, c->bprobs.p, c->bitem_prob.p, c->bitem_ldos.p,
+                   c->bjob_item.p, c->bjob_side.p, c->bE.p, c->bT.p, c->bldos.p, c->binfo.p, c->bslot.p,
+                   c->bjobE.p, c->bjobLead.p})
     sig.push_back((long long)(uintptr_t)bp);
   for (const BatchChunk& k : chunks)
     for (int v : {k.M, k.nmax, k.item0, k.nitems, k.job0, k.njobs}) sig.push_back(v);
   sig.push_back(cached);
   for (const DecGroup& g : groups)
     for (int v : {g.M, g.job0, g.njobs}) sig.push_back(v);
-  for (auto& kv : c->sigcache) sig.push_back((long long)(uintptr_t)kv.second.sig.p);
-  sig.push_back((long long)(uintptr_t)c->bslot.p);
-  sig.push_back((long long)(uintptr_t)c->bjobE.p);
-  sig.push_back((long long)(uintptr_t)c->bjob_item.p);
+  for (auto& kv : c->sigcache) {
+    sig.push_back(kv.first);
+    for (void* bp : {kv.second.sig.p, kv.second.wf.p, kv.second.sgn.p, kv.second.iters.p, kv.second.nheavy.p})
+      sig.push_back((long long)(uintptr_t)bp);
+  }
   if (!c->use_graph) {
     drop_graph(c);
     qtx_status s = enqueue_batch(c, chunks, groups, eta, mixed, cached);

@@ -209,3 +209,32 @@ def test_sigma_cache_emptied_by_decimation_options(gpu_lib):
         hits, misses = h, m_
         Tr, Lr, _, _ = ref.solve(E, ETA, _lib.FP64)
         assert np.array_equal(Ts[0], Tr) and np.array_equal(Ls[0], Lr), name
+
+
+@pytest.mark.parametrize("prec", [_lib.FP64, _lib.MIXED], ids=["fp64", "mixed"])
+@pytest.mark.parametrize("cache", [True, False], ids=["sigma-cache", "no-cache"])
+def test_batch_replay_after_a_larger_single_solve(gpu_lib, prec, cache):
+    """A batch is captured in a graph; a single solve on the batch context
+    (its own small-block problem, more energies than the batch has items)
+    then grows the per-energy buffers the graph also uses (doublings,
+    refined-column counts, re-solve lists) without moving the larger
+    self-energy buffers; the same batch shape again must not replay into
+    the freed buffers, and it reproduces the first batch bit for bit."""
+    devs = _devices()
+    ctx = _lib.Context(0)
+    if not cache:
+        ctx.set_option("sigma_cache_bytes", 0)
+    probs = [_lib.fill(ctx.problem(), d) for d in devs]
+    for p, d in zip(probs, devs):
+        p.N, p.m = d.N, d.m
+    grids = _grids()
+    grids[5] = np.linspace(-1.9, 1.9, 40)          # the m = 128 problem: the largest self-energy buffer
+    own = W.small_random_device(41, 5, 8, uniform=True, same_leads=True, pot_mode=W.POT_DIAG)
+    _lib.fill(ctx, own)
+    T1, L1, _ = _lib.solve_batch(ctx, probs, grids, ETA, prec)
+    Ts, Ls, _, _ = ctx.solve(np.linspace(-2.0, 2.0, 1000), ETA, prec)
+    assert np.all(np.isfinite(Ts))
+    T2, L2, _ = _lib.solve_batch(ctx, probs, grids, ETA, prec)
+    for p in range(len(devs)):
+        assert np.array_equal(T1[p], T2[p]) and np.array_equal(L1[p], L2[p]), p
+    ctx.close()
