@@ -156,6 +156,29 @@ qtx_status qtx_solve_device(qtx_ctx* ctx, const double* E_dev, int nE, double et
                             qtx_precision prec, double* T_dev, double* ldos_dev,
                             qtx_info* info_dev);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * solve as qtx_solve_device, same arguments, same results bit for bit, but
+ * it allocates nothing.  Every buffer of the solve (self-energies,
+ * broadening factors, decimation and sweep workspaces, partial sums,
+ * re-solve lists) is carved from a fixed device array of 512 MiB
+ * (QTX_NOALLOC_SCRATCH_BYTES) that the library holds on each GPU it runs
+ * on until the process ends.  The energies run in chunks with as many
+ * resident workgroups as that array holds, so large problems run with
+ * fewer workgroups than qtx_solve_device (slower, same results).  Returns
+ * QTX_ENOMEM with a message when not even one energy of the problem fits
+ * (at N = 200, m = 64 one energy needs about 27 MB in FP64).  Only the
+ * decimation self-energies (self_energy_method 0); no kernel timing.
+ * Every call on a GPU shares that GPU's array, which keeps the last call's
+ * contents: calls that overlap on one GPU (two streams, two contexts, two
+ * threads) race and must be serialised by the caller.  Nothing in the
+ * array needs to start at zero.  Asynchronous on the context stream like
+ * qtx_solve_device. */
+#define QTX_NOALLOC_SCRATCH_BYTES (512ull << 20)
+qtx_status qtx_solve_device_noalloc(qtx_ctx* ctx, const double* E_dev, int nE, double eta,
+                                    qtx_precision prec, double* T_dev, double* ldos_dev,
+                                    qtx_info* info_dev);
+
 /* Nearest-neighbour blocks of the density matrix in the slab basis (the
  * Bloch-basis density matrix of Sec. "Density", eq. density_matrices, whose
  * on-slab and neighbouring-slab blocks suffice for the density,

@@ -50,6 +50,8 @@ _SIGS = {
     "qtx_set_potential": (c_int, [c_void_p, c_void_p, c_int]),
     "qtx_solve": (c_int, [c_void_p, c_void_p, c_int, c_double, c_int, c_void_p, c_void_p, c_void_p]),
     "qtx_solve_device": (c_int, [c_void_p, c_void_p, c_int, c_double, c_int, c_void_p, c_void_p, c_void_p]),
+    "qtx_solve_device_noalloc": (c_int, [c_void_p, c_void_p, c_int, c_double, c_int, c_void_p, c_void_p,
+                                         c_void_p]),
     "qtx_self_energy": (c_int, [c_void_p, c_void_p, c_int, c_double, c_void_p, c_void_p, c_void_p, c_void_p]),
     "qtx_problem_create": (c_int, [c_void_p, POINTER(c_void_p)]),
     "qtx_kernel_times": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p]),
@@ -178,6 +180,14 @@ class Context:
         st = self.lib.qtx_solve_device(self.h, c_void_p(E_ptr), int(nE), float(eta), int(precision),
                                        c_void_p(T_ptr), c_void_p(ldos_ptr or None),
                                        c_void_p(info_ptr or None))
+        return self._check(st, allow_notconv=True)
+
+    def solve_device_noalloc(self, E_ptr, nE, eta, precision, T_ptr, ldos_ptr=0, info_ptr=0):
+        """qtx_solve_device_noalloc: as solve_device, with every buffer of
+        the solve taken from the library's fixed device scratch."""
+        st = self.lib.qtx_solve_device_noalloc(self.h, c_void_p(E_ptr), int(nE), float(eta), int(precision),
+                                               c_void_p(T_ptr), c_void_p(ldos_ptr or None),
+                                               c_void_p(info_ptr or None))
         return self._check(st, allow_notconv=True)
 
     def density_matrix(self, E, wL, wR, eta, want_ldos=False):

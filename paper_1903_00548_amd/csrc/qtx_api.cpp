@@ -18,6 +18,8 @@
 #include "qtx.h"
 #include "qtx_internal.h"
 
+static_assert(QTX_NOALLOC_SCRATCH_BYTES == qtx::kNoAllocScratchBytes, "scratch size in qtx.h and the library agree");
+
 namespace {
 
 // Device buffer that grows on demand and is freed with its owner (the
@@ -266,110 +268,170 @@ qtx_status check_method(qtx_ctx* c, double eta, bool mixed) {
   return QTX_OK;
 }
 
+// Device buffers of one launch chunk of a solve: the decimation outputs per
+// energy, the decimation and sweep workspaces of the resident workgroups,
+// and for the mixed path the re-solve list.  Filled from the context's
+// growable buffers, or carved from the fixed no-allocation scratch.
+struct SolveBufs {
+  double2* sig = nullptr;
+  double2* wf = nullptr;
+  double* sgn = nullptr;
+  int* iters = nullptr;
+  int* nheavy = nullptr;
+  double2* dscr = nullptr;      // decimation workspace, gdec workgroups
+  int gdec = 0;
+  char* sws = nullptr;          // sweep workspace, grid workgroups of wsb bytes
+  size_t wsb = 0;
+  int grid = 0;
+  double* part = nullptr;
+  int* redo = nullptr;          // mixed only
+  int* elist = nullptr;
+  int* ecount = nullptr;
+};
+
+// Decimation workgroups for nE energies (sides lead iterations each).
+int dec_grid(const qtx_ctx* c, int nE, int sides, bool mixed) {
+  return std::max(1, std::min(nE * sides, c->num_cu * wgs_per_cu(c, c->M, mixed)));
+}
+
 // lead self-energies, injection factors and signs for energies E_dev[0..nE)
-// into ctx->sig / wf / sgn / iters / nheavy: by decimation, or from the
-// complex band structure of the leads (option self_energy_method)
-qtx_status stage_decimate(qtx_ctx* c, const double* E_dev, int nE, double eta, bool mixed) {
+// into b.sig / wf / sgn / iters / nheavy: by decimation, or from the
+// complex band structure of the leads (option self_energy_method; its
+// workspace is the context's own)
+qtx_status stage_decimate(qtx_ctx* c, const double* E_dev, int nE, double eta, bool mixed, const SolveBufs& b) {
   const int M = c->M;
-  const size_t MM = (size_t)M * M;
   const int sides = leads_identical(c) ? 1 : 2;
   if (c->se_method == 1) {
     qtx_status s = check_method(c, eta, mixed);
     if (s != QTX_OK) return s;
     const int jb = qtx::modes_batch_jobs(M, nE * sides);
-    QTX_HIP(c, c->sig.ensure((size_t)nE * 2 * MM * sizeof(double2)));
-    QTX_HIP(c, c->wf.ensure((size_t)nE * 2 * MM * sizeof(double2)));
-    QTX_HIP(c, c->sgn.ensure((size_t)nE * 2 * M * sizeof(double)));
-    QTX_HIP(c, c->iters.ensure((size_t)nE * 2 * sizeof(int)));
-    QTX_HIP(c, c->nheavy.ensure((size_t)nE * 2 * sizeof(int)));
     QTX_HIP(c, c->mscr.ensure((size_t)jb * qtx::modes_ws_elems(M) * sizeof(double2)));
     QTX_HIP(c, c->mjst.ensure((size_t)jb * sizeof(int)));
     QTX_HIP(c, record(c, c->ev_dec, c->n_dec));
     QTX_HIP(c, qtx::run_modes(M, make_prob(c), E_dev, nE, eta, sides, c->mode_tol, c->m, c->num_cu,
-                              c->mscr.as<double2>(), c->mjst.as<int>(), c->sig.as<double2>(), c->wf.as<double2>(),
-                              c->sgn.as<double>(), c->iters.as<int>(), c->nheavy.as<int>(), c->stream));
+                              c->mscr.as<double2>(), c->mjst.as<int>(), b.sig, b.wf, b.sgn, b.iters, b.nheavy,
+                              c->stream));
     QTX_HIP(c, record(c, c->ev_dec, c->n_dec));
     return QTX_OK;
   }
-  const int grid = std::max(1, std::min(nE * sides, c->num_cu * wgs_per_cu(c, M, mixed)));
+  qtx::Prob P = make_prob(c);
+  QTX_HIP(c, record(c, c->ev_dec, c->n_dec));
+  QTX_HIP(c, qtx::run_decimate(M, P, qtx::BatchDesc{}, E_dev, nE, eta, sides, dec_opts(c), b.dscr, b.gdec, b.sig,
+                               b.wf, b.sgn, b.iters, b.nheavy, c->stream));
+  QTX_HIP(c, record(c, c->ev_dec, c->n_dec));
+  return QTX_OK;
+}
+
+// Per-energy decimation outputs of the context for nE energies.
+qtx_status ensure_dec_outputs(qtx_ctx* c, int nE, SolveBufs& b) {
+  const int M = c->M;
+  const size_t MM = (size_t)M * M;
   QTX_HIP(c, c->sig.ensure((size_t)nE * 2 * MM * sizeof(double2)));
   QTX_HIP(c, c->wf.ensure((size_t)nE * 2 * MM * sizeof(double2)));
   QTX_HIP(c, c->sgn.ensure((size_t)nE * 2 * M * sizeof(double)));
   QTX_HIP(c, c->iters.ensure((size_t)nE * 2 * sizeof(int)));
   QTX_HIP(c, c->nheavy.ensure((size_t)nE * 2 * sizeof(int)));
-  QTX_HIP(c, c->dscr.ensure((size_t)grid * qtx::dec_ws_elems(M) * sizeof(double2)));
-  qtx::Prob P = make_prob(c);
-  QTX_HIP(c, record(c, c->ev_dec, c->n_dec));
-  QTX_HIP(c, qtx::run_decimate(M, P, qtx::BatchDesc{}, E_dev, nE, eta, sides, dec_opts(c), c->dscr.as<double2>(),
-                               grid, c->sig.as<double2>(), c->wf.as<double2>(), c->sgn.as<double>(),
-                               c->iters.as<int>(), c->nheavy.as<int>(), c->stream));
-  QTX_HIP(c, record(c, c->ev_dec, c->n_dec));
+  b.sig = c->sig.as<double2>();
+  b.wf = c->wf.as<double2>();
+  b.sgn = c->sgn.as<double>();
+  b.iters = c->iters.as<int>();
+  b.nheavy = c->nheavy.as<int>();
   return QTX_OK;
 }
 
-qtx_status solve_device_core(qtx_ctx* c, const double* E_dev, int nE, double eta, qtx_precision prec,
-                             double* T_dev, double* ldos_dev, qtx_info* info_dev) {
+// One launch chunk of a solve on the context stream: self-energies, then
+// the sweep (mixed: the single-precision sweep with refinement, the list of
+// unconverged energies and their FP64 re-solve), all in the buffers b.
+qtx_status enqueue_chunk(qtx_ctx* c, const double* E_dev, int ne, double eta, bool mixed, double* T_dev,
+                         double* ldos_dev, qtx_info* info_dev, const SolveBufs& b) {
+  qtx_status s = stage_decimate(c, E_dev, ne, eta, mixed, b);
+  if (s != QTX_OK) return s;
+  qtx::Prob P = make_prob(c);
+  qtx::SweepArgs a{};
+  a.E = E_dev;
+  a.nE = ne;
+  a.eta = eta;
+  a.sig = b.sig;
+  a.wf = b.wf;
+  a.sgn = b.sgn;
+  a.iters = b.iters;
+  a.nheavy = b.nheavy;
+  a.ws = b.sws;
+  a.ws_bytes = b.wsb;
+  a.part = b.part;
+  a.nmax = c->N;
+  a.T = T_dev;
+  a.ldos = ldos_dev;
+  a.info = info_dev;
+  a.elist = nullptr;
+  a.ecount = nullptr;
+  a.redo = mixed ? b.redo : nullptr;
+  a.rtol = c->refine_tol;
+  a.maxstep = c->refine_max;
+  QTX_HIP(c, record(c, c->ev_sw, c->n_sw));
+  QTX_HIP(c, qtx::run_sweep(c->M, mixed, P, a, qtx::BatchDesc{}, b.grid, c->stream));
+  if (mixed) {
+    // energies whose refinement did not converge: FP64 sweep on the list
+    QTX_HIP(c, qtx::run_compact(b.redo, ne, b.elist, b.ecount, c->stream));
+    qtx::SweepArgs f = a;
+    f.elist = b.elist;
+    f.ecount = b.ecount;
+    f.redo = nullptr;
+    QTX_HIP(c, qtx::run_sweep(c->M, false, P, f, qtx::BatchDesc{}, b.grid, c->stream));
+  }
+  QTX_HIP(c, record(c, c->ev_sw, c->n_sw));
+  return QTX_OK;
+}
+
+qtx_status check_solve_args(qtx_ctx* c, const double* E_dev, int nE, double eta, qtx_precision prec,
+                            double* T_dev) {
   qtx_status s = check_ready(c);
   if (s != QTX_OK) return s;
   if (nE < 0 || !(eta >= 0.0)) return fail(c, QTX_EINVAL, "nE must be >= 0 and eta >= 0");
   if (nE == 0) return QTX_OK;
   if (!E_dev || !T_dev) return fail(c, QTX_EINVAL, "E and T must not be NULL");
   if (prec != QTX_FP64 && prec != QTX_MIXED) return fail(c, QTX_EINVAL, "precision must be QTX_FP64 or QTX_MIXED");
+  return check_method(c, eta, prec == QTX_MIXED);
+}
+
+qtx_status solve_device_core(qtx_ctx* c, const double* E_dev, int nE, double eta, qtx_precision prec,
+                             double* T_dev, double* ldos_dev, qtx_info* info_dev) {
+  qtx_status s = check_solve_args(c, E_dev, nE, eta, prec, T_dev);
+  if (s != QTX_OK || nE == 0) return s;
   const bool mixed = (prec == QTX_MIXED);
-  s = check_method(c, eta, mixed);
-  if (s != QTX_OK) return s;
   const int M = c->M, N = c->N;
+  const int sides = leads_identical(c) ? 1 : 2;
   for (int e0 = 0; e0 < nE; e0 += c->chunk) {
     const int ne = std::min(c->chunk, nE - e0);
-    s = stage_decimate(c, E_dev + e0, ne, eta, mixed);
+    SolveBufs b;
+    s = ensure_dec_outputs(c, ne, b);
     if (s != QTX_OK) return s;
-    const size_t wsb = qtx::sweep_ws_bytes(N, M, mixed);
-    int grid = 0;
-    for (bool retry = true; retry;) {
-      grid = sweep_grid(c, ne, M, mixed, wsb);
-      if (grid < 1) return fail(c, QTX_ENOMEM, "no sweep workspace of one workgroup fits (sweep_workspace_bytes or device memory)");
-      QTX_HIP(c, alloc_sweep_ws(c, (size_t)grid * wsb, &retry));
+    if (c->se_method != 1) {
+      b.gdec = dec_grid(c, ne, sides, mixed);
+      QTX_HIP(c, c->dscr.ensure((size_t)b.gdec * qtx::dec_ws_elems(M) * sizeof(double2)));
+      b.dscr = c->dscr.as<double2>();
     }
-    QTX_HIP(c, c->part.ensure((size_t)grid * 4 * 2 * N * (mixed ? 2 : 1) * sizeof(double)));
+    b.wsb = qtx::sweep_ws_bytes(N, M, mixed);
+    for (bool retry = true; retry;) {
+      b.grid = sweep_grid(c, ne, M, mixed, b.wsb);
+      if (b.grid < 1)
+        return fail(c, QTX_ENOMEM, "no sweep workspace of one workgroup fits (sweep_workspace_bytes or device memory)");
+      QTX_HIP(c, alloc_sweep_ws(c, (size_t)b.grid * b.wsb, &retry));
+    }
+    b.sws = c->sws.as<char>();
+    QTX_HIP(c, c->part.ensure((size_t)b.grid * 4 * 2 * N * (mixed ? 2 : 1) * sizeof(double)));
+    b.part = c->part.as<double>();
     if (mixed) {
       QTX_HIP(c, c->redo.ensure((size_t)ne * sizeof(int)));
       QTX_HIP(c, c->elist.ensure((size_t)ne * sizeof(int)));
       QTX_HIP(c, c->ecount.ensure(sizeof(int)));
+      b.redo = c->redo.as<int>();
+      b.elist = c->elist.as<int>();
+      b.ecount = c->ecount.as<int>();
     }
-    qtx::Prob P = make_prob(c);
-    qtx::SweepArgs a{};
-    a.E = E_dev + e0;
-    a.nE = ne;
-    a.eta = eta;
-    a.sig = c->sig.as<double2>();
-    a.wf = c->wf.as<double2>();
-    a.sgn = c->sgn.as<double>();
-    a.iters = c->iters.as<int>();
-    a.nheavy = c->nheavy.as<int>();
-    a.ws = c->sws.as<char>();
-    a.ws_bytes = wsb;
-    a.part = c->part.as<double>();
-    a.nmax = N;
-    a.T = T_dev + e0;
-    a.ldos = ldos_dev ? ldos_dev + (size_t)e0 * 2 * N : nullptr;
-    a.info = info_dev ? info_dev + e0 : nullptr;
-    a.elist = nullptr;
-    a.ecount = nullptr;
-    a.redo = mixed ? c->redo.as<int>() : nullptr;
-    a.rtol = c->refine_tol;
-    a.maxstep = c->refine_max;
-    QTX_HIP(c, record(c, c->ev_sw, c->n_sw));
-    QTX_HIP(c, qtx::run_sweep(M, mixed, P, a, qtx::BatchDesc{}, grid, c->stream));
-    if (mixed) {
-      // energies whose refinement did not converge: FP64 sweep on the list
-      QTX_HIP(c, qtx::run_compact(c->redo.as<int>(), ne, c->elist.as<int>(), c->ecount.as<int>(), c->stream));
-      qtx::SweepArgs f = a;
-      f.elist = c->elist.as<int>();
-      f.ecount = c->ecount.as<int>();
-      f.redo = nullptr;
-      QTX_HIP(c, qtx::run_sweep(M, false, P, f, qtx::BatchDesc{}, grid, c->stream));
-    }
-    QTX_HIP(c, record(c, c->ev_sw, c->n_sw));
+    s = enqueue_chunk(c, E_dev + e0, ne, eta, mixed, T_dev + e0, ldos_dev ? ldos_dev + (size_t)e0 * 2 * N : nullptr,
+                      info_dev ? info_dev + e0 : nullptr, b);
+    if (s != QTX_OK) return s;
   }
   return QTX_OK;
 }
@@ -415,7 +477,15 @@ qtx_status density_matrix_core(qtx_ctx* c, const double* E_dev, const double* wL
   QTX_HIP(c, c->part.ensure((size_t)grid * 4 * 2 * N * sizeof(double)));
   for (int e0 = 0; e0 < nE; e0 += c->chunk) {
     const int ne = std::min(c->chunk, nE - e0);
-    s = stage_decimate(c, E_dev + e0, ne, eta, false);
+    SolveBufs db;
+    s = ensure_dec_outputs(c, ne, db);
+    if (s != QTX_OK) return s;
+    if (c->se_method != 1) {
+      db.gdec = dec_grid(c, ne, leads_identical(c) ? 1 : 2, false);
+      QTX_HIP(c, c->dscr.ensure((size_t)db.gdec * qtx::dec_ws_elems(M) * sizeof(double2)));
+      db.dscr = c->dscr.as<double2>();
+    }
+    s = stage_decimate(c, E_dev + e0, ne, eta, false, db);
     if (s != QTX_OK) return s;
     qtx::SweepArgs a{};
     a.E = E_dev + e0;
@@ -443,6 +513,74 @@ qtx_status density_matrix_core(qtx_ctx* c, const double* E_dev, const double* wL
     QTX_HIP(c, record(c, c->ev_sw, c->n_sw));
   }
   QTX_HIP(c, qtx::run_dm_reduce(c->rho.as<double2>(), grid, stride, N, M, m, out_d, out_o, c->stream));
+  return QTX_OK;
+}
+
+// Layout of one solve chunk inside the fixed no-allocation scratch: every
+// buffer the launch sequence uses, each at a 256-byte boundary.  Sizes
+// (energies per chunk, sweep and decimation workgroups) are chosen so that
+// the whole layout fits in cap bytes: the sweep workspaces take up to three
+// quarters, the decimation workgroups a quarter of the rest, the per-energy
+// decimation outputs what is left.  Fails when not even one energy with one
+// workgroup of each kernel fits.
+qtx_status plan_noalloc(qtx_ctx* c, int nE, bool mixed, char* base, size_t cap, int* chunk, SolveBufs* out) {
+  const int M = c->M, N = c->N;
+  const size_t MM = (size_t)M * M, AL = 256;
+  const int sides = leads_identical(c) ? 1 : 2;
+  auto up = [&](size_t x) { return (x + AL - 1) / AL * AL; };
+  const size_t wsb = qtx::sweep_ws_bytes(N, M, mixed);
+  const size_t per_wg = up(wsb) + up((size_t)4 * 2 * N * (mixed ? 2 : 1) * sizeof(double));
+  const size_t dec_wg = up(qtx::dec_ws_elems(M) * sizeof(double2));
+  const size_t per_e = 2 * (2 * MM * sizeof(double2)) + 2 * M * sizeof(double) + 4 * sizeof(int) +
+                       (mixed ? 2 * sizeof(int) : 0);
+  const size_t slack = 16 * AL;                       // alignment of the eleven regions and ecount
+  if (cap <= slack || per_wg + dec_wg + per_e > cap - slack)
+    return fail(c, QTX_ENOMEM,
+                "problem too large for the no-allocation scratch: one energy needs " +
+                    std::to_string(per_wg + dec_wg + per_e + slack) + " bytes, the scratch holds " +
+                    std::to_string(cap) + " (use qtx_solve_device)");
+  const size_t avail = cap - slack;
+  const double budget = c->sweep_eff >= 0.0 ? std::min(c->sweep_eff, c->sweep_bytes) : c->sweep_bytes;
+  long long grid = std::min<long long>({(long long)c->num_cu * wgs_per_cu(c, M, mixed), (long long)nE,
+                                        (long long)(0.75 * (double)avail / (double)per_wg),
+                                        (long long)std::floor(budget / (double)wsb)});
+  grid = std::max<long long>(grid, 1);
+  size_t rest = avail - (size_t)grid * per_wg;
+  long long gdec = std::min<long long>({(long long)c->num_cu * wgs_per_cu(c, M, mixed), (long long)nE * sides,
+                                        (long long)(rest / 4 / dec_wg)});
+  gdec = std::max<long long>(gdec, 1);
+  rest -= (size_t)gdec * dec_wg;
+  long long ne = std::min<long long>({(long long)nE, (long long)c->chunk, (long long)(rest / per_e)});
+  if (ne < 1)
+    return fail(c, QTX_ENOMEM, "problem too large for the no-allocation scratch (use qtx_solve_device)");
+  grid = std::min(grid, ne);
+  gdec = std::min(gdec, ne * sides);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* p = base + off;
+    off += up(bytes);
+    return p;
+  };
+  SolveBufs b;
+  b.sig = (double2*)take((size_t)ne * 2 * MM * sizeof(double2));
+  b.wf = (double2*)take((size_t)ne * 2 * MM * sizeof(double2));
+  b.sgn = (double*)take((size_t)ne * 2 * M * sizeof(double));
+  b.iters = (int*)take((size_t)ne * 2 * sizeof(int));
+  b.nheavy = (int*)take((size_t)ne * 2 * sizeof(int));
+  b.gdec = (int)gdec;
+  b.dscr = (double2*)take((size_t)gdec * qtx::dec_ws_elems(M) * sizeof(double2));
+  b.grid = (int)grid;
+  b.wsb = wsb;
+  b.sws = take((size_t)grid * wsb);
+  b.part = (double*)take((size_t)grid * 4 * 2 * N * (mixed ? 2 : 1) * sizeof(double));
+  if (mixed) {
+    b.redo = (int*)take((size_t)ne * sizeof(int));
+    b.elist = (int*)take((size_t)ne * sizeof(int));
+    b.ecount = (int*)take(sizeof(int));
+  }
+  if (off > cap) return fail(c, QTX_EDEVICE, "internal error: no-allocation layout exceeds the scratch");
+  *chunk = (int)ne;
+  *out = b;
   return QTX_OK;
 }
 
@@ -616,6 +754,38 @@ qtx_status qtx_solve_device(qtx_ctx* c, const double* E_dev, int nE, double eta,
   return solve_device_core(c, E_dev, nE, eta, prec, T_dev, ldos_dev, info_dev);
 }
 
+qtx_status qtx_solve_device_noalloc(qtx_ctx* c, const double* E_dev, int nE, double eta, qtx_precision prec,
+                                    double* T_dev, double* ldos_dev, qtx_info* info_dev) {
+  if (!c) return QTX_EINVAL;
+  if (prec != QTX_FP64 && prec != QTX_MIXED) return fail(c, QTX_EINVAL, "unknown precision");
+  QTX_HIP(c, hipSetDevice(c->device));
+  qtx_status s = check_solve_args(c, E_dev, nE, eta, prec, T_dev);
+  if (s != QTX_OK || nE == 0) return s;
+  if (c->se_method != 0)
+    return fail(c, QTX_EINVAL, "the no-allocation solve uses the decimation (self_energy_method 0)");
+  char* base = nullptr;
+  QTX_HIP(c, qtx::noalloc_scratch(c->device, &base));
+  const bool mixed = prec == QTX_MIXED;
+  int ne = 0;
+  SolveBufs b;
+  s = plan_noalloc(c, nE, mixed, base, qtx::kNoAllocScratchBytes, &ne, &b);
+  if (s != QTX_OK) return s;
+  // no kernel timing here: recording it could create events
+  const bool timing = c->timing;
+  c->timing = false;
+  const int N = c->N;
+  for (int e0 = 0; e0 < nE && s == QTX_OK; e0 += ne) {
+    const int k = std::min(ne, nE - e0);
+    SolveBufs bk = b;
+    bk.grid = std::min(b.grid, k);
+    bk.gdec = std::min(b.gdec, k * (leads_identical(c) ? 1 : 2));
+    s = enqueue_chunk(c, E_dev + e0, k, eta, mixed, T_dev + e0, ldos_dev ? ldos_dev + (size_t)e0 * 2 * N : nullptr,
+                      info_dev ? info_dev + e0 : nullptr, bk);
+  }
+  c->timing = timing;
+  return s;
+}
+
 qtx_status qtx_solve(qtx_ctx* c, const double* E, int nE, double eta, qtx_precision prec, double* T,
                      double* ldos, qtx_info* info) {
   if (!c) return QTX_EINVAL;
@@ -726,7 +896,15 @@ qtx_status qtx_self_energy(qtx_ctx* c, const double* E, int nE, double eta, qtx_
   const size_t MM = (size_t)M * M;
   QTX_HIP(c, c->wE.ensure((size_t)nE * sizeof(double)));
   QTX_HIP(c, hipMemcpyAsync(c->wE.p, E, (size_t)nE * sizeof(double), hipMemcpyHostToDevice, c->stream));
-  qtx_status s = stage_decimate(c, c->wE.as<double>(), nE, eta, false);
+  SolveBufs db;
+  qtx_status s = ensure_dec_outputs(c, nE, db);
+  if (s != QTX_OK) return s;
+  if (c->se_method != 1) {
+    db.gdec = dec_grid(c, nE, leads_identical(c) ? 1 : 2, false);
+    QTX_HIP(c, c->dscr.ensure((size_t)db.gdec * qtx::dec_ws_elems(M) * sizeof(double2)));
+    db.dscr = c->dscr.as<double2>();
+  }
+  s = stage_decimate(c, c->wE.as<double>(), nE, eta, false, db);
   if (s != QTX_OK) return s;
   std::vector<double2> hs((size_t)nE * 2 * MM), hw;
   std::vector<double> hg;

@@ -178,6 +178,14 @@ inline int modes_batch_jobs(int M, int njobs) {
   return njobs < jb ? njobs : jb;
 }
 
+// Fixed device scratch of the no-allocation solve: kNoAllocScratchBytes per
+// GPU (a file-scope device array), its device address for `device` (which
+// must be the current device) in *ptr.  The address is looked up once per
+// device and kept.
+constexpr size_t kNoAllocScratchBytes = (size_t)512 << 20;
+constexpr int kMaxDevices = 64;
+hipError_t noalloc_scratch(int device, char** ptr);
+
 // Band energies of one lead (padded blocks, physical size m) at nk Bloch
 // phases: E[q * m + n] = E_n(k_q) + V.  work: grid * 2 M (M + 1) complex
 // doubles when M > 64 (else unused).
