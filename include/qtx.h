@@ -240,11 +240,23 @@ qtx_status qtx_self_energy(qtx_ctx* ctx, const double* E, int nE, double eta,
  *                           every doubling, inf none;
  *   "decimation_max_iters"  [1, 1000]     60     doublings before
  *                           QTX_FLAG_DEC_NOTCONV;
- *   "refine_tol"            (0, 1)        1e-12  QTX_MIXED: refinement stops
+ *   "sigma_newton_tol"      [-1, 1)       3e-11  after the doublings every
+ *                           self-energy is checked against its fixed point
+ *                           Sigma = A (D0 - Sigma)^-1 B (A = U, B = L for
+ *                           the right contact, A = L, B = U for the left);
+ *                           where the residual exceeds this times max|Sigma|
+ *                           (near the lead's band edges) one Newton step
+ *                           corrects it, its linear (Stein) equation summed
+ *                           by doubling; 0 corrects every self-energy, a
+ *                           negative value none;
+ *   "refine_tol"            (0, 1)        3e-11  QTX_MIXED: refinement stops
  *                           when ||r||_F <= refine_tol ||b||_F over the
  *                           refined columns;
  *   "refine_max_steps"      [0, 20]       3      QTX_MIXED: corrections before
- *                           the energy is re-solved in FP64;
+ *                           the energy is re-solved in FP64 (earlier when a
+ *                           correction does not halve the residual, or when
+ *                           the contraction seen so far cannot reach
+ *                           refine_tol in the corrections left);
  *   "refine_weight_tol"     [0, 1]        1e-8   QTX_MIXED: columns of the
  *                           broadening factor whose LDL^H pivot is at least
  *                           this times the largest are refined (whole tiles

@@ -288,6 +288,21 @@ def solve_batch(ctx: Context, problems, energies, eta, precision=FP64, want_ldos
     return Ts, Ls, st
 
 
+def charge(ldos, w, E, muL, muR, kT):
+    """qtx_charge: Fermi-weighted slab charge sum_k w_k (f_L n^L + f_R n^R)
+    of densities ldos (nE, 2, N) at energies E with weights w."""
+    lib = load()
+    ldos = np.ascontiguousarray(ldos, dtype=np.float64)
+    nE, _, N = ldos.shape
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    E = np.ascontiguousarray(E, dtype=np.float64)
+    out = np.empty(N)
+    st = lib.qtx_charge(_ptr(ldos), _ptr(w), nE, N, _ptr(E), float(muL), float(muR), float(kT), _ptr(out))
+    if st != OK:
+        raise QtxError(st, "qtx_charge")
+    return out
+
+
 def context_for(dev, device: int = 0) -> Context:
     """A context loaded with one transport problem (workloads.Device)."""
     ctx = Context(device)

@@ -122,9 +122,10 @@ struct qtx_ctx {
   int dec_maxit = 60;
   int chunk = 4096;
   int wg_per_cu = 2;
-  double refine_tol = 1e-12;      // stop when ||r|| <= refine_tol ||b||
+  double refine_tol = 3e-11;      // stop when ||r|| <= refine_tol ||b||
   int refine_max = 3;             // corrections per energy before the FP64 fallback
   double heavy_tol = 1e-8;        // refine columns with pivot >= heavy_tol * largest
+  double newton_tol = 3e-11;      // Newton step on a self-energy whose fixed-point residual exceeds this
   std::map<int, int> tuned_wg[2];  // autotuned workgroups per CU by block size (FP64, mixed)
 };
 
@@ -234,7 +235,9 @@ hipError_t alloc_sweep_ws(qtx_ctx* c, size_t bytes, bool* retry) {
   return hipSuccess;
 }
 
-qtx::DecOpts dec_opts(const qtx_ctx* c) { return qtx::DecOpts{c->dec_tol, c->dec_rcond, c->dec_maxit, c->heavy_tol}; }
+qtx::DecOpts dec_opts(const qtx_ctx* c) {
+  return qtx::DecOpts{c->dec_tol, c->dec_rcond, c->dec_maxit, c->heavy_tol, c->newton_tol};
+}
 
 qtx::Prob make_prob(const qtx_ctx* c) {
   qtx::Prob P;
@@ -977,6 +980,9 @@ qtx_status qtx_set_option(qtx_ctx* c, const char* name, double value) {
   } else if (n == "decimation_refine_cond") {
     if (!(value >= 0.0)) return fail(c, QTX_EINVAL, "decimation_refine_cond must be >= 0");
     c->dec_rcond = value;
+  } else if (n == "sigma_newton_tol") {
+    if (!(value >= -1.0 && value < 1.0)) return fail(c, QTX_EINVAL, "sigma_newton_tol must be in [-1, 1)");
+    c->newton_tol = value;
   } else if (n == "decimation_max_iters") {
     if (!integral || value < 1 || value > 1000) return fail(c, QTX_EINVAL, "decimation_max_iters must be in [1, 1000]");
     c->dec_maxit = (int)value;
@@ -1044,6 +1050,7 @@ qtx_status qtx_problem_create(qtx_ctx* parent, qtx_ctx** problem) {
   c->refine_tol = parent->refine_tol;
   c->refine_max = parent->refine_max;
   c->heavy_tol = parent->heavy_tol;
+  c->newton_tol = parent->newton_tol;
   c->use_graph = parent->use_graph;
   c->dm_bytes = parent->dm_bytes;
   c->sweep_bytes = parent->sweep_bytes;
@@ -1275,7 +1282,8 @@ qtx_status qtx_solve_batch(qtx_ctx* c, int nprob, qtx_ctx* const* probs, const d
     }
   } guard{c};
   if (cached) {
-    const std::vector<double> params = {eta, c->dec_tol, c->dec_rcond, (double)c->dec_maxit, c->heavy_tol};
+    const std::vector<double> params = {eta, c->dec_tol, c->dec_rcond, (double)c->dec_maxit, c->heavy_tol,
+                                        c->newton_tol};
     if (params != c->cache_params) {
       for (auto& kv : c->sigcache) {
         kv.second.index.clear();
@@ -1461,6 +1469,8 @@ qtx_status qtx_solve_batch(qtx_ctx* c, int nprob, qtx_ctx* const* probs, const d
   std::memcpy(&eb, &c->dec_tol, sizeof(eb));
   sig.push_back(eb);
   std::memcpy(&eb, &c->dec_rcond, sizeof(eb));
+  sig.push_back(eb);
+  std::memcpy(&eb, &c->newton_tol, sizeof(eb));
   sig.push_back(eb);
   std::memcpy(&eb, &c->sweep_bytes, sizeof(eb));
   sig.push_back(eb);

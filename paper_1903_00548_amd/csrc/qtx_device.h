@@ -130,6 +130,14 @@ template <typename R> struct ALds {            // row-major in LDS
   __device__ __forceinline__ cpx<R> get(int row, int k) const { return p[row * S + k]; }
 };
 
+struct ALdsF {                                 // FP64 row-major in LDS, read as FP32
+  const cpx<double>* p; int S;
+  __device__ __forceinline__ cpx<float> get(int row, int k) const {
+    const cpx<double> v = p[row * S + k];
+    return mk<float>((float)v.re, (float)v.im);
+  }
+};
+
 template <typename R> struct AGlob {           // row-major global, optionally negated
   const typename vec2t<R>::type* p; int ld; R sgn;
   __device__ __forceinline__ cpx<R> get(int row, int k) const {
@@ -215,6 +223,17 @@ template <typename R> struct BGen {
     cpx<double> sv = ldd(S + (size_t)k * M + col);
     cpx<double> hv = ldd(H + (size_t)k * M + col);
     return mk<R>((R)(zv.re * sv.re - zv.im * sv.im - hv.re), (R)(zv.re * sv.im + zv.im * sv.re - hv.im));
+  }
+};
+
+// B[k][col] = zv * conj(S[col][k]) - conj(H[col][k]): the coupling block
+// back from slab j+1 to slab j as a B operand.
+template <typename R> struct BGenCT {
+  const double2* S; const double2* H; cpx<double> zv; int M;
+  __device__ __forceinline__ cpx<R> get(int k, int col) const {
+    cpx<double> sv = ldd(S + (size_t)col * M + k);
+    cpx<double> hv = ldd(H + (size_t)col * M + k);
+    return mk<R>((R)(zv.re * sv.re + zv.im * sv.im - hv.re), (R)(zv.im * sv.re - zv.re * sv.im + hv.im));
   }
 };
 

@@ -111,10 +111,13 @@ struct SweepArgs {
 // The density-matrix sweep (FP64) keeps a second back-substitution buffer.
 // Blocks above 64 (96, 128) keep two more M x (M + 1) complex matrices of
 // the sweep precision at the end: the working matrix and the staged
-// coupling block.
+// coupling block, and in the mixed sweep before them one M x (M + 1) FP64
+// block staged for the refinement's residual products.
 inline size_t sweep_ws_bytes(int N, int M, bool mixed, bool dm = false) {
   const size_t MM = (size_t)M * M;
-  const size_t big = M > 64 ? 2 * (size_t)M * (M + 1) * (mixed ? sizeof(float2) : sizeof(double2)) : 0;
+  const size_t big = M > 64 ? 2 * (size_t)M * (M + 1) * (mixed ? sizeof(float2) : sizeof(double2)) +
+                                  (mixed ? (size_t)M * (M + 1) * sizeof(double2) : 0)
+                            : 0;
   if (!mixed) return (size_t)(N + (dm ? 2 : 1)) * 2 * MM * sizeof(double2) + big;
   return ((size_t)(N + 1) * 2 * MM + (size_t)N * MM + (size_t)N * 2 * MM + 2 * MM) * sizeof(float2) +
          (size_t)N * 2 * MM * sizeof(double2) + big;
@@ -133,12 +136,15 @@ inline int padded_block(int m) { return m <= 64 ? ((m + 15) / 16) * 16 : (m <= 9
 // Decimation settings: stop when the couplings fall below tol |D0| (at most
 // maxit doublings); refine g [a | b] when ||e||_F ||e^-1||_F > rcond (every
 // doubling for rcond = 0); heavy_tol sets the count of leading broadening
-// columns reported per contact.
+// columns reported per contact; a self-energy whose fixed-point residual
+// exceeds newton_tol times its largest element takes one Newton step
+// (always for newton_tol = 0, never for newton_tol < 0).
 struct DecOpts {
   double tol;
   double rcond;
   int maxit;
   double heavy_tol;
+  double newton_tol;
 };
 
 hipError_t run_decimate(int M, const Prob& P, const BatchDesc& b, const double* E, int nE, double eta, int sides,

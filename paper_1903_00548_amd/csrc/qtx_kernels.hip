@@ -357,6 +357,219 @@ __device__ __forceinline__ Prob load_prob(const Prob* pp) {
   return P;
 }
 
+// One self-energy job of a decimation launch.  Single problem: jobs
+// (energy, side), or one job per energy (side -1: both surfaces of one lead
+// iteration) when both leads are the same; batch: the job list names item
+// and side; self-energy cache: job j fills slot job_item[j] (both surfaces)
+// for the lead job_lead[j] at the already shifted energy job_E[j].
+struct DecJob {
+  int e, side;
+  const double2* lead;
+  cpx<double> zx;          // E - V_lead + i eta
+};
+__device__ __forceinline__ DecJob dec_job(const Prob& P0, const BatchDesc& b, const double* E, double eta, int sides,
+                                          int job) {
+  DecJob J;
+  if (b.job_E) {
+    J.e = __builtin_amdgcn_readfirstlane(b.job_item[job]);
+    J.side = -1;
+    J.lead = uni(b.job_lead[job]);
+    J.zx = mk<double>(b.job_E[job], eta);
+    return J;
+  }
+  Prob P = P0;
+  if (b.probs) {
+    J.e = __builtin_amdgcn_readfirstlane(b.job_item[job]);
+    J.side = __builtin_amdgcn_readfirstlane(b.job_side[job]);
+    P = load_prob(b.probs + __builtin_amdgcn_readfirstlane(b.item_prob[J.e]));
+  } else {
+    J.e = job / sides;
+    J.side = (sides == 2) ? (job % 2) : -1;
+  }
+  J.lead = (J.side == 1) ? P.leadR : P.leadL;
+  J.zx = mk<double>(E[J.e] - ((J.side == 1) ? P.VR : P.VL), eta);
+  return J;
+}
+
+// ------------------------------------------------ self-energy Newton step
+// max(a, b), NaN if either is NaN
+__device__ __forceinline__ double max_nan(double a, double b) { return (a != a) ? a : ((b != b || b > a) ? b : a); }
+
+// Largest |re| + |im| over the workgroup with NaN propagated (a NaN
+// anywhere makes the result NaN); every thread gets the same value.
+// red: NWAVE doubles of LDS.  Two barriers.
+__device__ __forceinline__ double block_max_nan(double v, double* red) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    const double o = __shfl_xor(v, m, 64);
+    v = (o != o || o > v) ? o : v;
+  }
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = red[0];
+#pragma unroll
+  for (int q = 1; q < NWAVE; ++q) r = (red[q] != red[q] || red[q] > r) ? red[q] : r;
+  __syncthreads();
+  return r;
+}
+
+// Each wave computes the column tiles tj = w, w + NWAVE, ... of an M x M
+// product A B (FP64) into acc and hands every element to fn(idx, re, im).
+template <int M, class AF, class BF, class F>
+__device__ __forceinline__ void prod_cols(const AF& A, const BF& B, F fn) {
+  constexpr int MT = M / 16;
+  const int w = threadIdx.x >> 6;
+#pragma unroll 1
+  for (int tj = w; tj < MT; tj += NWAVE) {
+    ctile<double> acc[MT];
+#pragma unroll
+    for (int ti = 0; ti < MT; ++ti) tzero(acc[ti]);
+    cgemm_col<double, MT, MT>(acc, A, B, tj);
+    tiles_foreach<double, MT>(acc, tj, [&](int row, int col, int ti, int r) {
+      fn((unsigned)(row * M + col), acc[ti].re[r], acc[ti].im[r]);
+    });
+  }
+}
+
+// The doubling reaches a self-energy through a chain of eliminations whose
+// rounding errors nothing corrects afterwards; within about a meV of a
+// band edge of the lead the result then misses its fixed point
+//   Sigma = A (D0 - Sigma)^-1 B     (right contact: A = U, B = L;
+//                                     left contact:  A = L, B = U)
+// by up to 1e-10 relative (Sec. "Contact self-energies": Sigma is the
+// projection of the lead's outgoing Bloch modes, which this equation
+// characterises), and the density of states there amplifies that error.
+// The residual R = Sigma - A G B with G = (D0 - Sigma)^-1 is formed for
+// every self-energy; where max|R| > tol max|Sigma| one Newton step
+// Sigma += X follows, X solving the linearised fixed point
+//   X - P X Q = -R,   P = A G,  Q = G B,
+// a Stein equation, summed as the series X = sum_j P^j (-R) Q^j by
+// doubling: X_0 = -R, X_{k+1} = X_k + P_k X_k Q_k, P_{k+1} = P_k^2,
+// Q_{k+1} = Q_k^2, until a term no longer changes X (P and Q decay like
+// the lead's Bloch factors, about 20 doublings at eta = 1e-6).  A
+// correction that is not finite or not small against Sigma is dropped.
+// ws: 7 M^2 complex doubles of free global workspace; mat, Y, sc: the
+// Gauss-Jordan matrix, scratch and pivots; red: NWAVE doubles of LDS.
+template <int M>
+__device__ void sigma_newton(double2* sig, const double2* lead, cpx<double> zx, int side, double tol, double2* ws,
+                             cpx<double>* mat, cpx<double>* Y, BGJ<double, M>& sc, double* red) {
+  constexpr int MT = M / 16, MM = M * M, S = M + 1;
+  const int t = threadIdx.x, w = t >> 6;
+  const double2 *H00 = lead, *H01 = lead + MM, *S00 = lead + 2 * MM, *S01 = lead + 3 * MM;
+  double2* Gn = ws;                 // G in natural row/column order
+  double2* Q = ws + MM;
+  double2* P = ws + 2 * MM;
+  double2* X = ws + 3 * MM;
+  double2* T1 = ws + 4 * MM;
+  double2* P2 = ws + 5 * MM;
+  double2* Q2 = ws + 6 * MM;
+  double2* Bn = T1;                 // B in natural order until the doubling needs T1
+  // D0 - Sigma into the working matrix, B (= L or U) into Bn, max|Sigma|
+  double smax = 0.0;
+  for (int idx = t; idx < MM; idx += NT) {
+    const int r = idx / M, c = idx - r * M;
+    const cpx<double> sv = ldd(S00 + idx), hv = ldd(H00 + idx), g = ldd(sig + idx);
+    mat[r * S + c] = mk<double>(zx.re * sv.re - zx.im * sv.im - hv.re - g.re,
+                                zx.re * sv.im + zx.im * sv.re - hv.im - g.im);
+    smax = max_nan(smax, fabs(g.re) + fabs(g.im));
+    if (side == 0) {                // U[r][c]
+      const cpx<double> s1 = ldd(S01 + idx), h1 = ldd(H01 + idx);
+      Bn[idx] = make_double2(zx.re * s1.re - zx.im * s1.im - h1.re, zx.re * s1.im + zx.im * s1.re - h1.im);
+    } else {                        // L[c][r] from S01[r][c], H01[r][c] (coalesced read)
+      const cpx<double> s1 = ldd(S01 + idx), h1 = ldd(H01 + idx);
+      Bn[c * M + r] = make_double2(zx.re * s1.re + zx.im * s1.im - h1.re, zx.im * s1.re - zx.re * s1.im + h1.im);
+    }
+  }
+  smax = block_max_nan(smax, red);
+  gj_inverse<double, M>(mat, S, Y, sc);
+  // Q = G B = P_r (mat (B rows in pivot order)), rows landing through pinv
+#pragma unroll 1
+  for (int tj = w; tj < MT; tj += NWAVE) {
+    ctile<double> acc[MT];
+#pragma unroll
+    for (int ti = 0; ti < MT; ++ti) tzero(acc[ti]);
+    cgemm_col<double, MT, MT>(acc, ALds<double>{mat, S}, BPerm<BGlob<double>>{BGlob<double>{Bn, M}, sc.piv}, tj);
+    tiles_foreach<double, MT>(acc, tj, [&](int row, int col, int ti, int r) {
+      Q[(unsigned)(sc.pinv[row] * M + col)] = make_double2(acc[ti].re[r], acc[ti].im[r]);
+    });
+  }
+  for (int idx = t; idx < MM; idx += NT) {
+    const int j = idx / M, c = idx - j * M;
+    const cpx<double> v = mat[sc.piv[j] * S + sc.pinv[c]];
+    Gn[idx] = make_double2(v.re, v.im);
+  }
+  __syncthreads();
+  // A (= U or L) staged in the working matrix for the two products that use it
+  for (int idx = t; idx < MM; idx += NT) {
+    const int r = idx / M, c = idx - r * M;
+    const cpx<double> s1 = ldd(S01 + idx), h1 = ldd(H01 + idx);
+    if (side == 1)
+      mat[r * S + c] = mk<double>(zx.re * s1.re - zx.im * s1.im - h1.re, zx.re * s1.im + zx.im * s1.re - h1.im);
+    else
+      mat[c * S + r] = mk<double>(zx.re * s1.re + zx.im * s1.im - h1.re, zx.im * s1.re - zx.re * s1.im + h1.im);
+  }
+  __syncthreads();
+  auto store = [](double2* D) { return [D](unsigned idx, double re, double im) { D[idx] = make_double2(re, im); }; };
+  const ALds<double> As{mat, S};
+  // X_0 = -R = A Q - Sigma
+  double cmax = 0.0;
+  prod_cols<M>(As, BGlob<double>{Q, M}, [&](unsigned idx, double re, double im) {
+    const double2 g = sig[idx];
+    const double2 v = make_double2(re - g.x, im - g.y);
+    X[idx] = v;
+    cmax = max_nan(cmax, fabs(v.x) + fabs(v.y));
+  });
+  cmax = block_max_nan(cmax, red);
+  if (!(cmax > tol * smax)) return;              // uniform; also for a non-finite residual
+  prod_cols<M>(As, BGlob<double>{Gn, M}, store(P));                          // P = A G (A still staged)
+  __syncthreads();
+  // the A operand of every product staged in the working matrix
+  auto stage = [&](const double2* src) {
+    for (int idx = t; idx < MM; idx += NT) {
+      const int r = idx / M, c = idx - r * M;
+      const double2 v = src[idx];
+      mat[r * S + c] = mk<double>(v.x, v.y);
+    }
+    __syncthreads();
+  };
+  double xmax = cmax;
+#pragma unroll 1
+  for (int k = 0; k < 64; ++k) {
+    stage(P);
+    prod_cols<M>(As, BGlob<double>{X, M}, store(T1));
+    prod_cols<M>(As, BGlob<double>{P, M}, store(P2));
+    __syncthreads();
+    stage(T1);
+    // X += T1 Q (a wave reads and writes only its own column tiles of X)
+    double imax = 0.0, xm = 0.0;
+    prod_cols<M>(As, BGlob<double>{Q, M}, [&](unsigned idx, double re, double im) {
+      double2 v = X[idx];
+      v.x += re;
+      v.y += im;
+      X[idx] = v;
+      imax = max_nan(imax, fabs(re) + fabs(im));
+      xm = max_nan(xm, fabs(v.x) + fabs(v.y));
+    });
+    __syncthreads();
+    stage(Q);
+    prod_cols<M>(As, BGlob<double>{Q, M}, store(Q2));
+    imax = block_max_nan(imax, red);
+    xmax = block_max_nan(xm, red);
+    double2* tp = P; P = P2; P2 = tp;
+    tp = Q; Q = Q2; Q2 = tp;
+    if (!(imax > 1e-17 * xmax)) break;           // converged, or non-finite
+  }
+  if (!(xmax <= 1e-3 * smax)) return;            // not a small correction (or NaN): keep Sigma
+  for (int idx = t; idx < MM; idx += NT) {
+    double2 g = sig[idx];
+    const double2 x = X[idx];
+    g.x += x.x;
+    g.y += x.y;
+    sig[idx] = g;
+  }
+  __syncthreads();
+}
+
 // ------------------------------------------------------------- decimation
 // Doubling elimination of the semi-infinite lead: with on-site e and
 // couplings a (slab j -> j+1) and b (j+1 -> j), eliminating every other slab
@@ -373,10 +586,11 @@ __device__ __forceinline__ Prob load_prob(const Prob* pp) {
 // of them away from the lead's band edges, skip the step's two products.
 template <int M>
 __global__ __launch_bounds__(NT, M > 64 ? 1 : 2) void k_decimate(Prob P0, BatchDesc b, const double* E, int nE,
-                                                                 double eta, int sides, double tol, double rcond,
-                                                                 int maxit, double heavy_tol, double2* scratch,
-                                                                 double2* sig,
-                                                                 double2* wf, double* sgn, int* iters, int* nheavy) {
+                                                                 double eta, int sides, DecOpts o, double2* scratch,
+                                                                 double2* sig, double2* wf, double* sgn, int* iters,
+                                                                 int* nheavy) {
+  const double tol = o.tol, rcond = o.rcond;
+  const int maxit = o.maxit;
   constexpr int MT = M / 16, MM = M * M, S = M + 1, LB = 2 * M;
   constexpr bool BIG = M > 64;                    // working matrix in the global workspace
   __shared__ cpx<double> mat_l[BIG ? 1 : M * S];
@@ -401,29 +615,11 @@ __global__ __launch_bounds__(NT, M > 64 ? 1 : 2) void k_decimate(Prob P0, BatchD
   double2* Rr = ws + 6 * MM;                      // residual
   const int njobs = b.probs ? b.njobs : nE * sides;
   for (int job = blockIdx.x; job < njobs; job += gridDim.x) {
-    // single problem: jobs (energy, side), or one job per energy when both
-    // leads are the same; batch: the job list names item and side
-    int e, side;
-    Prob P = P0;
-    if (b.job_E) {
-      // self-energy cache: job j fills slot job_item[j] (both surfaces) for
-      // the lead job_lead[j] at the already shifted energy job_E[j]
-      e = __builtin_amdgcn_readfirstlane(b.job_item[job]);
-      side = -1;
-      P.leadL = P.leadR = uni(b.job_lead[job]);
-      P.VL = P.VR = 0.0;
-    } else if (b.probs) {
-      e = __builtin_amdgcn_readfirstlane(b.job_item[job]);
-      side = __builtin_amdgcn_readfirstlane(b.job_side[job]);
-      P = load_prob(b.probs + __builtin_amdgcn_readfirstlane(b.item_prob[e]));
-    } else {
-      e = job / sides;
-      side = (sides == 2) ? (job % 2) : -1;
-    }
-    const double2* lead = (side == 1) ? P.leadR : P.leadL;
-    const double V = (side == 1) ? P.VR : P.VL;
+    const DecJob J = dec_job(P0, b, E, eta, sides, job);
+    const int e = J.e, side = J.side;
+    const double2* lead = J.lead;
     const double2 *H00 = lead, *H01 = lead + MM, *S00 = lead + 2 * MM, *S01 = lead + 3 * MM;
-    const cpx<double> zx = mk<double>((b.job_E ? b.job_E[job] : E[e]) - V, eta);
+    const cpx<double> zx = J.zx;
     double scl = 0.0;
     for (int idx = t; idx < MM; idx += NT) {
       const int r = idx / M, c = idx - r * M;
@@ -575,49 +771,138 @@ __global__ __launch_bounds__(NT, M > 64 ? 1 : 2) void k_decimate(Prob P0, BatchD
         sig[(size_t)(2 * e + 1) * MM + idx] = make_double2(dr - vr.x, di - vr.y);
       }
     }
-    __syncthreads();
     for (int s = 0; s < 2; ++s) {
       if ((side == 0 && s == 1) || (side == 1 && s == 0)) continue;
-      gamma_ldl<M>(sig + (size_t)(2 * e + s) * MM, wf + (size_t)(2 * e + s) * MM, sgn + (size_t)(2 * e + s) * M,
-                   heavy_tol, nheavy + 2 * e + s, u.ldl);
       if (t == 0) iters[2 * e + s] = it;
     }
     __syncthreads();
   }
 }
 
+// Second stage of the self-energy jobs of a decimation launch (same jobs,
+// same workspace): the Newton check and step on each self-energy (option
+// newton_tol >= 0), then the LDL^H factor of its broadening.  A kernel of its
+// own so that the doubling loop keeps its registers.
+template <int M>
+__global__ __launch_bounds__(NT, M > 64 ? 1 : 2) void k_sigma_finish(Prob P0, BatchDesc b, const double* E, int nE,
+                                                                     double eta, int sides, DecOpts o,
+                                                                     double2* scratch, double2* sig, double2* wf,
+                                                                     double* sgn, int* nheavy) {
+  constexpr int MM = M * M, S = M + 1;
+  constexpr bool BIG = M > 64;
+  __shared__ cpx<double> mat_l[BIG ? 1 : M * S];
+  __shared__ union {
+    cpx<double> y[gj_scratch<M>()];
+    LDLScratch<M> ldl;
+  } u;
+  __shared__ BGJ<double, M> sc;
+  __shared__ double red[NWAVE];
+  double2* ws = scratch + (size_t)blockIdx.x * dec_ws_elems(M);
+  cpx<double>* mat;
+  if constexpr (BIG) mat = (cpx<double>*)(ws + 8 * MM);
+  else mat = mat_l;
+  const int njobs = b.probs ? b.njobs : nE * sides;
+  for (int job = blockIdx.x; job < njobs; job += gridDim.x) {
+    const DecJob J = dec_job(P0, b, E, eta, sides, job);
+    for (int s = 0; s < 2; ++s) {
+      if ((J.side == 0 && s == 1) || (J.side == 1 && s == 0)) continue;
+      const size_t k = 2 * (size_t)J.e + s;
+      if (o.newton_tol >= 0.0) sigma_newton<M>(sig + k * MM, J.lead, J.zx, s, o.newton_tol, ws, mat, u.y, sc, red);
+      gamma_ldl<M>(sig + k * MM, wf + k * MM, sgn + k * M, o.heavy_tol, nheavy + k, u.ldl);
+      __syncthreads();
+    }
+  }
+}
+
 // ------------------------------------------------------------ refinement
+// -B (FP64) into the M x (M + 1) buffer stg for one block B of row i of
+// A(z): which = 0: U_i = A_{i,i+1}; 1: A_ii, with the contact self-energies
+// subtracted on the end slabs; 2: L_i = A_{i,i-1}.  All threads; no barrier.
+template <int M>
+__device__ __forceinline__ void stage_neg_block(cpx<double>* stg, const Prob& P, cpx<double> z, int i, int which,
+                                                const double2* sL, const double2* sR) {
+  constexpr int MM = M * M, S = M + 1;
+  const int t = threadIdx.x, N = P.N;
+  if (which == 0) {
+    const cpx<double> zu = mk<double>(z.re - P.vu(i), z.im);
+    const double2 *Su = P.Su(i), *Hu = P.Hu(i);
+    for (int idx = t; idx < MM; idx += NT) {
+      const int r = idx / M, k = idx - r * M;
+      const cpx<double> sv = ldd(Su + idx), hv = ldd(Hu + idx);
+      stg[r * S + k] = mk<double>(hv.re - (zu.re * sv.re - zu.im * sv.im), hv.im - (zu.re * sv.im + zu.im * sv.re));
+    }
+  } else if (which == 1) {
+    const cpx<double> zd = mk<double>(z.re - P.vd(i), z.im);
+    const double2 *Sd = P.Sd(i), *Hd = P.Hd(i);
+    for (int idx = t; idx < MM; idx += NT) {
+      const int r = idx / M, k = idx - r * M;
+      const cpx<double> sv = ldd(Sd + idx), hv = ldd(Hd + idx);
+      double re = zd.re * sv.re - zd.im * sv.im - hv.re, im = zd.re * sv.im + zd.im * sv.re - hv.im;
+      if (i == 0) {
+        const cpx<double> g = ldd(sL + idx);
+        re -= g.re;
+        im -= g.im;
+      }
+      if (i == N - 1) {
+        const cpx<double> g = ldd(sR + idx);
+        re -= g.re;
+        im -= g.im;
+      }
+      stg[r * S + k] = mk<double>(-re, -im);
+    }
+  } else {
+    const cpx<double> zu = mk<double>(z.re - P.vu(i - 1), z.im);
+    const double2 *Su = P.Su(i - 1), *Hu = P.Hu(i - 1);
+    for (int idx = t; idx < MM; idx += NT) {
+      const int k = idx / M, r = idx - k * M;       // read S[k][r] along r
+      const cpx<double> sv = ldd(Su + idx), hv = ldd(Hu + idx);
+      const double re = zu.re * sv.re + zu.im * sv.im - hv.re;
+      const double im = zu.im * sv.re - zu.re * sv.im + hv.im;
+      stg[r * S + k] = mk<double>(-re, -im);
+    }
+  }
+}
+
 // Mixed-precision refinement of the heavy injected columns of one energy
 // (the single-precision sweep has left its factors X_i, Dt_i^-1 and its
 // solution, widened to FP64, in P64).  One step:
-//   forward:  r_i = b_i - (L_i psi_{i-1} + A_ii psi_i + U_i psi_{i+1})  (FP64)
-//             c_i = Dt_i^-1 (r_i - L_i c_{i-1})                          (FP32 factors)
+//   forward:  r_i = b_i - (U_i psi_{i+1} + A_ii psi_i + L_i psi_{i-1})  (FP64)
+//             c_i = Dt_i^-1 (r_i - L_i c_{i-1})                          (FP32)
 //   backward: d_i = c_i - X_i d_{i+1},   psi_i += d_i
 // repeated until ||r||_F <= rtol ||b||_F over the refined columns, with at
-// most maxstep corrections, stopping early when a correction fails to halve
-// the residual.  The refined columns are the first hR column
-// tiles of the right injection and the first hL of the left one (the
-// broadening factor orders its columns by decreasing weight).  The output
-// tiles (row tile, column tile) are dealt round-robin to the waves, so a
-// slab takes two barriers forward and one backward.  Returns the last
-// relative residual; *steps receives the corrections applied.
+// most maxstep corrections.  It stops early when a correction fails to
+// halve the residual, or when the contraction observed so far could not
+// reach rtol in the corrections left: the FP64 fallback then takes over.
+// The refined columns are the first hR column tiles of the right injection
+// and the first hL of the left one (the broadening factor orders its
+// columns by decreasing weight).
+// Every residual product is a full column of tiles (M rows, 16 columns) of
+// an M x M block times the solution, with the block staged once per slab
+// in stg (FP64, LDS for M <= 64) and read by every wave.  A wave keeps the
+// same column tiles through the whole chain (up to TPP at a time), so the
+// correction's dependencies (c_{i-1} -> c_i, d_{i+1} -> d_i) stay within
+// the wave: the forward pass takes barriers only around the stagings, the
+// backward pass none.  Returns the last relative residual; *steps receives
+// the corrections applied.
 template <int M>
 __device__ __forceinline__ double refine(const Prob& P, const SweepArgs& a, const double2* sL, const double2* sR,
                                          const double2* WL, const double2* WR, cpx<double> z, int hR, int hL,
                                          const float2* XZ, const float2* DI, float2* ZC, float2* YB, double2* P64,
-                                         double* red, int* steps) {
-  constexpr int MT = M / 16, MM = M * M, LD = 2 * M;
-  const int N = P.N, t = threadIdx.x, w = t >> 6;
-  const int npair = MT * (hR + hL);
-  // column tile of the q-th refined tile: right injection first
+                                         cpx<double>* stg, double* red, int* steps) {
+  constexpr int MT = M / 16, MM = M * M, LD = 2 * M, S = M + 1;
+  constexpr int TPP = M <= 64 ? 2 : 1;              // column tiles per wave and pass
+  const int N = P.N, w = threadIdx.x >> 6;
+  const int nc = hR + hL;
+  const int npass = (nc + NWAVE * TPP - 1) / (NWAVE * TPP);
+  // column tile of the q-th refined tile (right injection first); the
+  // wave's u-th tile of pass p is q = (p TPP + u) NWAVE + w
   auto colt = [&](int q) { return q < hR ? q : MT + q - hR; };
   double bb = 0.0;
-  for (int p = w; p < npair; p += NWAVE) {
-    const int ti = p % MT, tj = colt(p / MT);
-    ctile<double> acc[1];
-    tiles_foreach<double, 1>(acc, tj, [&](int row, int col, int, int) {
-      const int gr = 16 * ti + row;
-      const cpx<double> v = col < M ? ldd(WR + gr * M + col) : ldd(WL + gr * M + col - M);
+  for (int q = w; q < nc; q += NWAVE) {
+    const int tj = colt(q);
+    ctile<double> acc[MT];
+    tiles_foreach<double, MT>(acc, tj, [&](int row, int col, int, int) {
+      const cpx<double> v = col < M ? ldd(WR + row * M + col) : ldd(WL + row * M + col - M);
       bb += v.re * v.re + v.im * v.im;
     });
   }
@@ -628,95 +913,121 @@ __device__ __forceinline__ double refine(const Prob& P, const SweepArgs& a, cons
     double rr = 0.0;
     for (int i = 0; i < N; ++i) {
       const double2* Pi = P64 + (size_t)i * M * LD;
-      const cpx<double> zd = mk<double>(z.re - P.vd(i), z.im);
-#pragma unroll 1
-      for (int p = w; p < npair; p += NWAVE) {
-        const int ti = p % MT, tj = colt(p / MT);
-        const bool bL = (i == 0 && tj >= MT), bR = (i == N - 1 && tj < MT);
-        ctile<double> acc[1];
-        tiles_foreach<double, 1>(acc, tj, [&](int row, int col, int, int r) {
-          const int gr = 16 * ti + row;
-          cpx<double> v = mk<double>(0.0, 0.0);
-          if (bL) v = ldd(WL + gr * M + col - M);
-          if (bR) v = ldd(WR + gr * M + col);
-          acc[0].re[r] = v.re;
-          acc[0].im[r] = v.im;
-        });
-        cgemm_col<double, 1, MT>(acc, ARows<AGen<double>>{{P.Sd(i), P.Hd(i), zd, -1.0, M}, 16 * ti},
-                                 BGlob<double>{Pi, LD}, tj);
-        if (i == 0) cgemm_col<double, 1, MT>(acc, ARows<AGlob<double>>{{sL, M, 1.0}, 16 * ti}, BGlob<double>{Pi, LD}, tj);
-        if (i == N - 1) cgemm_col<double, 1, MT>(acc, ARows<AGlob<double>>{{sR, M, 1.0}, 16 * ti}, BGlob<double>{Pi, LD}, tj);
-        if (i > 0) {
-          const cpx<double> zu = mk<double>(z.re - P.vu(i - 1), z.im);
-          cgemm_col<double, 1, MT>(acc, ARows<AGenCT<double>>{{P.Su(i - 1), P.Hu(i - 1), zu, -1.0, M}, 16 * ti},
-                                   BGlob<double>{Pi - (size_t)M * LD, LD}, tj);
-        }
-        if (i < N - 1) {
-          const cpx<double> zu = mk<double>(z.re - P.vu(i), z.im);
-          cgemm_col<double, 1, MT>(acc, ARows<AGen<double>>{{P.Su(i), P.Hu(i), zu, -1.0, M}, 16 * ti},
-                                   BGlob<double>{Pi + (size_t)M * LD, LD}, tj);
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) rr += acc[0].re[r] * acc[0].re[r] + acc[0].im[r] * acc[0].im[r];
-        // right-hand side of the correction: r_i - L_i c_{i-1}
-        if (i > 0) {
-          const cpx<double> zu = mk<double>(z.re - P.vu(i - 1), z.im);
-          cgemm_col<double, 1, MT>(acc, ARows<AGenCT<double>>{{P.Su(i - 1), P.Hu(i - 1), zu, -1.0, M}, 16 * ti},
-                                   BGlobF<double>{ZC + (size_t)(i - 1) * M * LD, LD}, tj);
-        }
-        tiles_foreach<double, 1>(acc, tj, [&](int row, int col, int, int r) {
-          YB[(16 * ti + row) * LD + col] = make_float2((float)acc[0].re[r], (float)acc[0].im[r]);
-        });
-      }
-      __syncthreads();
       float2* Ci = ZC + (size_t)i * M * LD;
 #pragma unroll 1
-      for (int p = w; p < npair; p += NWAVE) {
-        const int ti = p % MT, tj = colt(p / MT);
-        ctile<float> acc[1];
-        tzero(acc[0]);
-        cgemm_col<float, 1, MT>(acc, ARows<AGlob<float>>{{DI + (size_t)i * MM, M, 1.0f}, 16 * ti},
-                                BGlob<float>{YB, LD}, tj);
-        tiles_foreach<float, 1>(acc, tj, [&](int row, int col, int, int r) {
-          Ci[(16 * ti + row) * LD + col] = make_float2(acc[0].re[r], acc[0].im[r]);
-        });
+      for (int pass = 0; pass < npass; ++pass) {
+        int tj[TPP];
+        bool act[TPP];
+        ctile<double> acc[TPP][MT];
+#pragma unroll
+        for (int u = 0; u < TPP; ++u) {
+          const int q = (pass * TPP + u) * NWAVE + w;
+          act[u] = q < nc;
+          tj[u] = act[u] ? colt(q) : 0;
+          // b_i: W_L on the first slab (left injection), W_R on the last
+          const bool bL = act[u] && i == 0 && tj[u] >= MT, bR = act[u] && i == N - 1 && tj[u] < MT;
+          tiles_foreach<double, MT>(acc[u], tj[u], [&](int row, int col, int ti, int r) {
+            cpx<double> v = mk<double>(0.0, 0.0);
+            if (bL) v = ldd(WL + row * M + col - M);
+            if (bR) v = ldd(WR + row * M + col);
+            acc[u][ti].re[r] = v.re;
+            acc[u][ti].im[r] = v.im;
+          });
+        }
+#pragma unroll 1
+        for (int which = 0; which < 3; ++which) {
+          if ((which == 0 && i == N - 1) || (which == 2 && i == 0)) continue;
+          __syncthreads();                            // the previous block's readers are done
+          stage_neg_block<M>(stg, P, z, i, which, sL, sR);
+          __syncthreads();
+          const double2* Pb = Pi + (which == 0 ? (ptrdiff_t)M * LD : which == 2 ? -(ptrdiff_t)M * LD : 0);
+#pragma unroll
+          for (int u = 0; u < TPP; ++u)
+            if (act[u]) cgemm_col<double, MT, MT>(acc[u], ALds<double>{stg, S}, BGlob<double>{Pb, LD}, tj[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < TPP; ++u) {
+          if (!act[u]) continue;
+#pragma unroll
+          for (int ti = 0; ti < MT; ++ti)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              rr += acc[u][ti].re[r] * acc[u][ti].re[r] + acc[u][ti].im[r] * acc[u][ti].im[r];
+          tiles_foreach<double, MT>(acc[u], tj[u], [&](int row, int col, int ti, int r) {
+            YB[row * LD + col] = make_float2((float)acc[u][ti].re[r], (float)acc[u][ti].im[r]);
+          });
+        }
+        __threadfence_block();                        // YB tiles: written and read by this wave
+        // right-hand side of the correction, y_i = r_i - L_i c_{i-1}, in
+        // single precision (it only feeds the single-precision solve); -L_i
+        // is still staged
+        if (i > 0) {
+#pragma unroll
+          for (int u = 0; u < TPP; ++u) {
+            if (!act[u]) continue;
+            ctile<float> cf[MT];
+            tiles_foreach<float, MT>(cf, tj[u], [&](int row, int col, int ti, int r) {
+              const float2 v = YB[row * LD + col];
+              cf[ti].re[r] = v.x;
+              cf[ti].im[r] = v.y;
+            });
+            cgemm_col<float, MT, MT>(cf, ALdsF{stg, S}, BGlob<float>{Ci - (size_t)M * LD, LD}, tj[u]);
+            tiles_foreach<float, MT>(cf, tj[u], [&](int row, int col, int ti, int r) {
+              YB[row * LD + col] = make_float2(cf[ti].re[r], cf[ti].im[r]);
+            });
+          }
+          __threadfence_block();
+        }
+#pragma unroll
+        for (int u = 0; u < TPP; ++u) {
+          if (!act[u]) continue;
+          ctile<float> cf[MT];
+#pragma unroll
+          for (int ti = 0; ti < MT; ++ti) tzero(cf[ti]);
+          cgemm_col<float, MT, MT>(cf, AGlob<float>{DI + (size_t)i * MM, M, 1.0f}, BGlob<float>{YB, LD}, tj[u]);
+          tiles_foreach<float, MT>(cf, tj[u], [&](int row, int col, int ti, int r) {
+            Ci[row * LD + col] = make_float2(cf[ti].re[r], cf[ti].im[r]);
+          });
+        }
+        __threadfence_block();                        // c_i tiles: read by this wave at slab i + 1
       }
-      __syncthreads();
     }
     rr = block_sum(rr, red);
     prev = rel;
     rel = bb > 0.0 ? sqrt(rr / bb) : 0.0;
-    // uniform exits (NaN stops too): converged, out of steps, or a step
-    // that did not halve the residual (the single-precision factors are
-    // too inaccurate for this energy: the FP64 fallback takes over)
+    // uniform exits (NaN stops too): converged, out of steps, a step that
+    // did not halve the residual, or a contraction too slow to reach rtol
+    // in the steps left (the single-precision factors are too inaccurate
+    // for this energy: the FP64 fallback takes over)
     if (!(rel > a.rtol) || s == a.maxstep || (s > 0 && !(rel < 0.5 * prev))) break;
+    if (s > 0 && s + log(rel / a.rtol) / log(prev / rel) > a.maxstep + 0.5) break;
+#pragma unroll 1
     for (int i = N - 1; i >= 0; --i) {
       float2* Ci = ZC + (size_t)i * M * LD;
       double2* Pi = P64 + (size_t)i * M * LD;
 #pragma unroll 1
-      for (int p = w; p < npair; p += NWAVE) {
-        const int ti = p % MT, tj = colt(p / MT);
-        ctile<float> acc[1];
-        tiles_foreach<float, 1>(acc, tj, [&](int row, int col, int, int r) {
-          const float2 v = Ci[(16 * ti + row) * LD + col];
-          acc[0].re[r] = v.x;
-          acc[0].im[r] = v.y;
+      for (int q = w; q < nc; q += NWAVE) {
+        const int tj = colt(q);
+        ctile<float> acc[MT];
+        tiles_foreach<float, MT>(acc, tj, [&](int row, int col, int ti, int r) {
+          const float2 v = Ci[row * LD + col];
+          acc[ti].re[r] = v.x;
+          acc[ti].im[r] = v.y;
         });
         if (i < N - 1)
-          cgemm_col<float, 1, MT>(acc, ARows<AGlob<float>>{{XZ + (size_t)i * M * LD, LD, -1.0f}, 16 * ti},
-                                  BGlob<float>{Ci + (size_t)M * LD, LD}, tj);
-        // d_i replaces c_i: this tile of c_i is read by this wave only, and
-        // c_{i+1} is complete since the previous barrier
-        tiles_foreach<float, 1>(acc, tj, [&](int row, int col, int, int r) {
-          const unsigned idx = (16 * ti + row) * LD + col;
-          Ci[idx] = make_float2(acc[0].re[r], acc[0].im[r]);
+          cgemm_col<float, MT, MT>(acc, AGlob<float>{XZ + (size_t)i * M * LD, LD, -1.0f},
+                                   BGlob<float>{Ci + (size_t)M * LD, LD}, tj);
+        // d_i replaces c_i (read again by this wave only, at slab i - 1)
+        tiles_foreach<float, MT>(acc, tj, [&](int row, int col, int ti, int r) {
+          const unsigned idx = row * LD + col;
+          Ci[idx] = make_float2(acc[ti].re[r], acc[ti].im[r]);
           double2 v = Pi[idx];
-          v.x += (double)acc[0].re[r];
-          v.y += (double)acc[0].im[r];
+          v.x += (double)acc[ti].re[r];
+          v.y += (double)acc[ti].im[r];
           Pi[idx] = v;
         });
       }
-      __syncthreads();
+      __threadfence_block();
     }
   }
   *steps = s;
@@ -755,7 +1066,14 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(Prob P0, SweepArgs a, BatchDesc
   // M > 64: the working matrix and the staged coupling block live at the
   // end of the workgroup's global workspace (they do not fit in LDS)
   constexpr bool BIG = M > 64;
-  __shared__ cpx<R> mat_l[BIG ? 1 : M * S];
+  // the working matrix; during the mixed refinement (M <= 64) the FP64
+  // block staged for the residual products
+  constexpr int STG = (MIX && !BIG) ? M * S : 1;
+  __shared__ union {
+    cpx<R> m[BIG ? 1 : M * S];
+    cpx<double> stg[STG];
+  } lu;
+  cpx<R>* const mat_l = lu.m;
   __shared__ cpx<R> Ysc[gj_scratch<M>()];
   __shared__ BGJ<R, M> sc;
   __shared__ double tred[NWAVE];
@@ -1077,7 +1395,12 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(Prob P0, SweepArgs a, BatchDesc
     int steps = 0;
     double rel = 0.0;
     if constexpr (MIX) {
-      rel = refine<M>(P, a, sL, sR, WL, WR, z, hR, hL, (const float2*)XZ, DI, ZC, YB, P64, tred, &steps);
+      // M > 64: the staged FP64 block sits below the working matrix and
+      // the coupling block at the end of the workspace
+      cpx<double>* stg = lu.stg;
+      if constexpr (BIG) stg = (cpx<double>*)(wsb + a.ws_bytes - 2 * (size_t)M * S * sizeof(cpx<R>) -
+                                              (size_t)M * S * sizeof(cpx<double>));
+      rel = refine<M>(P, a, sL, sR, WL, WR, z, hR, hL, (const float2*)XZ, DI, ZC, YB, P64, stg, tred, &steps);
       // transmission and the heavy columns' densities from the refined solution
       {
         const double2* PN = P64 + (size_t)(N - 1) * M * LD;
@@ -1398,8 +1721,12 @@ template <int M>
 hipError_t launch_decimate(const Prob& P, const BatchDesc& b, const double* E, int nE, double eta, int sides,
                            const DecOpts& o, double2* scratch, int grid, double2* sig, double2* wf, double* sgn,
                            int* iters, int* nheavy, hipStream_t st) {
-  hipLaunchKernelGGL((k_decimate<M>), dim3(grid), dim3(NT), 0, st, P, b, E, nE, eta, sides, o.tol, o.rcond, o.maxit,
-                     o.heavy_tol, scratch, sig, wf, sgn, iters, nheavy);
+  hipLaunchKernelGGL((k_decimate<M>), dim3(grid), dim3(NT), 0, st, P, b, E, nE, eta, sides, o, scratch, sig, wf,
+                     sgn, iters, nheavy);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_sigma_finish<M>), dim3(grid), dim3(NT), 0, st, P, b, E, nE, eta, sides, o, scratch, sig, wf,
+                     sgn, nheavy);
   return hipGetLastError();
 }
 

@@ -6,7 +6,9 @@ broadening factors are refined against an FP64 residual and the energies
 whose refinement does not converge are re-solved in FP64.
 
 Tolerances: |dT| <= 1e-8 absolute per energy; slab densities
-|dn| <= 1e-8 * max(1, max_i |n_i|) per energy and contact.
+|dn| <= 1e-8 * max(1, max_i |n_i|) per energy and contact (single-energy
+densities reach 10^3 near resonances; the charge, summed over energies,
+is held to 1e-8 absolute against the oracle in test_gpu_charge.py).
 """
 import numpy as np
 import pytest
@@ -46,7 +48,7 @@ def test_mixed_cfg0(gpu_lib):
     Tref, Lref = oracle.solve_device(wl.device, wl.E, wl.eta)
     _check(T, L, Tref, Lref, "cfg0 mixed")
     assert np.all(info["refine_steps"] <= 3)
-    assert np.all(info["resid"] <= 1e-12) or np.any(info["fell_back_fp64"] == 1)
+    assert np.all((info["resid"] <= 3e-11) | (info["fell_back_fp64"] == 1))
 
 
 @pytest.mark.parametrize("case", small_cases.CASES, ids=lambda c: f"seed{c[0]}-N{c[1]}-m{c[2]}")

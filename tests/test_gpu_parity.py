@@ -1,8 +1,17 @@
 """GPU parity: the HIP path through the C ABI against the FP64 CPU oracle.
 
 Tolerances (FP64 path): |dT| <= 1e-10 absolute per energy; slab densities
-|dn| <= 1e-9 * max(1, max_i |n_i|) per energy and contact.  The inputs are
-the seeded synthetic workloads; the oracle runs live on the same arrays.
+|dn| <= 1e-9 * max(1, max_i |n_i|) per energy and contact, and where the
+densities stay moderate (the tiny workload, the small devices and the
+sampled N = 200, m = 64 energies) also |dn| <= 1e-8 absolute.  At a single
+energy the slab densities reach 300-450 states / eV / slab near resonances
+of these devices at eta = 1e-6, and there the oracle's own two elimination
+orders differ by up to 7.6e-9 (N = 200, m = 64) and 3.9e-8 (N = 400,
+m = 128) absolute (1e-10 relative), so an absolute per-energy bar below
+that is not one the oracle can certify; the charge, summed over energies
+with Fermi weights, is held to 1e-8 absolute in test_gpu_charge.py.  The
+inputs are the seeded synthetic workloads; the oracle runs live on the
+same arrays.
 """
 import numpy as np
 import pytest
@@ -18,20 +27,26 @@ pytestmark = pytest.mark.gpu
 
 TOL_T = 1e-10
 TOL_N = 1e-9
+TOL_N_ABS = 1e-8
 
 
 def _ctx(dev):
     return _lib.context_for(dev, 0)
 
 
-def _check(T, L, Tref, Lref, tolT=TOL_T, tolN=TOL_N, label=""):
+def _check(T, L, Tref, Lref, tolT=TOL_T, tolN=TOL_N, absN=None, label=""):
     dT = np.abs(T - Tref)
     scale = np.maximum(1.0, np.abs(Lref).max(axis=2))      # (nE, 2)
-    dn = (np.abs(L - Lref).max(axis=2) / scale)
+    dabs = np.abs(L - Lref).max(axis=2)
+    dn = dabs / scale
     worst = int(np.argmax(dT))
+    print(f"{label}: max|dT|={dT.max():.3e} max rel|dn|={dn.max():.3e} max abs|dn|={dabs.max():.3e} "
+          f"(max|n|={np.abs(Lref).max():.1f})")
     assert np.all(np.isfinite(T)) and np.all(np.isfinite(L)), label
     assert dT.max() <= tolT, f"{label} max|dT|={dT.max():.3e} at energy index {worst}"
     assert dn.max() <= tolN, f"{label} max rel|dn|={dn.max():.3e}"
+    if absN is not None:
+        assert dabs.max() <= absN, f"{label} max abs|dn|={dabs.max():.3e}"
     return dT.max(), dn.max()
 
 
@@ -60,7 +75,7 @@ def test_solve_cfg0_fp64(gpu_lib):
     T, L, info, st = ctx.solve(wl.E, wl.eta, _lib.FP64)
     assert st == _lib.OK
     Tref, Lref = oracle.solve_device(dev, wl.E, wl.eta)
-    _check(T, L, Tref, Lref, label="cfg0")
+    _check(T, L, Tref, Lref, absN=TOL_N_ABS, label="cfg0")
     assert np.all(info["flags"] == 0)
 
 
@@ -71,7 +86,7 @@ def test_solve_small_devices_fp64(gpu_lib, case):
     ctx = _lib.context_for(dev, 0)
     T, L, info, st = ctx.solve(E, small_cases.ETA, _lib.FP64)
     Tref, Lref = small_cases.reference(*case)
-    _check(T, L, Tref, Lref, label=f"seed{case[0]}")
+    _check(T, L, Tref, Lref, absN=TOL_N_ABS, label=f"seed{case[0]}")
 
 
 def test_cfg1_full_size_sampled(gpu_lib):
@@ -88,7 +103,7 @@ def test_cfg1_full_size_sampled(gpu_lib):
     rng = np.random.default_rng(1234)
     idx = np.sort(np.concatenate([[0, len(wl.E) - 1], rng.choice(len(wl.E), 10, replace=False)]))
     Tref, Lref = oracle.solve_device(dev, wl.E[idx], wl.eta)
-    _check(T[idx], L[idx], Tref, Lref, label="cfg1")
+    _check(T[idx], L[idx], Tref, Lref, absN=TOL_N_ABS, label="cfg1")
     assert np.all(info["dec_iters"] > 0)
 
 
@@ -156,8 +171,11 @@ def test_solve_device_on_a_torch_stream(gpu_lib):
 
 def test_cfg2_full_size_sampled(gpu_lib):
     """N = 400, m = 128 with its 4096 energies (band-edge set included) in one
-    FP64 call, as the benchmark runs it: every output finite, four energies
-    (two uniform, two within 1 meV of a band edge) against the oracle."""
+    FP64 call, as the benchmark runs it: every output finite, six energies
+    (two uniform, four within 1 meV of a band edge, among them the two
+    hardest of the set for the decimation) against the oracle at the fixed
+    bars.  The self-energies there rely on the Newton step after the
+    doublings (test_gpu_sigma_newton.py)."""
     import os
     edges = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "cfg2_band_edge_energies.txt"))
     wl = W.config2(band_edge_energies=edges)
@@ -166,22 +184,6 @@ def test_cfg2_full_size_sampled(gpu_lib):
     T, L, info, st = ctx.solve(wl.E, wl.eta, _lib.FP64)
     assert st == _lib.OK and np.all(np.isfinite(T)) and np.all(np.isfinite(L))
     n_uni = len(wl.E) - len(edges)
-    idx = np.array([7, n_uni - 100, n_uni + 11, len(wl.E) - 2])
+    idx = np.array([7, n_uni - 100, n_uni + 11, n_uni + 150, n_uni + 250, len(wl.E) - 2])
     Tref, Lref = oracle.solve_device(dev, wl.E[idx], wl.eta)
-    # Within 1 meV of a band edge a self-energy obtained by decimation is
-    # accurate only to ~1e-10 (fixed-point residual; the oracle's own
-    # LAPACK-based decimation shows it too), and the densities feel it
-    # directly.  The density tolerance per energy is therefore 1e-9, or ten
-    # times the deviation that the oracle's decimated self-energy causes at
-    # that energy, whichever is larger.
-    from oracle import decimation as odec
-    from oracle.observables import solve_energy
-    lead = (dev.lead_L.H00, dev.lead_L.H01, dev.lead_L.S00, dev.lead_L.S01)
-    for k, e in zip(range(len(idx)), wl.E[idx]):
-        dl, dr, _ = odec.decimate(float(e) + 1j * wl.eta, lead)
-        _, nl, nr = solve_energy(dev, float(e), wl.eta, sigma=(dl, dr))
-        scale = max(1.0, np.abs(Lref[k]).max())
-        dev_dec = max(np.abs(nl - Lref[k, 0]).max(), np.abs(nr - Lref[k, 1]).max()) / scale
-        tol_n = max(TOL_N, 10.0 * dev_dec)
-        _check(T[idx[k:k + 1]], L[idx[k:k + 1]], Tref[k:k + 1], Lref[k:k + 1], tolN=tol_n,
-               label=f"cfg2 energy {idx[k]} (density tolerance {tol_n:.1e})")
+    _check(T[idx], L[idx], Tref, Lref, label="cfg2")
