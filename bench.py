@@ -11,7 +11,10 @@ sweeps, transmission and slab densities.  Energies and outputs stay in HBM
 Prints ONE JSON line.  Both precisions are timed; `value` is the faster
 path whose transmission agrees with the FP64 path to |dT| <= 1e-8 on every
 energy of the grid (the FP64 path itself is held to 1e-10 of the CPU
-oracle by the parity tests).
+oracle by the parity tests).  Two more legs ride along unless
+--no-extra-legs: a short rate-scaled run of the serving workload (served
+energy-solves/s, p50/p99 request latency; top-level p99_latency_s) and the
+N = 400, m = 128 FP64 rate.
 """
 import argparse
 import hashlib
@@ -482,8 +485,8 @@ def bench_batch(args):
         if d.m not in tuned:
             sample = np.resize(E, min(items[d.m], 4096))
             tuned[d.m] = pr.autotune(sample, wl.eta, _lib.FP64)[0]
-    out["autotuned_workgroups_per_cu"] = {str(k): v for k, v in sorted(tuned.items())}
-    print(json.dumps({"autotuned": out["autotuned_workgroups_per_cu"]}), file=sys.stderr, flush=True)
+    out["autotuned_launch_shape"] = {str(k): v for k, v in sorted(tuned.items())}
+    print(json.dumps({"autotuned": out["autotuned_launch_shape"]}), file=sys.stderr, flush=True)
 
     for name, prec, steps, warmup in (("batch_fp64", _lib.FP64, args.steps, 1),
                                       ("batch_mixed", _lib.MIXED, 1, 0)):
@@ -555,6 +558,65 @@ def bench_serve(args):
     }))
 
 
+def serving_leg(precision_name="fp64", probe_seconds=10.0, seconds=20.0):
+    """A short run of the serving workload for the default benchmark line:
+    Poisson requests from the serving generator (pool of 8 lead sets,
+    N 50..400, m 32..128, 512..4096 lattice energies, right-lead bias),
+    continuous batching.  A saturated probe (the configured 200 req/s for
+    probe_seconds) measures capacity; then requests arrive at 80 % of it for
+    `seconds` and are drained (at most four times as long).  Returns served
+    energy-solves/s and the p50/p99 request latency of the rate-scaled run."""
+    from paper_1903_00548_amd import _lib, serve, workloads
+    pool = workloads.serving_lead_pool()
+    prec = _lib.FP64 if precision_name == "fp64" else _lib.MIXED
+
+    def make(reqs):
+        return [serve.Request(rid=k, t_arrival=q["t"], device=workloads.serving_device(q, pool), E=q["E"])
+                for k, q in enumerate(reqs)]
+
+    backend = serve.QtxBackend(0, eta=1e-6, precision=prec, want_ldos=True)
+    probe = workloads.serving_requests(rate=200.0, duration=probe_seconds)
+    srv = serve.Server(backend, hbm_budget=96 << 30, max_active=32, energies_per_step=512)
+    st0 = srv.run(make(probe), time_limit=probe_seconds)
+    mean_nE = float(np.mean([len(q["E"]) for q in probe]))
+    rate = 0.8 * st0["energy_solves_per_s"] / mean_nE
+    reqs = workloads.serving_requests(rate=rate, duration=seconds, seed=5)
+    srv = serve.Server(backend, hbm_budget=96 << 30, max_active=32, energies_per_step=512)
+    st = srv.run(make(reqs), time_limit=4 * seconds)
+    backend.ctx.close()
+    return {"precision": precision_name, "saturated_energy_solves_per_s": st0["energy_solves_per_s"],
+            "offered_rate_per_s": rate, "offered_requests": len(reqs), "completed": st["completed"],
+            "unfinished": st["unfinished"], "energy_solves_per_s": st["energy_solves_per_s"],
+            "p50_latency_s": st["p50_latency_s"], "p99_latency_s": st["p99_latency_s"],
+            "note": f"rate-scaled to 80 % of the saturated throughput, {seconds:.0f} s of arrivals; the "
+                    "configured 200 req/s offers ~100x one GPU's capacity (queueing only)"}
+
+
+def cfg2_fp64_leg():
+    """N = 400, m = 128, 4096 energies (256 within 1 meV of band edges), FP64
+    path, one timed grid after a 512-energy warm-up."""
+    import torch
+    from paper_1903_00548_amd import _lib, workloads
+    edges = np.loadtxt(os.path.join(ROOT, "tests", "golden", "cfg2_band_edge_energies.txt"))
+    wl = workloads.config2(band_edge_energies=edges)
+    dev = wl.device
+    nE = len(wl.E)
+    ctx = _lib.context_for(dev, 0)
+    ctx.set_stream(torch.cuda.current_stream().cuda_stream)
+    E_t = torch.tensor(wl.E, dtype=torch.float64, device="cuda")
+    T_t = torch.empty(nE, dtype=torch.float64, device="cuda")
+    L_t = torch.empty((nE, 2, dev.N), dtype=torch.float64, device="cuda")
+    I_t = torch.empty(nE * _lib.INFO_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+    ctx.solve_device(E_t.data_ptr(), 512, wl.eta, _lib.FP64, T_t.data_ptr(), L_t.data_ptr(), I_t.data_ptr())
+    torch.cuda.synchronize()
+    r = time_path(ctx, torch, E_t, T_t, L_t, I_t, wl.eta, _lib.FP64, 1, 0)
+    ctx.close()
+    n_dec = float(np.mean(r["info"]["dec_iters"]))
+    return {"workload": "cfg2_N400_m128_E4096", "energy_solves_per_s": nE / r["s"], "s_per_grid": r["s"],
+            "sweep_kernel_ms": r["sweep_ms"], "decimation_kernel_ms": r["dec_ms"],
+            "whole_solve_frac_of_fp64_peak": nE / r["s"] * flops_per_energy(dev.N, dev.m, n_dec) / 78.6e12}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -572,6 +634,8 @@ def main():
     ap.add_argument("--cfg2-fp64-only", action="store_true",
                     help="N=400, m=128 workload: time the FP64 path only (no mixed run, no comparison)")
     ap.add_argument("--serve-precision", choices=("fp64", "mixed"), default="fp64")
+    ap.add_argument("--no-extra-legs", action="store_true",
+                    help="headline workload only: skip the serving and N=400, m=128 legs")
     args = ap.parse_args()
     if args.workload == "bands":
         bench_bands(args)
@@ -685,6 +749,10 @@ def main():
     best = "mixed" if (ok_mixed and paths["mixed"]["energy_solves_per_s"] > paths["fp64"]["energy_solves_per_s"]) \
         else "fp64"
     p = paths[best]
+    extra = {}
+    if not args.no_extra_legs:
+        extra["serving"] = serving_leg("fp64")
+        extra["cfg2_fp64"] = cfg2_fp64_leg()
     out = {
         "metric": METRIC,
         "value": p["energy_solves_per_s"],
@@ -703,12 +771,16 @@ def main():
         "roofline": {"bound": "mfma", "achieved": p["sweep_tflops"], "peak": PEAK[best], "unit": "TFLOP/s",
                      "frac": p["sweep_tflops"] / PEAK[best],
                      "traffic": measured_traffic() if best == "fp64" else None,
-                     "kernel": "k_sweep (block forward/backward sweeps)"},
+                     "kernel": "k_sweep (block forward/backward sweeps)",
+                     "whole_solve_frac": p["whole_solve_frac_of_fp64_peak"]},
         "cpu_baseline": cpu,
         "mfma_counters": measured_mfma(),
         "paths": paths,
         "mixed_within_1e-8": ok_mixed,
+        **extra,
     }
+    if "serving" in extra:
+        out["p99_latency_s"] = extra["serving"]["p99_latency_s"]
     print(json.dumps(out))
 
 

@@ -257,14 +257,28 @@ qtx_status qtx_self_energy(qtx_ctx* ctx, const double* E, int nE, double eta,
  *                           correction does not halve the residual, or when
  *                           the contraction seen so far cannot reach
  *                           refine_tol in the corrections left);
- *   "refine_weight_tol"     [0, 1]        1e-8   QTX_MIXED: columns of the
+ *   "refine_weight_tol"     [0, 1]        0      QTX_MIXED: columns of the
  *                           broadening factor whose LDL^H pivot is at least
  *                           this times the largest are refined (whole tiles
  *                           of 16 columns, at least one tile per contact);
- *                           0 refines every column;
+ *                           0 refines every column (the light columns keep
+ *                           single-precision densities otherwise, which near
+ *                           resonances miss 1e-8 relative);
  *   "workgroups_per_cu"     [1, 4]        2      resident energies per CU for
  *                           blocks up to 64 (blocks of 96 and 128 use two
  *                           with QTX_FP64, one with QTX_MIXED); setting it
+ *                           discards autotuned values;
+ *   "panel_width"           0, 16 or 32   0      columns of a Gauss-Jordan panel
+ *                           in the sweeps' block inverse; 0 takes 16 up to
+ *                           padded blocks of 64 and 32 above; a width that
+ *                           does not divide the padded block falls back to
+ *                           that default.  It changes the order of the
+ *                           floating-point operations (results agree to
+ *                           rounding); setting it discards autotuned values;
+ *   "refine_tiles"          0, 1 or 2     0      QTX_MIXED: 16-column tiles a
+ *                           wave carries at once through the refinement at
+ *                           padded blocks 48 and 64 (0: 2; other blocks have
+ *                           one value); results do not change; setting it
  *                           discards autotuned values;
  *   "energies_per_launch"   [1, 2^20]     4096   energies per launch chunk;
  *   "sigma_cache_bytes"     [0, 1e13]     16 GiB qtx_solve_batch keeps the lead
@@ -344,19 +358,39 @@ qtx_status qtx_solve_batch(qtx_ctx* ctx, int nprob, qtx_ctx* const* probs,
                            const double* const* E, const int* nE, double eta,
                            qtx_precision prec, double* const* T, double* const* ldos);
 
-/* Autotuning of the launch shape for the context's problem: for every
- * number of resident workgroups per CU (one energy each) from 1 to 4 that
- * the kernels' register and LDS use allow at this block size, time the
- * solve of the sample energies E[nE] (host, eta, prec) and keep the
- * fastest.  The choice is stored for this block size and precision in the
- * context (and in its parent, for batched solves) and used by later
- * solves.  *wg_out (or NULL) receives it; times_ms[4] (or NULL) the
- * measured milliseconds per candidate (0 where a count was not possible).
- * Takes about twice the solve time of the sample per candidate.  The sweep
- * and decimation workspaces the timing allocated are released on return;
- * the next solve on the context allocates what it needs. */
+/* Launch configuration of the sweep kernels for one padded block size and
+ * precision: the autotuner's choice (qtx_autotune). */
+typedef struct {
+  int workgroups_per_cu;  /* resident energies per CU, 1..4 */
+  int panel_width;        /* columns of a Gauss-Jordan panel of the block
+                             inverse, 16 or 32 (dividing the padded block) */
+  int refine_tiles;       /* QTX_MIXED: 16-column tiles a wave carries at
+                             once through the refinement, 1 or 2 at padded
+                             blocks 48 and 64 (fixed otherwise) */
+} qtx_tune;
+
+#define QTX_TUNE_MAX_CANDIDATES 16
+
+/* Autotuning of the sweep's launch shape and tile shapes for the context's
+ * problem (the block elimination of Sec. "Extended states", eq.
+ * qtbm_system, as block sweeps).  Candidates: every built combination of
+ * panel width and refinement tiles at this block size, each with every
+ * number of resident workgroups per CU from 1 to 4 that its register and
+ * LDS use allow (mixed sweeps of blocks above 64: one).  Each candidate
+ * solves the sample energies E[nE] (host, eta, prec) once to warm up and
+ * three times timed with HIP events; the median decides.  The fastest is
+ * stored for this block size and precision in the context (and in its
+ * parent, for batched solves) and used by later solves.  The workgroup
+ * count and the refinement tiles never change a result; the panel width
+ * changes the rounding of the block inverses (results agree to the
+ * parity tolerances).  *best (or NULL) receives it; cand[] and times_ms[] (each
+ * QTX_TUNE_MAX_CANDIDATES long, or NULL) every candidate and its median
+ * milliseconds, *ncand (or NULL) their count.  Takes about four times the
+ * sample's solve time per candidate.  The sweep and decimation workspaces
+ * the timing allocated are released on return; the next solve on the
+ * context allocates what it needs. */
 qtx_status qtx_autotune(qtx_ctx* ctx, const double* E, int nE, double eta, qtx_precision prec,
-                        int* wg_out, double* times_ms);
+                        qtx_tune* best, qtx_tune* cand, double* times_ms, int* ncand);
 
 /* Self-energy cache of qtx_solve_batch (option "sigma_cache_bytes"):
  * contact lookups that found their entry (hits) and that had to run the

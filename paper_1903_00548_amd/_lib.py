@@ -27,6 +27,13 @@ class qtx_c128(ctypes.Structure):
     _fields_ = [("re", c_double), ("im", c_double)]
 
 
+class qtx_tune(ctypes.Structure):
+    _fields_ = [("workgroups_per_cu", c_int), ("panel_width", c_int), ("refine_tiles", c_int)]
+
+
+TUNE_MAX = 16
+
+
 class qtx_info(ctypes.Structure):
     _fields_ = [("dec_iters", c_int), ("refine_steps", c_int), ("resid", c_double),
                 ("fell_back_fp64", c_int), ("flags", c_int)]
@@ -58,7 +65,8 @@ _SIGS = {
     "qtx_set_option": (c_int, [c_void_p, c_char_p, c_double]),
     "qtx_sigma_cache_stats": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "qtx_bands": (c_int, [c_void_p, c_int, c_void_p, c_int, c_void_p]),
-    "qtx_autotune": (c_int, [c_void_p, c_void_p, c_int, c_double, c_int, c_void_p, c_void_p]),
+    "qtx_autotune": (c_int, [c_void_p, c_void_p, c_int, c_double, c_int, c_void_p, c_void_p, c_void_p,
+                             c_void_p]),
     "qtx_solve_batch": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_double, c_int,
                                 c_void_p, c_void_p]),
     "qtx_density_matrix": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_double, c_void_p, c_void_p,
@@ -243,14 +251,21 @@ class Context:
         self._check(self.lib.qtx_set_option(self.h, name.encode(), float(value)))
 
     def autotune(self, E, eta, precision=FP64):
-        """Pick the workgroups per CU for this problem from timed solves of
-        the sample energies; returns (chosen, times_ms[4])."""
+        """Pick the sweep's launch and tile shapes for this problem from
+        timed solves of the sample energies (median of three per
+        candidate).  Returns (best, candidates, times_ms): best and each
+        candidate a dict with workgroups_per_cu, panel_width and
+        refine_tiles."""
         E = np.ascontiguousarray(E, dtype=np.float64)
-        wg = c_int()
-        times = np.zeros(4)
-        self._check(self.lib.qtx_autotune(self.h, _ptr(E), len(E), float(eta), int(precision), ctypes.byref(wg),
-                                          _ptr(times)))
-        return wg.value, times
+        best = qtx_tune()
+        cand = (qtx_tune * TUNE_MAX)()
+        times = np.zeros(TUNE_MAX)
+        n = c_int()
+        self._check(self.lib.qtx_autotune(self.h, _ptr(E), len(E), float(eta), int(precision), ctypes.byref(best),
+                                          cand, _ptr(times), ctypes.byref(n)))
+        as_dict = lambda t: {"workgroups_per_cu": t.workgroups_per_cu, "panel_width": t.panel_width,
+                             "refine_tiles": t.refine_tiles}
+        return as_dict(best), [as_dict(cand[k]) for k in range(n.value)], times[:n.value].copy()
 
     def bands(self, side, k):
         """Band energies E_n(k) + V_lead of one lead, shape (len(k), m)."""

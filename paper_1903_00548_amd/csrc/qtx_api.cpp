@@ -122,11 +122,13 @@ struct qtx_ctx {
   int dec_maxit = 60;
   int chunk = 4096;
   int wg_per_cu = 2;
+  int opt_pw = 0;                 // Gauss-Jordan panel width (0: default per block size)
+  int opt_tpp = 0;                // mixed refinement tiles per wave (0: default per block size)
   double refine_tol = 3e-11;      // stop when ||r|| <= refine_tol ||b||
   int refine_max = 3;             // corrections per energy before the FP64 fallback
-  double heavy_tol = 1e-8;        // refine columns with pivot >= heavy_tol * largest
+  double heavy_tol = 0.0;         // refine columns with pivot >= heavy_tol * largest (0: all)
   double newton_tol = 3e-11;      // Newton step on a self-energy whose fixed-point residual exceeds this
-  std::map<int, int> tuned_wg[2];  // autotuned workgroups per CU by block size (FP64, mixed)
+  std::map<int, qtx_tune> tuned[2];  // autotuned launch shape by block size (FP64, mixed)
 };
 
 namespace {
@@ -203,10 +205,28 @@ qtx_status check_ready(qtx_ctx* c) {
 // workspace (0.3-0.5 GB per workgroup at N = 400) would otherwise crowd the
 // self-energy cache and the batch buffers out of device memory.
 int wgs_per_cu(const qtx_ctx* c, int M, bool mixed) {
-  auto it = c->tuned_wg[mixed].find(M);
-  if (it != c->tuned_wg[mixed].end()) return it->second;
+  auto it = c->tuned[mixed].find(M);
+  if (it != c->tuned[mixed].end()) return it->second.workgroups_per_cu;
   if (M > 64) return mixed ? 1 : 2;
   return c->wg_per_cu;
+}
+
+// Launch shape of the sweeps at block size M: the autotuned one, else the
+// default workgroups per CU with the tile shapes of the options panel_width
+// and refine_tiles where the block size allows them, else the defaults.
+qtx_tune tune_of(const qtx_ctx* c, int M, bool mixed) {
+  auto it = c->tuned[mixed].find(M);
+  if (it != c->tuned[mixed].end()) return it->second;
+  qtx_tune t{wgs_per_cu(c, M, mixed), qtx::sweep_default_pw(M), qtx::sweep_default_tpp(M)};
+  if (c->opt_pw && qtx::sweep_variant_ok(M, mixed, c->opt_pw, t.refine_tiles)) t.panel_width = c->opt_pw;
+  if (c->opt_tpp && qtx::sweep_variant_ok(M, mixed, t.panel_width, c->opt_tpp)) t.refine_tiles = c->opt_tpp;
+  return t;
+}
+
+hipError_t sweep_launch(const qtx_ctx* c, int M, bool mixed, const qtx::Prob& P, const qtx::SweepArgs& a,
+                        const qtx::BatchDesc& b, int grid) {
+  const qtx_tune t = tune_of(c, M, mixed);
+  return qtx::run_sweep(M, mixed, t.panel_width, t.refine_tiles, P, a, b, grid, c->stream);
 }
 
 // Resident workgroups of a sweep launch over `items` energies of block size
@@ -372,7 +392,7 @@ qtx_status enqueue_chunk(qtx_ctx* c, const double* E_dev, int ne, double eta, bo
   a.rtol = c->refine_tol;
   a.maxstep = c->refine_max;
   QTX_HIP(c, record(c, c->ev_sw, c->n_sw));
-  QTX_HIP(c, qtx::run_sweep(c->M, mixed, P, a, qtx::BatchDesc{}, b.grid, c->stream));
+  QTX_HIP(c, sweep_launch(c, c->M, mixed, P, a, qtx::BatchDesc{}, b.grid));
   if (mixed) {
     // energies whose refinement did not converge: FP64 sweep on the list
     QTX_HIP(c, qtx::run_compact(b.redo, ne, b.elist, b.ecount, c->stream));
@@ -380,7 +400,7 @@ qtx_status enqueue_chunk(qtx_ctx* c, const double* E_dev, int ne, double eta, bo
     f.elist = b.elist;
     f.ecount = b.ecount;
     f.redo = nullptr;
-    QTX_HIP(c, qtx::run_sweep(c->M, false, P, f, qtx::BatchDesc{}, b.grid, c->stream));
+    QTX_HIP(c, sweep_launch(c, c->M, false, P, f, qtx::BatchDesc{}, b.grid));
   }
   QTX_HIP(c, record(c, c->ev_sw, c->n_sw));
   return QTX_OK;
@@ -998,8 +1018,8 @@ qtx_status qtx_set_option(qtx_ctx* c, const char* name, double value) {
   } else if (n == "workgroups_per_cu") {
     if (!integral || value < 1 || value > 4) return fail(c, QTX_EINVAL, "workgroups_per_cu must be in [1, 4]");
     c->wg_per_cu = (int)value;
-    c->tuned_wg[0].clear();
-    c->tuned_wg[1].clear();
+    c->tuned[0].clear();
+    c->tuned[1].clear();
   } else if (n == "sigma_cache_bytes") {
     if (!(value >= 0.0 && value <= 1e13)) return fail(c, QTX_EINVAL, "sigma_cache_bytes must be in [0, 1e13]");
     c->sigcache_bytes = value;
@@ -1025,6 +1045,16 @@ qtx_status qtx_set_option(qtx_ctx* c, const char* name, double value) {
   } else if (n == "mode_tol") {
     if (!(value > 0.0 && value <= 1e-2)) return fail(c, QTX_EINVAL, "mode_tol must be in (0, 1e-2]");
     c->mode_tol = value;
+  } else if (n == "panel_width") {
+    if (!(value == 0.0 || value == 16.0 || value == 32.0)) return fail(c, QTX_EINVAL, "panel_width must be 0, 16 or 32");
+    c->opt_pw = (int)value;
+    c->tuned[0].clear();
+    c->tuned[1].clear();
+  } else if (n == "refine_tiles") {
+    if (!(value == 0.0 || value == 1.0 || value == 2.0)) return fail(c, QTX_EINVAL, "refine_tiles must be 0, 1 or 2");
+    c->opt_tpp = (int)value;
+    c->tuned[0].clear();
+    c->tuned[1].clear();
   } else if (n == "energies_per_launch") {
     if (!integral || value < 1 || value > (1 << 20)) return fail(c, QTX_EINVAL, "energies_per_launch must be in [1, 2^20]");
     c->chunk = (int)value;
@@ -1045,8 +1075,10 @@ qtx_status qtx_problem_create(qtx_ctx* parent, qtx_ctx** problem) {
   c->dec_maxit = parent->dec_maxit;
   c->chunk = parent->chunk;
   c->wg_per_cu = parent->wg_per_cu;
-  c->tuned_wg[0] = parent->tuned_wg[0];
-  c->tuned_wg[1] = parent->tuned_wg[1];
+  c->opt_pw = parent->opt_pw;
+  c->opt_tpp = parent->opt_tpp;
+  c->tuned[0] = parent->tuned[0];
+  c->tuned[1] = parent->tuned[1];
   c->refine_tol = parent->refine_tol;
   c->refine_max = parent->refine_max;
   c->heavy_tol = parent->heavy_tol;
@@ -1161,14 +1193,14 @@ qtx_status enqueue_batch(qtx_ctx* c, const std::vector<BatchChunk>& chunks, cons
     a.redo = mixed ? c->redo.as<int>() : nullptr;
     a.rtol = c->refine_tol;
     a.maxstep = c->refine_max;
-    QTX_HIP(c, qtx::run_sweep(M, mixed, P0, a, b, grid, c->stream));
+    QTX_HIP(c, sweep_launch(c, M, mixed, P0, a, b, grid));
     if (mixed) {
       QTX_HIP(c, qtx::run_compact(c->redo.as<int>(), k.nitems, c->elist.as<int>(), c->ecount.as<int>(), c->stream));
       qtx::SweepArgs f = a;
       f.elist = c->elist.as<int>();
       f.ecount = c->ecount.as<int>();
       f.redo = nullptr;
-      QTX_HIP(c, qtx::run_sweep(M, false, P0, f, b, grid, c->stream));
+      QTX_HIP(c, sweep_launch(c, M, false, P0, f, b, grid));
     }
   }
   return QTX_OK;
@@ -1456,7 +1488,11 @@ qtx_status qtx_solve_batch(qtx_ctx* c, int nprob, qtx_ctx* const* probs, const d
   std::vector<long long> sig;
   sig.push_back(mixed);
   sig.push_back(c->wg_per_cu);
-  for (const BatchChunk& k : chunks) sig.push_back(wgs_per_cu(c, k.M, mixed));
+  for (const BatchChunk& k : chunks)
+    for (bool mx : {mixed, false}) {
+      const qtx_tune t = tune_of(c, k.M, mx);
+      for (int v : {t.workgroups_per_cu, t.panel_width, t.refine_tiles}) sig.push_back(v);
+    }
   sig.push_back(c->chunk);
   sig.push_back(c->refine_max);
   long long eb;
@@ -1537,8 +1573,8 @@ qtx_status qtx_solve_batch(qtx_ctx* c, int nprob, qtx_ctx* const* probs, const d
   return QTX_OK;
 }
 
-qtx_status qtx_autotune(qtx_ctx* c, const double* E, int nE, double eta, qtx_precision prec, int* wg_out,
-                        double* times_ms) {
+qtx_status qtx_autotune(qtx_ctx* c, const double* E, int nE, double eta, qtx_precision prec, qtx_tune* best_out,
+                        qtx_tune* cand_out, double* times_ms, int* ncand_out) {
   if (!c) return QTX_EINVAL;
   if (prec != QTX_FP64 && prec != QTX_MIXED) return fail(c, QTX_EINVAL, "precision must be QTX_FP64 or QTX_MIXED");
   if (nE < 1 || !E) return fail(c, QTX_EINVAL, "need at least one sample energy");
@@ -1550,11 +1586,19 @@ qtx_status qtx_autotune(qtx_ctx* c, const double* E, int nE, double eta, qtx_pre
   QTX_HIP(c, hipSetDevice(c->device));
   const bool mixed = prec == QTX_MIXED;
   const int M = c->M, N = c->N;
-  int occ_sweep = 0, occ_dec = 0;
-  QTX_HIP(c, qtx::max_resident(M, mixed, &occ_sweep, &occ_dec));
-  // mixed sweeps above 64 keep one workgroup per CU: their workspace (0.3-0.5
-  // GB per workgroup at N = 400) bounds the count
-  const int cand = std::max(1, std::min(M > 64 && mixed ? 1 : 4, occ_sweep));
+  // candidates: every built tile shape, with every workgroup count from 1 to
+  // what the kernel's registers and LDS allow (at most 4; mixed sweeps above
+  // 64 keep one: their workspace of 0.3-0.5 GB per workgroup at N = 400
+  // bounds the count)
+  std::vector<qtx_tune> cand;
+  for (int pw : {16, 32})
+    for (int tpp : {1, 2}) {
+      if (!qtx::sweep_variant_ok(M, mixed, pw, tpp)) continue;
+      int occ_sweep = 0, occ_dec = 0;
+      QTX_HIP(c, qtx::max_resident(M, mixed, pw, tpp, &occ_sweep, &occ_dec));
+      const int top = std::max(1, std::min(M > 64 && mixed ? 1 : 4, occ_sweep));
+      for (int wg = 1; wg <= top; ++wg) cand.push_back(qtx_tune{wg, pw, tpp});
+    }
   QTX_HIP(c, c->wE.ensure((size_t)nE * sizeof(double)));
   QTX_HIP(c, c->wT.ensure((size_t)nE * sizeof(double)));
   QTX_HIP(c, c->wldos.ensure((size_t)nE * 2 * N * sizeof(double)));
@@ -1564,33 +1608,32 @@ qtx_status qtx_autotune(qtx_ctx* c, const double* E, int nE, double eta, qtx_pre
   QTX_HIP(c, hipEventCreate(&e1));
   const bool timing = c->timing;
   c->timing = false;
-  double best = 1e300;
-  int best_wg = 1;
+  const bool had = c->tuned[mixed].count(M) > 0;
+  const qtx_tune before = had ? c->tuned[mixed][M] : qtx_tune{};
+  std::vector<double> med(cand.size(), 0.0);
+  size_t best = 0;
   qtx_status st = QTX_OK;
-  for (int wg = 1; wg <= 4; ++wg) {
-    if (times_ms) times_ms[wg - 1] = 0.0;
-    if (wg > cand) continue;
-    c->tuned_wg[mixed][M] = wg;
-    // once to allocate, once timed
-    for (int rep = 0; rep < 2 && st == QTX_OK; ++rep) {
-      if (rep == 1 && hipEventRecord(e0, c->stream) != hipSuccess) st = fail(c, QTX_EDEVICE, "hipEventRecord");
+  for (size_t k = 0; k < cand.size() && st == QTX_OK; ++k) {
+    c->tuned[mixed][M] = cand[k];
+    // one solve to allocate and warm up, then the median of three timed ones
+    double t[3];
+    for (int rep = 0; rep < 4 && st == QTX_OK; ++rep) {
+      if (rep > 0 && hipEventRecord(e0, c->stream) != hipSuccess) st = fail(c, QTX_EDEVICE, "hipEventRecord");
       if (st == QTX_OK)
         st = solve_device_core(c, c->wE.as<double>(), nE, eta, prec, c->wT.as<double>(), c->wldos.as<double>(),
                                nullptr);
-      if (st == QTX_OK && rep == 1 && hipEventRecord(e1, c->stream) != hipSuccess)
-        st = fail(c, QTX_EDEVICE, "hipEventRecord");
+      if (st == QTX_OK && rep > 0) {
+        float ms = 0.0f;
+        if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+          st = fail(c, QTX_EDEVICE, "event timing failed");
+        t[rep - 1] = ms;
+      }
     }
     if (st != QTX_OK) break;
-    float ms = 0.0f;
-    if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-      st = fail(c, QTX_EDEVICE, "event timing failed");
-      break;
-    }
-    if (times_ms) times_ms[wg - 1] = ms;
-    if (ms < best) {
-      best = ms;
-      best_wg = wg;
-    }
+    std::sort(t, t + 3);
+    med[k] = t[1];
+    if (med[k] < med[best]) best = k;
   }
   c->timing = timing;
   (void)hipEventDestroy(e0);
@@ -1602,12 +1645,19 @@ qtx_status qtx_autotune(qtx_ctx* c, const double* E, int nE, double eta, qtx_pre
   c->sws.release();
   c->dscr.release();
   if (st != QTX_OK) {
-    c->tuned_wg[mixed].erase(M);
+    if (had) c->tuned[mixed][M] = before;
+    else c->tuned[mixed].erase(M);
     return st;
   }
-  c->tuned_wg[mixed][M] = best_wg;
-  if (c->parent) c->parent->tuned_wg[mixed][M] = best_wg;
-  if (wg_out) *wg_out = best_wg;
+  c->tuned[mixed][M] = cand[best];
+  if (c->parent) c->parent->tuned[mixed][M] = cand[best];
+  if (best_out) *best_out = cand[best];
+  const int n = (int)std::min<size_t>(cand.size(), QTX_TUNE_MAX_CANDIDATES);
+  for (int k = 0; k < n; ++k) {
+    if (cand_out) cand_out[k] = cand[k];
+    if (times_ms) times_ms[k] = med[k];
+  }
+  if (ncand_out) *ncand_out = n;
   return QTX_OK;
 }
 

@@ -151,10 +151,20 @@ hipError_t run_decimate(int M, const Prob& P, const BatchDesc& b, const double* 
                         const DecOpts& o, double2* scratch, int grid, double2* sig, double2* wf, double* sgn,
                         int* iters, int* nheavy, hipStream_t st);
 
+// Tile shapes of the sweeps (the autotuner's choices): pw, the columns of
+// a Gauss-Jordan panel (16 or 32, dividing M; by default 16 up to M = 64,
+// 32 above); tpp, the column tiles a wave carries at once through the mixed
+// refinement (1 or 2 at M = 48 and 64, by default 2; 2 below 48 and 1 above
+// 64 are the only values).
+constexpr int sweep_default_pw(int M) { return M > 64 ? 32 : 16; }
+constexpr int sweep_default_tpp(int M) { return M <= 64 ? 2 : 1; }
+bool sweep_variant_ok(int M, bool mixed, int pw, int tpp);
+
 // mixed = false: FP64 sweep (with a.elist: re-solve of the listed energies).
-// mixed = true: FP32 sweep plus refinement of the heavy columns.
-hipError_t run_sweep(int M, bool mixed, const Prob& P, const SweepArgs& a, const BatchDesc& b, int grid,
-                     hipStream_t st);
+// mixed = true: FP32 sweep plus refinement of the heavy columns.  pw, tpp:
+// the tile shapes above (hipErrorInvalidValue if not a built variant).
+hipError_t run_sweep(int M, bool mixed, int pw, int tpp, const Prob& P, const SweepArgs& a, const BatchDesc& b,
+                     int grid, hipStream_t st);
 
 // FP64 sweep that also accumulates the density-matrix blocks (a.dmw,
 // a.rho, a.rho_stride, a.rho_first; workspace sweep_ws_bytes(N, M, false,
@@ -198,10 +208,10 @@ hipError_t noalloc_scratch(int device, char** ptr);
 hipError_t run_bands(int M, const double2* lead, int m, double V, const double* k, int nk, double2* work, int grid,
                      double* E, hipStream_t st);
 
-// Workgroups of the sweep (FP64 or mixed), of the decimation and (dm_wgs
-// non-null) of the density-matrix sweep that one CU can hold at block size
-// M, from the kernels' register and LDS use.
-hipError_t max_resident(int M, bool mixed, int* sweep_wgs, int* dec_wgs, int* dm_wgs = nullptr);
+// Workgroups of the sweep (FP64 or mixed, tile shapes pw and tpp), of the
+// decimation and (dm_wgs non-null) of the density-matrix sweep that one CU
+// can hold at block size M, from the kernels' register and LDS use.
+hipError_t max_resident(int M, bool mixed, int pw, int tpp, int* sweep_wgs, int* dec_wgs, int* dm_wgs = nullptr);
 
 // elist[0 .. *ecount) = the energies e < nE with redo[e] != 0 (one wave).
 hipError_t run_compact(const int* redo, int nE, int* elist, int* ecount, hipStream_t st);

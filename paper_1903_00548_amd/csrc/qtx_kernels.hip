@@ -31,14 +31,13 @@ template <typename R, int M> struct BGJ {
 // is in LDS; 32 when it lives in global memory (M > 64), which halves the
 // read-modify-write passes of the trailing update over the matrix and
 // doubles the MFMA work per tile loaded.
-template <int M> constexpr int gj_pw() { return M > 64 ? 32 : 16; }
+template <int M> constexpr int gj_pw() { return sweep_default_pw(M); }
 
 // LDS scratch (complex elements) that gj_inverse needs beside the matrix:
 // the compacted pivot rows of the panel update, and during the panel the
 // double-buffered row multipliers.
-template <int M> constexpr int gj_scratch() {
-  return gj_pw<M>() * (M - gj_pw<M>()) > 2 * 64 * ((M + 63) / 64) ? gj_pw<M>() * (M - gj_pw<M>())
-                                                                    : 2 * 64 * ((M + 63) / 64);
+template <int M, int PW = gj_pw<M>()> constexpr int gj_scratch() {
+  return PW * (M - PW) > 2 * 64 * ((M + 63) / 64) ? PW * (M - PW) : 2 * 64 * ((M + 63) / 64);
 }
 
 // Elimination of panel k (columns PW k .. PW k + PW - 1, PW = gj_pw<M>())
@@ -53,10 +52,10 @@ template <int M> constexpr int gj_scratch() {
 //   x_rj <- -m_r.
 // The multipliers alternate between two LDS buffers, so that one barrier
 // per step orders both the publication and the reuse.
-template <typename R, int M>
+template <typename R, int M, int PW>
 __device__ __forceinline__ void gj_panel(cpx<R>* mat, int S, int k, BGJ<R, M>& sc, cpx<R>* mb) {
   constexpr int RL = (M + 63) / 64;             // rows per lane
-  constexpr int PW = gj_pw<M>(), CW = PW / NWAVE;
+  constexpr int CW = PW / NWAVE;
   static_assert(M <= 128, "pivot keys carry 8-bit row indices");
   const int lane = lane_id(), w = threadIdx.x >> 6;
   const int c0 = PW * k + CW * w;
@@ -142,9 +141,9 @@ __device__ __forceinline__ void gj_panel(cpx<R>* mat, int S, int k, BGJ<R, M>& s
 // waves; each wave runs its tiles in groups of at most four through one
 // interleaved MFMA loop, so that up to eight accumulator chains are in
 // flight.  A group's surplus slots recompute a valid tile and do not store.
-template <typename R, int M>
+template <typename R, int M, int PW>
 __device__ __forceinline__ void gj_update(cpx<R>* mat, int S, int k, const cpx<R>* Y, const BGJ<R, M>& sc) {
-  constexpr int PW = gj_pw<M>(), PT = PW / 16;
+  constexpr int PT = PW / 16;
   constexpr int MT = M / 16, NTILE = MT * (MT - PT), TPW = (NTILE + NWAVE - 1) / NWAVE, WY = M - PW;
   constexpr int GRP = TPW < 4 ? TPW : 4;
   if constexpr (NTILE > 0) {
@@ -209,15 +208,17 @@ __device__ __forceinline__ void gj_update(cpx<R>* mat, int S, int k, const cpx<R
 // Ends with a barrier.  The elimination is the latency-bound critical path
 // of its workgroup, so its waves raise their issue priority over the other
 // workgroup resident on the CU (which is then mostly in MFMA phases).
-template <typename R, int M>
+template <typename R, int M, int PW = gj_pw<M>()>
 __device__ __forceinline__ void gj_inverse(cpx<R>* mat, int S, cpx<R>* Y, BGJ<R, M>& sc) {
-  constexpr int PW = gj_pw<M>(), NP = M / PW;
+  static_assert(PW == 16 || PW == 32, "panels of 16 or 32 columns");
+  static_assert(M % PW == 0, "whole panels");
+  constexpr int NP = M / PW;
   const int t = threadIdx.x;
   __builtin_amdgcn_s_setprio(2);
   if (t < M) sc.ppanel[t] = -1;
   __syncthreads();
   for (int k = 0; k < NP; ++k) {
-    gj_panel<R, M>(mat, S, k, sc, Y);
+    gj_panel<R, M, PW>(mat, S, k, sc, Y);
     __syncthreads();
     // pivot rows of the columns outside the panel, compacted (PW x (M-PW));
     // a single panel (M = PW) leaves nothing to update
@@ -229,7 +230,7 @@ __device__ __forceinline__ void gj_inverse(cpx<R>* mat, int S, cpx<R>* Y, BGJ<R,
         Y[idx] = mat[sc.piv[PW * k + jj] * S + c];
       }
       __syncthreads();
-      gj_update<R, M>(mat, S, k, Y, sc);
+      gj_update<R, M, PW>(mat, S, k, Y, sc);
       __syncthreads();
     }
   }
@@ -884,13 +885,12 @@ __device__ __forceinline__ void stage_neg_block(cpx<double>* stg, const Prob& P,
 // the wave: the forward pass takes barriers only around the stagings, the
 // backward pass none.  Returns the last relative residual; *steps receives
 // the corrections applied.
-template <int M>
+template <int M, int TPP>
 __device__ __forceinline__ double refine(const Prob& P, const SweepArgs& a, const double2* sL, const double2* sR,
                                          const double2* WL, const double2* WR, cpx<double> z, int hR, int hL,
                                          const float2* XZ, const float2* DI, float2* ZC, float2* YB, double2* P64,
                                          cpx<double>* stg, double* red, int* steps) {
   constexpr int MT = M / 16, MM = M * M, LD = 2 * M, S = M + 1;
-  constexpr int TPP = M <= 64 ? 2 : 1;              // column tiles per wave and pass
   const int N = P.N, w = threadIdx.x >> 6;
   const int nc = hR + hL;
   const int npass = (nc + NWAVE * TPP - 1) / (NWAVE * TPP);
@@ -1058,7 +1058,7 @@ __device__ __forceinline__ double refine(const Prob& P, const SweepArgs& a, cons
 // registers at 256 per lane, and the FP64 sweep spills about 100 bytes per
 // lane at M = 128.  A second wave per SIMD issues MFMAs while the first
 // waits on its operands in L2, which more than pays for the spill.
-template <typename R, int M, bool MIX, bool DM>
+template <typename R, int M, bool MIX, bool DM, int PW = gj_pw<M>(), int TPP = (M <= 64 ? 2 : 1)>
 __global__ __launch_bounds__(NT, 2) void k_sweep(Prob P0, SweepArgs a, BatchDesc b) {
   static_assert(!DM || (!MIX && sizeof(R) == 8), "density-matrix blocks come from the FP64 sweep");
   typedef typename vec2t<R>::type V2;
@@ -1074,7 +1074,7 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(Prob P0, SweepArgs a, BatchDesc
     cpx<double> stg[STG];
   } lu;
   cpx<R>* const mat_l = lu.m;
-  __shared__ cpx<R> Ysc[gj_scratch<M>()];
+  __shared__ cpx<R> Ysc[gj_scratch<M, PW>()];
   __shared__ BGJ<R, M> sc;
   __shared__ double tred[NWAVE];
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
@@ -1230,7 +1230,7 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(Prob P0, SweepArgs a, BatchDesc
         }
       }
       __syncthreads();
-      gj_inverse<R, M>(mat, S, Ysc, sc);
+      gj_inverse<R, M, PW>(mat, S, Ysc, sc);
       if constexpr (MIX) {
         // Dt_i^-1[j][c] = mat[piv[j]][pinv[c]]
         float2* Di = DI + (size_t)i * MM;
@@ -1400,7 +1400,7 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(Prob P0, SweepArgs a, BatchDesc
       cpx<double>* stg = lu.stg;
       if constexpr (BIG) stg = (cpx<double>*)(wsb + a.ws_bytes - 2 * (size_t)M * S * sizeof(cpx<R>) -
                                               (size_t)M * S * sizeof(cpx<double>));
-      rel = refine<M>(P, a, sL, sR, WL, WR, z, hR, hL, (const float2*)XZ, DI, ZC, YB, P64, stg, tred, &steps);
+      rel = refine<M, TPP>(P, a, sL, sR, WL, WR, z, hR, hL, (const float2*)XZ, DI, ZC, YB, P64, stg, tred, &steps);
       // transmission and the heavy columns' densities from the refined solution
       {
         const double2* PN = P64 + (size_t)(N - 1) * M * LD;
@@ -1730,9 +1730,9 @@ hipError_t launch_decimate(const Prob& P, const BatchDesc& b, const double* E, i
   return hipGetLastError();
 }
 
-template <typename R, int M, bool MIX, bool DM = false>
+template <typename R, int M, bool MIX, bool DM = false, int PW = gj_pw<M>(), int TPP = (M <= 64 ? 2 : 1)>
 hipError_t launch_sweep(const Prob& P, const SweepArgs& a, const BatchDesc& b, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((k_sweep<R, M, MIX, DM>), dim3(grid), dim3(NT), 0, st, P, a, b);
+  hipLaunchKernelGGL((k_sweep<R, M, MIX, DM, PW, TPP>), dim3(grid), dim3(NT), 0, st, P, a, b);
   return hipGetLastError();
 }
 
@@ -1753,20 +1753,54 @@ hipError_t run_decimate(int M, const Prob& P, const BatchDesc& b, const double* 
 #undef QTX_DEC
 }
 
-hipError_t run_sweep(int M, bool mixed, const Prob& P, const SweepArgs& a, const BatchDesc& b, int grid,
-                     hipStream_t st) {
-#define QTX_SWEEP(MM) \
-  return mixed ? launch_sweep<float, MM, true>(P, a, b, grid, st) : launch_sweep<double, MM, false>(P, a, b, grid, st)
+// Whether (panel width, refinement tiles per wave) is a built variant for
+// block size M: panels of 16 or 32 columns that divide M, and one or two
+// column tiles per wave in the mixed refinement for blocks of 48 and 64
+// (smaller blocks have at most one tile per wave, larger ones one).
+bool sweep_variant_ok(int M, bool mixed, int pw, int tpp) {
+  if (pw != 16 && pw != 32) return false;
+  if (M % pw != 0) return false;
+  if (!mixed) return tpp == sweep_default_tpp(M);
+  if (M == 48 || M == 64) return tpp == 1 || tpp == 2;
+  return tpp == sweep_default_tpp(M);
+}
+
+// Dispatch over the built variants; an invalid combination returns
+// hipErrorInvalidValue.
+template <int M>
+hipError_t sweep_dispatch(bool mixed, int pw, int tpp, const Prob& P, const SweepArgs& a, const BatchDesc& b, int grid,
+                          hipStream_t st) {
+  if (!sweep_variant_ok(M, mixed, pw, tpp)) return hipErrorInvalidValue;
+  constexpr int D = M <= 64 ? 2 : 1;
+  if (!mixed) {
+    if constexpr (M % 32 == 0)
+      if (pw == 32) return launch_sweep<double, M, false, false, 32, D>(P, a, b, grid, st);
+    return launch_sweep<double, M, false, false, 16, D>(P, a, b, grid, st);
+  }
+  if constexpr (M == 48 || M == 64) {
+    if constexpr (M % 32 == 0)
+      if (pw == 32) return tpp == 1 ? launch_sweep<float, M, true, false, 32, 1>(P, a, b, grid, st)
+                                    : launch_sweep<float, M, true, false, 32, 2>(P, a, b, grid, st);
+    return tpp == 1 ? launch_sweep<float, M, true, false, 16, 1>(P, a, b, grid, st)
+                    : launch_sweep<float, M, true, false, 16, 2>(P, a, b, grid, st);
+  } else {
+    if constexpr (M % 32 == 0)
+      if (pw == 32) return launch_sweep<float, M, true, false, 32, D>(P, a, b, grid, st);
+    return launch_sweep<float, M, true, false, 16, D>(P, a, b, grid, st);
+  }
+}
+
+hipError_t run_sweep(int M, bool mixed, int pw, int tpp, const Prob& P, const SweepArgs& a, const BatchDesc& b,
+                     int grid, hipStream_t st) {
   switch (M) {
-    case 16: QTX_SWEEP(16);
-    case 32: QTX_SWEEP(32);
-    case 48: QTX_SWEEP(48);
-    case 64: QTX_SWEEP(64);
-    case 96: QTX_SWEEP(96);
-    case 128: QTX_SWEEP(128);
+    case 16: return sweep_dispatch<16>(mixed, pw, tpp, P, a, b, grid, st);
+    case 32: return sweep_dispatch<32>(mixed, pw, tpp, P, a, b, grid, st);
+    case 48: return sweep_dispatch<48>(mixed, pw, tpp, P, a, b, grid, st);
+    case 64: return sweep_dispatch<64>(mixed, pw, tpp, P, a, b, grid, st);
+    case 96: return sweep_dispatch<96>(mixed, pw, tpp, P, a, b, grid, st);
+    case 128: return sweep_dispatch<128>(mixed, pw, tpp, P, a, b, grid, st);
     default: return hipErrorInvalidValue;
   }
-#undef QTX_SWEEP
 }
 
 hipError_t run_sweep_dm(int M, const Prob& P, const SweepArgs& a, int grid, hipStream_t st) {
@@ -1810,29 +1844,45 @@ hipError_t run_bands(int M, const double2* lead, int m, double V, const double* 
 #undef QTX_BANDS
 }
 
-hipError_t max_resident(int M, bool mixed, int* sweep_wgs, int* dec_wgs, int* dm_wgs) {
-  int a = 0, b = 0;
+template <typename R, int M, bool MIX, int PW, int TPP>
+hipError_t occ_sweep(int* n) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_sweep<R, M, MIX, false, PW, TPP>, NT, 0);
+}
+
+template <int M>
+hipError_t max_resident_m(bool mixed, int pw, int tpp, int* sweep_wgs, int* dec_wgs, int* dm_wgs) {
+  if (!sweep_variant_ok(M, mixed, pw, tpp)) return hipErrorInvalidValue;
+  constexpr int D = M <= 64 ? 2 : 1;
   hipError_t e = hipSuccess;
-#define QTX_OCC(MM)                                                                                              \
-  e = mixed ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_sweep<float, MM, true, false>, NT, 0)        \
-            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_sweep<double, MM, false, false>, NT, 0);     \
-  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_decimate<MM>, NT, 0);           \
-  if (e == hipSuccess && dm_wgs)                                                                              \
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(dm_wgs, k_sweep<double, MM, false, true>, NT, 0);        \
-  break
+  if (!mixed) {
+    e = occ_sweep<double, M, false, 16, D>(sweep_wgs);
+    if constexpr (M % 32 == 0)
+      if (pw == 32) e = occ_sweep<double, M, false, 32, D>(sweep_wgs);
+  } else if constexpr (M == 48 || M == 64) {
+    e = tpp == 1 ? occ_sweep<float, M, true, 16, 1>(sweep_wgs) : occ_sweep<float, M, true, 16, 2>(sweep_wgs);
+    if constexpr (M % 32 == 0)
+      if (pw == 32) e = tpp == 1 ? occ_sweep<float, M, true, 32, 1>(sweep_wgs) : occ_sweep<float, M, true, 32, 2>(sweep_wgs);
+  } else {
+    e = occ_sweep<float, M, true, 16, D>(sweep_wgs);
+    if constexpr (M % 32 == 0)
+      if (pw == 32) e = occ_sweep<float, M, true, 32, D>(sweep_wgs);
+  }
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(dec_wgs, k_decimate<M>, NT, 0);
+  if (e == hipSuccess && dm_wgs)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(dm_wgs, k_sweep<double, M, false, true>, NT, 0);
+  return e;
+}
+
+hipError_t max_resident(int M, bool mixed, int pw, int tpp, int* sweep_wgs, int* dec_wgs, int* dm_wgs) {
   switch (M) {
-    case 16: QTX_OCC(16);
-    case 32: QTX_OCC(32);
-    case 48: QTX_OCC(48);
-    case 64: QTX_OCC(64);
-    case 96: QTX_OCC(96);
-    case 128: QTX_OCC(128);
+    case 16: return max_resident_m<16>(mixed, pw, tpp, sweep_wgs, dec_wgs, dm_wgs);
+    case 32: return max_resident_m<32>(mixed, pw, tpp, sweep_wgs, dec_wgs, dm_wgs);
+    case 48: return max_resident_m<48>(mixed, pw, tpp, sweep_wgs, dec_wgs, dm_wgs);
+    case 64: return max_resident_m<64>(mixed, pw, tpp, sweep_wgs, dec_wgs, dm_wgs);
+    case 96: return max_resident_m<96>(mixed, pw, tpp, sweep_wgs, dec_wgs, dm_wgs);
+    case 128: return max_resident_m<128>(mixed, pw, tpp, sweep_wgs, dec_wgs, dm_wgs);
     default: return hipErrorInvalidValue;
   }
-#undef QTX_OCC
-  *sweep_wgs = a;
-  *dec_wgs = b;
-  return e;
 }
 
 hipError_t run_compact(const int* redo, int nE, int* elist, int* ecount, hipStream_t st) {

@@ -1,6 +1,12 @@
-"""Launch-shape autotuning (qtx_autotune): the choice is one of the timed
-candidates allowed by the kernels' occupancy, later solves use it, and
-the launch shape never changes a result."""
+"""Autotuning of the sweep's launch and tile shapes (qtx_autotune): the
+candidates are the built tile shapes (Gauss-Jordan panel width, column
+tiles per wave in the mixed refinement) times the workgroup counts the
+kernels' occupancy allows; the choice is the candidate with the smallest
+median time, and later solves use it.  The workgroup count and the
+refinement tiles never change a result (bit for bit); the panel width
+changes the rounding of the block inverses, so a result after tuning is
+held to the FP64 solve at the parity tolerances (FP64: |dT| <= 1e-10,
+densities 1e-9 relative; mixed: 1e-8)."""
 import numpy as np
 import pytest
 
@@ -10,19 +16,55 @@ from paper_1903_00548_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 
+def _close(a, b, prec):
+    tolT, tolN = (1e-10, 1e-9) if prec == _lib.FP64 else (1e-8, 1e-8)
+    (T0, L0), (T1, L1) = a, b
+    scale = np.maximum(1.0, np.abs(L0).max(axis=2))
+    return np.abs(T1 - T0).max() <= tolT and (np.abs(L1 - L0).max(axis=2) / scale).max() <= tolN
+
+
+@pytest.mark.parametrize("prec", [_lib.FP64, _lib.MIXED], ids=["fp64", "mixed"])
 @pytest.mark.parametrize("m,N", [(8, 16), (32, 40), (64, 24), (128, 10)])
-def test_autotune_picks_a_timed_candidate_and_keeps_results(gpu_lib, m, N):
+def test_autotune_picks_the_fastest_candidate(gpu_lib, m, N, prec):
     dev = W.small_random_device(61 + m, N, m, uniform=True, same_leads=True, pot_mode=W.POT_LINEAR_FE)
-    E = np.linspace(-1.5, 1.5, 1024)
+    E = np.linspace(-1.5, 1.5, 512 if prec == _lib.MIXED else 1024)
     ctx = _lib.context_for(dev, 0)
-    T0, L0, _, _ = ctx.solve(E, 1e-6, _lib.FP64)
-    wg, times = ctx.autotune(E, 1e-6, _lib.FP64)
-    print(f"m={m}: chose {wg} workgroups per CU; ms per candidate {np.round(times, 2).tolist()}")
-    assert 1 <= wg <= 4 and times[wg - 1] > 0
-    assert times[wg - 1] == min(t for t in times if t > 0)
-    assert times[0] > 0 and times[1] > 0          # every block size runs two workgroups per CU
-    T1, L1, _, _ = ctx.solve(E, 1e-6, _lib.FP64)
-    assert np.array_equal(T0, T1) and np.array_equal(L0, L1)
+    T0, L0, _, _ = _lib.context_for(dev, 0).solve(E, 1e-6, _lib.FP64)
+    best, cands, times = ctx.autotune(E, 1e-6, prec)
+    print(f"m={m} prec={prec}: chose {best}; candidates {len(cands)}, median ms {np.round(times, 2).tolist()}")
+    assert best in cands and np.all(times > 0)
+    assert times[cands.index(best)] == times.min()
+    M = ((m + 15) // 16) * 16 if m <= 64 else 128
+    assert {c["panel_width"] for c in cands} == ({16, 32} if M % 32 == 0 else {16})
+    if prec == _lib.MIXED and M == 64:
+        assert {c["refine_tiles"] for c in cands} == {1, 2}
+    assert len({tuple(c.values()) for c in cands}) == len(cands)
+    T1, L1, _, _ = ctx.solve(E, 1e-6, prec)
+    assert _close((T0, L0), (T1, L1), prec)
+
+
+@pytest.mark.parametrize("prec", [_lib.FP64, _lib.MIXED], ids=["fp64", "mixed"])
+def test_tile_shapes_agree(gpu_lib, prec):
+    """N = 24, m = 64 (own blocks, distinct leads) under every tile shape,
+    set through the options: the workgroup count and the refinement tiles
+    leave every bit unchanged, the other panel width agrees to the parity
+    tolerances."""
+    dev = W.small_random_device(125, 24, 64, uniform=False, same_leads=False, pot_mode=W.POT_LINEAR_FE)
+    E = np.linspace(-1.4, 1.4, 300)
+    out = {}
+    for pw in (16, 32):
+        for tpp in ((1, 2) if prec == _lib.MIXED else (0,)):
+            for wg in (1, 2):
+                ctx = _lib.context_for(dev, 0)
+                ctx.set_option("panel_width", pw)
+                ctx.set_option("refine_tiles", tpp)
+                ctx.set_option("workgroups_per_cu", wg)
+                T, L, _, _ = ctx.solve(E, 1e-6, prec)
+                out[(pw, tpp, wg)] = (T, L)
+    for (pw, tpp, wg), r in out.items():
+        ref = out[(pw, (1, 2)[0] if prec == _lib.MIXED else 0, 1)]
+        assert np.array_equal(r[0], ref[0]) and np.array_equal(r[1], ref[1]), (pw, tpp, wg)
+        assert _close(out[(16, tpp, 1)], r, prec), (pw, tpp, wg)
 
 
 def test_autotune_errors(gpu_lib):
@@ -34,3 +76,7 @@ def test_autotune_errors(gpu_lib):
     with pytest.raises(_lib.QtxError) as ei:
         ctx2.autotune(np.zeros(0), 1e-6)
     assert ei.value.status == _lib.EINVAL
+    for name, bad in (("panel_width", 24.0), ("refine_tiles", 3.0)):
+        with pytest.raises(_lib.QtxError) as ei:
+            ctx2.set_option(name, bad)
+        assert ei.value.status == _lib.EINVAL
