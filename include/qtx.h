@@ -418,6 +418,16 @@ qtx_status qtx_kernel_times(qtx_ctx* ctx, int enable, double* decimate_ms, doubl
 /* Library version string. */
 const char* qtx_version(void);
 
+/* Self-check of the library's memory layouts, host arithmetic only (no
+ * device needed): every sweep workspace (block sizes 16..128, FP64, mixed,
+ * density-matrix, the FP64 re-solve inside the mixed workspace, items
+ * shorter than the launch's longest), the decimation and Newton
+ * workspaces, and the no-allocation layouts of several problems must keep
+ * their regions aligned, inside their allocation and disjoint.  Returns 0
+ * with the number of layouts checked in msg[len], or 1 with a description
+ * of the first violation there (msg may be NULL). */
+int qtx_check_layouts(char* msg, int len);
+
 #ifdef __cplusplus
 }
 #endif

@@ -75,6 +75,7 @@ _SIGS = {
                                           c_void_p, c_void_p, c_void_p, c_void_p]),
     "qtx_charge": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_double, c_double, c_double,
                            c_void_p]),
+    "qtx_check_layouts": (c_int, [c_char_p, c_int]),
 }
 
 

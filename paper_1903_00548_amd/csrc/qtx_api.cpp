@@ -1661,6 +1661,111 @@ qtx_status qtx_autotune(qtx_ctx* c, const double* E, int nE, double eta, qtx_pre
   return QTX_OK;
 }
 
+int qtx_check_layouts(char* msg, int len) {
+  std::string err;
+  int nsweep = 0, ndec = 0, nplan = 0;
+  struct Reg {
+    const char* name;
+    size_t off, n, align;
+  };
+  auto check = [&](const std::string& what, size_t cap, const std::vector<Reg>& regs) {
+    for (size_t i = 0; i < regs.size() && err.empty(); ++i) {
+      const Reg& a = regs[i];
+      if (a.n == 0) continue;
+      if (a.off % a.align != 0) err = what + ": " + a.name + " misaligned";
+      else if (a.off > cap || a.n > cap - a.off) err = what + ": " + a.name + " beyond the workspace";
+      for (size_t j = 0; j < i && err.empty(); ++j) {
+        const Reg& b = regs[j];
+        if (b.n != 0 && a.off < b.off + b.n && b.off < a.off + a.n)
+          err = what + ": " + a.name + " overlaps " + b.name;
+      }
+    }
+  };
+  const int Ms[] = {16, 32, 48, 64, 96, 128};
+  // sweep workspaces: every block size and precision, items of N slabs in a
+  // launch sized for nmax >= N slabs, and the FP64 re-solve that runs in the
+  // mixed sweep's workspace after it
+  for (int M : Ms)
+    for (int N : {1, 2, 3, 7, 50, 200, 400})
+      for (int extra : {0, 13})
+        for (int mode = 0; mode < 3 && err.empty(); ++mode) {
+          const bool mixed = mode == 1, dm = mode == 2;
+          const size_t ws = qtx::sweep_ws_bytes(N + extra, M, mixed, dm);
+          const std::string what = "sweep M=" + std::to_string(M) + " N=" + std::to_string(N) + "/" +
+                                   std::to_string(N + extra) + (mixed ? " mixed" : dm ? " dm" : " fp64");
+          for (bool fallback : {false, true}) {
+            if (fallback && !mixed) continue;
+            const qtx::SweepLayout L = qtx::sweep_layout(N, M, mixed && !fallback, dm, ws);
+            ++nsweep;
+            const size_t al = (mixed && !fallback) ? 8 : 16;
+            check(what + (fallback ? " (FP64 re-solve)" : ""), ws,
+                  {{"[X|z]", L.xz, L.xz_n, al}, {"psi", L.psi, L.psi_n, al}, {"Dt^-1", L.di, L.di_n, 8},
+                   {"corrections", L.zc, L.zc_n, 8}, {"rhs slab", L.yb, L.yb_n, 8}, {"psi64", L.p64, L.p64_n, 16},
+                   {"working matrix", L.mat, L.mat_n, al}, {"coupling block", L.lst, L.lst_n, al},
+                   {"residual block", L.stg, L.stg_n, 16}});
+          }
+        }
+  // decimation workspace: e, eR, [a | b], X, residual (8 M^2) and the
+  // working matrix above 64; the Newton step reuses the first 7 M^2
+  for (int M : Ms) {
+    const size_t MM = (size_t)M * M, el = sizeof(double2);
+    const size_t cap = qtx::dec_ws_elems(M) * el;
+    ++ndec;
+    check("decimation M=" + std::to_string(M), cap,
+          {{"e", 0, MM * el, 16}, {"eR", MM * el, MM * el, 16}, {"[a|b]", 2 * MM * el, 2 * MM * el, 16},
+           {"X", 4 * MM * el, 2 * MM * el, 16}, {"residual", 6 * MM * el, 2 * MM * el, 16},
+           {"working matrix", 8 * MM * el, M > 64 ? (size_t)M * (M + 1) * el : 0, 16}});
+    check("newton M=" + std::to_string(M), cap,
+          {{"G, Q, P, X, T1, P2, Q2", 0, 7 * MM * el, 16},
+           {"working matrix", 8 * MM * el, M > 64 ? (size_t)M * (M + 1) * el : 0, 16}});
+  }
+  // no-allocation layouts of several problems (host arithmetic only)
+  for (int M : Ms)
+    for (int N : {1, 16, 200, 400})
+      for (int nE : {1, 64, 2048, 100000})
+        for (int mode = 0; mode < 4 && err.empty(); ++mode) {
+          const bool mixed = mode & 1, two = mode & 2;
+          qtx_ctx c;
+          c.M = M;
+          c.m = M;
+          c.N = N;
+          c.num_cu = 256;
+          if (two) c.Vlead[1] = 0.1;                  // distinct leads: two lead iterations per energy
+          char* base = reinterpret_cast<char*>((uintptr_t)1 << 20);
+          int ne = 0;
+          SolveBufs b;
+          const size_t cap = qtx::kNoAllocScratchBytes;
+          if (plan_noalloc(&c, nE, mixed, base, cap, &ne, &b) != QTX_OK) continue;   // refused: nothing carved
+          ++nplan;
+          const size_t MM = (size_t)M * M;
+          auto off = [&](const void* p) { return (size_t)(reinterpret_cast<const char*>(p) - base); };
+          check("noalloc M=" + std::to_string(M) + " N=" + std::to_string(N) + " nE=" + std::to_string(nE) +
+                    (mixed ? " mixed" : " fp64") + (two ? " two leads" : ""),
+                cap,
+                {{"sigma", off(b.sig), (size_t)ne * 2 * MM * sizeof(double2), 256},
+                 {"W", off(b.wf), (size_t)ne * 2 * MM * sizeof(double2), 256},
+                 {"signs", off(b.sgn), (size_t)ne * 2 * M * sizeof(double), 256},
+                 {"doublings", off(b.iters), (size_t)ne * 2 * sizeof(int), 256},
+                 {"heavy", off(b.nheavy), (size_t)ne * 2 * sizeof(int), 256},
+                 {"decimation ws", off(b.dscr), (size_t)b.gdec * qtx::dec_ws_elems(M) * sizeof(double2), 256},
+                 {"sweep ws", off(b.sws), (size_t)b.grid * b.wsb, 256},
+                 {"partials", off(b.part), (size_t)b.grid * 4 * 2 * N * (mixed ? 2 : 1) * sizeof(double), 256},
+                 {"redo", mixed ? off(b.redo) : 0, mixed ? (size_t)ne * sizeof(int) : 0, 256},
+                 {"elist", mixed ? off(b.elist) : 0, mixed ? (size_t)ne * sizeof(int) : 0, 256},
+                 {"ecount", mixed ? off(b.ecount) : 0, mixed ? sizeof(int) : 0, 256}});
+          if (err.empty() && (b.grid < 1 || b.gdec < 1 || ne < 1 || b.grid > ne || b.wsb != qtx::sweep_ws_bytes(N, M, mixed)))
+            err = "noalloc: inconsistent grid or chunk";
+        }
+  const std::string out = err.empty() ? "ok: " + std::to_string(nsweep) + " sweep, " + std::to_string(ndec) +
+                                            " decimation, " + std::to_string(nplan) + " no-allocation layouts"
+                                      : err;
+  if (msg && len > 0) {
+    std::strncpy(msg, out.c_str(), (size_t)len - 1);
+    msg[len - 1] = '\0';
+  }
+  return err.empty() ? 0 : 1;
+}
+
 qtx_status qtx_bands(qtx_ctx* c, qtx_side side, const double* k, int nk, double* E) {
   if (!c) return QTX_EINVAL;
   if (side != QTX_LEFT && side != QTX_RIGHT) return fail(c, QTX_EINVAL, "side must be QTX_LEFT or QTX_RIGHT");

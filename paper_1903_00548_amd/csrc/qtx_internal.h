@@ -123,6 +123,50 @@ inline size_t sweep_ws_bytes(int N, int M, bool mixed, bool dm = false) {
          (size_t)N * 2 * MM * sizeof(double2) + big;
 }
 
+// Byte offsets within one workgroup's sweep workspace (ws_bytes long) of
+// the regions a sweep over an item of N slabs uses, and their sizes; the
+// kernels take their pointers from here, and qtx_check_layouts tests the
+// layouts on the host.  FP64 sweep: [X_i | z_i] per slab, then the
+// back-substitution buffer (two for the density-matrix sweep).  Mixed
+// sweep: the same in complex floats, then the inverses of the Schur
+// complements, the correction columns, one slab of right-hand sides and
+// the refined FP64 solution.  Blocks above 64: the working matrix and the
+// staged coupling block at the end, and in the mixed sweep the FP64 block
+// of the refinement's residual products just below them.
+struct SweepLayout {
+  size_t xz, psi, di, zc, yb, p64, mat, lst, stg;
+  size_t xz_n, psi_n, di_n, zc_n, yb_n, p64_n, mat_n, lst_n, stg_n;
+};
+__host__ __device__ inline SweepLayout sweep_layout(int N, int M, bool mixed, bool dm, size_t ws_bytes) {
+  SweepLayout L{};
+  const size_t MM = (size_t)M * M, LD = 2 * (size_t)M, S = (size_t)M + 1;
+  const size_t el = mixed ? 8 : 16;                      // complex float / complex double
+  L.xz = 0;
+  L.xz_n = (size_t)N * M * LD * el;
+  L.psi = L.xz + L.xz_n;
+  L.psi_n = (dm ? 2 : 1) * (size_t)M * LD * el;
+  if (mixed) {
+    L.di = L.psi + L.psi_n;
+    L.di_n = (size_t)N * MM * 8;
+    L.zc = L.di + L.di_n;
+    L.zc_n = (size_t)N * M * LD * 8;
+    L.yb = L.zc + L.zc_n;
+    L.yb_n = (size_t)M * LD * 8;
+    L.p64 = L.yb + L.yb_n;
+    L.p64_n = (size_t)N * M * LD * 16;
+  }
+  if (M > 64) {
+    L.mat_n = L.lst_n = S * (size_t)M * el;
+    L.mat = ws_bytes - 2 * L.mat_n;
+    L.lst = L.mat + L.mat_n;
+    if (mixed) {
+      L.stg_n = S * (size_t)M * 16;
+      L.stg = L.mat - L.stg_n;
+    }
+  }
+  return L;
+}
+
 // Per-workgroup decimation workspace (complex doubles): e, the right surface
 // block, [a | b], g [a | b], the residual, and for M > 64 the working matrix
 // M x (M + 1).

@@ -1079,16 +1079,17 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(Prob P0, SweepArgs a, BatchDesc
   __shared__ double tred[NWAVE];
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   char* wsb = a.ws + (size_t)blockIdx.x * a.ws_bytes;
+  const SweepLayout L0 = sweep_layout(0, M, MIX, DM, a.ws_bytes);
   cpx<R>* mat;
   cpx<R>* Lst;                                  // -L_i, staged once per slab
   if constexpr (BIG) {
-    mat = (cpx<R>*)(wsb + a.ws_bytes - 2 * (size_t)M * S * sizeof(cpx<R>));
-    Lst = mat + M * S;
+    mat = (cpx<R>*)(wsb + L0.mat);
+    Lst = (cpx<R>*)(wsb + L0.lst);
   } else {
     mat = mat_l;
     Lst = mat_l;
   }
-  V2* XZ = (V2*)wsb;
+  V2* XZ = (V2*)(wsb + L0.xz);
   double* prt = a.part + (size_t)blockIdx.x * NWAVE * 2 * a.nmax * (MIX ? 2 : 1);
   double* prt2 = prt + (size_t)NWAVE * 2 * a.nmax;
   // values loaded from memory are made wave-uniform explicitly, so that
@@ -1099,16 +1100,17 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(Prob P0, SweepArgs a, BatchDesc
     const Prob P = b.probs ? load_prob(b.probs + __builtin_amdgcn_readfirstlane(b.item_prob[e])) : P0;
     const int N = P.N;
     // workspace layout for this item's slab count (at most a.nmax)
-    V2* PSI = XZ + (size_t)N * M * LD;
+    const SweepLayout Lw = sweep_layout(N, M, MIX, DM, a.ws_bytes);
+    V2* PSI = (V2*)(wsb + Lw.psi);
     float2* DI = nullptr;
     float2* ZC = nullptr;
     float2* YB = nullptr;
     double2* P64 = nullptr;
     if constexpr (MIX) {
-      DI = (float2*)(XZ + (size_t)(N + 1) * M * LD);
-      ZC = DI + (size_t)N * MM;
-      YB = ZC + (size_t)N * M * LD;
-      P64 = (double2*)(YB + (size_t)M * LD);
+      DI = (float2*)(wsb + Lw.di);
+      ZC = (float2*)(wsb + Lw.zc);
+      YB = (float2*)(wsb + Lw.yb);
+      P64 = (double2*)(wsb + Lw.p64);
     }
     double* ldos_e = nullptr;
     if (a.ldos) ldos_e = a.ldos + (b.probs ? b.item_ldos[e] : (size_t)e * 2 * N);
@@ -1398,8 +1400,7 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(Prob P0, SweepArgs a, BatchDesc
       // M > 64: the staged FP64 block sits below the working matrix and
       // the coupling block at the end of the workspace
       cpx<double>* stg = lu.stg;
-      if constexpr (BIG) stg = (cpx<double>*)(wsb + a.ws_bytes - 2 * (size_t)M * S * sizeof(cpx<R>) -
-                                              (size_t)M * S * sizeof(cpx<double>));
+      if constexpr (BIG) stg = (cpx<double>*)(wsb + L0.stg);
       rel = refine<M, TPP>(P, a, sL, sR, WL, WR, z, hR, hL, (const float2*)XZ, DI, ZC, YB, P64, stg, tred, &steps);
       // transmission and the heavy columns' densities from the refined solution
       {
