@@ -1716,7 +1716,7 @@ int qtx_check_layouts(char* msg, int len) {
            {"X", 4 * MM * el, 2 * MM * el, 16}, {"residual", 6 * MM * el, 2 * MM * el, 16},
            {"working matrix", 8 * MM * el, M > 64 ? (size_t)M * (M + 1) * el : 0, 16}});
     check("newton M=" + std::to_string(M), cap,
-          {{"G, Q, P, X, T1, P2, Q2", 0, 7 * MM * el, 16},
+          {{"G, Q, P, X, T1, P2, Q2", 0, 7 * MM * el, 16}, {"job counter", 7 * MM * el, sizeof(int), 4},
            {"working matrix", 8 * MM * el, M > 64 ? (size_t)M * (M + 1) * el : 0, 16}});
   }
   // no-allocation layouts of several problems (host arithmetic only)

@@ -778,12 +778,21 @@ __global__ __launch_bounds__(NT, M > 64 ? 1 : 2) void k_decimate(Prob P0, BatchD
     }
     __syncthreads();
   }
+  // the job counter of the k_sigma_finish launch that follows: the first
+  // element of block 7 M^2 of workgroup 0's workspace (the residual, dead
+  // once that workgroup's jobs are done; the Newton step uses blocks 0-6)
+  if (blockIdx.x == 0 && t == 0) *reinterpret_cast<int*>(scratch + 7 * MM) = 0;
 }
 
 // Second stage of the self-energy jobs of a decimation launch (same jobs,
 // same workspace): the Newton check and step on each self-energy (option
 // newton_tol >= 0), then the LDL^H factor of its broadening.  A kernel of its
-// own so that the doubling loop keeps its registers.
+// own so that the doubling loop keeps its registers.  The few self-energies
+// that take a Newton step cost tens of times a check, so the jobs are dealt
+// from a counter (zeroed by k_decimate) rather than by a fixed stride: a
+// workgroup that draws a correction takes fewer jobs, and the launch ends
+// about one correction after the last check instead of after the sum of the
+// corrections that one stride happens to collect.
 template <int M>
 __global__ __launch_bounds__(NT, M > 64 ? 1 : 2) void k_sigma_finish(Prob P0, BatchDesc b, const double* E, int nE,
                                                                      double eta, int sides, DecOpts o,
@@ -798,12 +807,20 @@ __global__ __launch_bounds__(NT, M > 64 ? 1 : 2) void k_sigma_finish(Prob P0, Ba
   } u;
   __shared__ BGJ<double, M> sc;
   __shared__ double red[NWAVE];
+  __shared__ int next_job;
+  const int t = threadIdx.x;
   double2* ws = scratch + (size_t)blockIdx.x * dec_ws_elems(M);
+  int* counter = reinterpret_cast<int*>(scratch + 7 * MM);
   cpx<double>* mat;
   if constexpr (BIG) mat = (cpx<double>*)(ws + 8 * MM);
   else mat = mat_l;
   const int njobs = b.probs ? b.njobs : nE * sides;
-  for (int job = blockIdx.x; job < njobs; job += gridDim.x) {
+  for (;;) {
+    if (t == 0) next_job = atomicAdd(counter, 1);
+    __syncthreads();
+    const int job = __builtin_amdgcn_readfirstlane(next_job);
+    __syncthreads();
+    if (job >= njobs) break;
     const DecJob J = dec_job(P0, b, E, eta, sides, job);
     for (int s = 0; s < 2; ++s) {
       if ((J.side == 0 && s == 1) || (J.side == 1 && s == 0)) continue;
