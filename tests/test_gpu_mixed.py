@@ -61,25 +61,40 @@ def test_mixed_small_devices(gpu_lib, case):
     _check(T, L, Tref, Lref, label=f"seed{case[0]} mixed")
 
 
-def test_mixed_cfg1_full_size(gpu_lib):
+def test_mixed_cfg1_full_size(gpu_lib, cfg1_oracle):
     """Headline workload, 2048 energies in one call: every energy against the
     FP64 GPU path (held to 1e-10 of the oracle by the FP64 parity tests),
-    12 sampled energies against the oracle directly."""
-    wl = W.config1()
+    64 sampled energies against the oracle directly."""
+    wl, idx, Tref, Lref = cfg1_oracle
     dev = wl.device
     ctx = _lib.context_for(dev, 0)
     T64, L64, _, _ = ctx.solve(wl.E, wl.eta, _lib.FP64)
     T, L, info, st = ctx.solve(wl.E, wl.eta, _lib.MIXED)
     assert st == _lib.OK
     _check(T, L, T64, L64, "cfg1 mixed vs fp64 (all 2048)", tolT=TOL_T - 1e-10, tolN=TOL_N)
-    rng = np.random.default_rng(4321)
-    idx = np.sort(np.concatenate([[0, len(wl.E) - 1], rng.choice(len(wl.E), 10, replace=False)]))
-    Tref, Lref = oracle.solve_device(dev, wl.E[idx], wl.eta)
-    _check(T[idx], L[idx], Tref, Lref, "cfg1 mixed vs oracle (sampled)")
+    _check(T[idx], L[idx], Tref, Lref, "cfg1 mixed vs oracle (64 sampled)")
     steps = info["refine_steps"]
     print("refinement steps histogram:", np.bincount(steps, minlength=4).tolist(),
           "fallbacks:", int(info["fell_back_fp64"].sum()))
     assert steps.max() <= 3
+
+
+def test_mixed_cfg2_full_size(gpu_lib, cfg2_oracle):
+    """N = 400, m = 128, all 4096 energies (3840 uniform, 256 within 1 meV of
+    a band edge) in one mixed call, as the benchmark runs it: every energy
+    within 1e-8 of the FP64 path, the 16 sampled energies against the
+    oracle."""
+    wl, idx, n_uni, Tref, Lref = cfg2_oracle
+    ctx = _lib.context_for(wl.device, 0)
+    T64, L64, _, _ = ctx.solve(wl.E, wl.eta, _lib.FP64)
+    T, L, info, st = ctx.solve(wl.E, wl.eta, _lib.MIXED)
+    assert st == _lib.OK
+    _check(T[:n_uni], L[:n_uni], T64[:n_uni], L64[:n_uni], "cfg2 mixed vs fp64 (3840 uniform)",
+           tolT=TOL_T - 1e-10)
+    _check(T[n_uni:], L[n_uni:], T64[n_uni:], L64[n_uni:], "cfg2 mixed vs fp64 (256 band edge)",
+           tolT=TOL_T - 1e-10)
+    _check(T[idx], L[idx], Tref, Lref, "cfg2 mixed vs oracle (16 sampled)")
+    assert info["refine_steps"].max() <= 3
 
 
 def test_mixed_forced_fallback_is_the_fp64_result(gpu_lib):

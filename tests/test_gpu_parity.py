@@ -89,20 +89,19 @@ def test_solve_small_devices_fp64(gpu_lib, case):
     _check(T, L, Tref, Lref, absN=TOL_N_ABS, label=f"seed{case[0]}")
 
 
-def test_cfg1_full_size_sampled(gpu_lib):
+def test_cfg1_full_size_sampled(gpu_lib, cfg1_oracle):
     """The headline workload at full size (2048 energies in one call, the
-    launch configuration the benchmark times); 12 energies are checked
-    against the oracle one by one, and every output must be finite."""
-    wl = W.config1()
+    launch configuration the benchmark times); 64 energies (both ends of
+    the grid and 62 drawn at random) are checked against the oracle one by
+    one, and every output must be finite."""
+    wl, idx, Tref, Lref = cfg1_oracle
     dev = wl.device
     ctx = _ctx(dev)
     T, L, info, st = ctx.solve(wl.E, wl.eta, _lib.FP64)
     assert st == _lib.OK
     assert np.all(np.isfinite(T)) and np.all(np.isfinite(L))
     assert np.all(T > -1e-9)
-    rng = np.random.default_rng(1234)
-    idx = np.sort(np.concatenate([[0, len(wl.E) - 1], rng.choice(len(wl.E), 10, replace=False)]))
-    Tref, Lref = oracle.solve_device(dev, wl.E[idx], wl.eta)
+    assert len(idx) == 64
     _check(T[idx], L[idx], Tref, Lref, absN=TOL_N_ABS, label="cfg1")
     assert np.all(info["dec_iters"] > 0)
 
@@ -169,21 +168,16 @@ def test_solve_device_on_a_torch_stream(gpu_lib):
     assert np.array_equal(T_t.cpu().numpy(), T) and np.array_equal(L_t.cpu().numpy(), L)
 
 
-def test_cfg2_full_size_sampled(gpu_lib):
+def test_cfg2_full_size_sampled(gpu_lib, cfg2_oracle):
     """N = 400, m = 128 with its 4096 energies (band-edge set included) in one
-    FP64 call, as the benchmark runs it: every output finite, six energies
-    (two uniform, four within 1 meV of a band edge, among them the two
+    FP64 call, as the benchmark runs it: every output finite, 16 energies
+    (eight uniform, eight within 1 meV of a band edge, among them the two
     hardest of the set for the decimation) against the oracle at the fixed
     bars.  The self-energies there rely on the Newton step after the
     doublings (test_gpu_sigma_newton.py)."""
-    import os
-    edges = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "cfg2_band_edge_energies.txt"))
-    wl = W.config2(band_edge_energies=edges)
-    dev = wl.device
-    ctx = _ctx(dev)
+    wl, idx, n_uni, Tref, Lref = cfg2_oracle
+    ctx = _ctx(wl.device)
     T, L, info, st = ctx.solve(wl.E, wl.eta, _lib.FP64)
     assert st == _lib.OK and np.all(np.isfinite(T)) and np.all(np.isfinite(L))
-    n_uni = len(wl.E) - len(edges)
-    idx = np.array([7, n_uni - 100, n_uni + 11, n_uni + 150, n_uni + 250, len(wl.E) - 2])
-    Tref, Lref = oracle.solve_device(dev, wl.E[idx], wl.eta)
+    assert np.sum(idx < n_uni) == 8 and np.sum(idx >= n_uni) == 8
     _check(T[idx], L[idx], Tref, Lref, label="cfg2")
