@@ -379,6 +379,40 @@ def bench_density_matrix(args):
     }))
 
 
+def bench_integration(args):
+    """Energy integration at full size: the adaptive density integral
+    (Fermi-weighted slab densities, both contacts) of the N = 200, m = 64
+    device over [-1.5, 0.2 + 20 kT] at eta = 1e-6, mu_L = 0.2, mu_R = -0.1,
+    kT = 0.025, to an absolute tolerance of 1e-3 on every slab density, with
+    and without the look-ahead levels (fill = 512, one energy per resident
+    workgroup).  Reports calls, energies, wall time and the value agreement
+    of the two runs."""
+    from paper_1903_00548_amd import _lib, integrate, workloads
+    wl = workloads.config1()
+    dev = wl.device
+    ctx = _lib.context_for(dev, 0)
+    muL, muR, kT = 0.2, -0.1, 0.025
+    A, B = -1.5, muL + 20 * kT
+    solve = integrate.qtx_solver(ctx, wl.eta)
+    solve(np.linspace(A, B, 64))                          # warm-up: workspaces
+    out = {}
+    for fill in (0, 512):
+        t0 = time.perf_counter()
+        r = integrate.integrate(solve, "density", A, B, muL, muR, kT, tol=1e-3, fill=fill)
+        dt = time.perf_counter() - t0
+        out[f"fill{fill}"] = {"seconds": dt, "calls": r.rounds, "energies": r.evaluations,
+                              "energies_used": int(np.count_nonzero(r.weights)), "converged": bool(r.converged),
+                              "energy_solves_per_s": r.evaluations / dt, "value": r.value}
+        print(json.dumps({k: v for k, v in out[f"fill{fill}"].items() if k != "value"}), file=sys.stderr, flush=True)
+    v0, v1 = out["fill0"].pop("value"), out["fill512"].pop("value")
+    print(json.dumps({"metric": "density integral time-to-solution (N=200, m=64)", "value": out["fill512"]["seconds"],
+                      "unit": "s", "n_gpus": 1, "higher_is_better": False, "dtype": "f64", "data": "synthetic",
+                      "config": {"workload": "cfg1_N200_m64_density_integral", "A": A, "B": B, "muL": muL,
+                                 "muR": muR, "kT": kT, "tol": 1e-3, "eta": wl.eta},
+                      "runs": out, "max_abs_value_difference": float(np.abs(v0 - v1).max())}), flush=True)
+    ctx.close()
+
+
 def bench_modes(args):
     """The N=200, m=64 grid of 2048 energies in the paper's mode-space form
     at eta = 0 (self-energies from the complex band structure of the lead on
@@ -626,7 +660,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration)")
-    ap.add_argument("--workload", choices=("cfg1", "cfg2", "batch64", "serve", "bands", "density_matrix", "modes"),
+    ap.add_argument("--workload", choices=("cfg1", "cfg2", "batch64", "serve", "bands", "density_matrix", "modes",
+                                           "integration"),
                     default="cfg1",
                     help="cfg1: the headline N=200, m=64 grid (default); batch64: the uneven 64-device "
                          "batch; serve: the Poisson request loop")
@@ -645,6 +680,12 @@ def main():
             print("bench.py: one GPU only", file=sys.stderr)
             sys.exit(2)
         bench_modes(args)
+        return
+    if args.workload == "integration":
+        if args.gpus != 1:
+            print("bench.py: one GPU only", file=sys.stderr)
+            sys.exit(2)
+        bench_integration(args)
         return
     if args.workload == "density_matrix":
         if args.gpus != 1:

@@ -63,10 +63,21 @@ class Result:
 
 
 def adaptive_simpson(F: Callable[[np.ndarray], np.ndarray], A: float, B: float, tol: float,
-                     n0: int = 16, max_rounds: int = 40, min_width: float = 1e-10) -> Result:
+                     n0: int = 16, max_rounds: int = 40, min_width: float = 1e-10, fill: int = 0,
+                     max_ahead: int = 6) -> Result:
     """Integrate the vector function F over [A, B] to absolute tolerance tol
     (max norm over components).  F takes a 1-D array of energies and returns
-    an array of shape (len(E), K)."""
+    an array of shape (len(E), K).
+
+    fill > 0: a round whose new abscissae number fewer than fill also takes
+    the abscissae of up to max_ahead further levels of its failing panels'
+    halves (as many whole levels as keep the call within fill).  A GPU call
+    costs about the same for any count up to one energy per resident
+    workgroup, so late rounds, which carry few energies, get their next
+    levels for free and the number of calls drops.  Panels accepted before
+    those levels are needed leave the extra abscissae unused (weight 0);
+    the accepted panels, the value and the weights of the used abscissae
+    are those of fill = 0."""
     if not (B > A) or not (tol > 0):
         raise ValueError("need B > A and tol > 0")
     vals: Dict[float, np.ndarray] = {}
@@ -93,11 +104,25 @@ def adaptive_simpson(F: Callable[[np.ndarray], np.ndarray], A: float, B: float, 
     def add_weights(points, factors, h):
         for p, f in zip(points, factors):
             wts[p] = wts.get(p, 0.0) + h * f
-    while pending and rounds < max_rounds:
-        pts = set()
-        for a, b in pending:
+    def panel_points(panels):
+        out = set()
+        for a, b in panels:
             m = 0.5 * (a + b)
-            pts.update((a, 0.5 * (a + m), m, 0.5 * (m + b), b))
+            out.update((a, 0.5 * (a + m), m, 0.5 * (m + b), b))
+        return out
+
+    while pending and rounds < max_rounds:
+        pts = panel_points(pending)
+        if fill > 0:
+            n_new = sum(1 for p in pts if p not in vals)
+            level = pending
+            for _ in range(max_ahead):
+                level = [h for a, b in level for h in ((a, 0.5 * (a + b)), (0.5 * (a + b), b))]
+                more = {p for p in panel_points(level) if p not in vals and p not in pts}
+                if n_new == 0 or n_new + len(more) > fill:
+                    break
+                pts |= more
+                n_new += len(more)
         evaluate(pts)
         nxt = []
         for a, b in pending:
@@ -147,10 +172,13 @@ def integrand(quantity: str, solve: Callable, muL: float, muR: float, kT: float)
 
 
 def integrate(solve: Callable, quantity: str, A: float, B: float, muL: float, muR: float, kT: float,
-              tol: float, n0: int = 16, max_rounds: int = 40) -> Result:
+              tol: float, n0: int = 16, max_rounds: int = 40, fill: int = 0) -> Result:
     """Adaptive integral of a quantity over [A, B] (see the module docstring)
-    with the transport solve as integrand."""
-    return adaptive_simpson(integrand(quantity, solve, muL, muR, kT), A, B, tol, n0=n0, max_rounds=max_rounds)
+    with the transport solve as integrand; fill as in adaptive_simpson (one
+    energy per resident workgroup, e.g. 512 at m <= 64, keeps late calls
+    full)."""
+    return adaptive_simpson(integrand(quantity, solve, muL, muR, kT), A, B, tol, n0=n0, max_rounds=max_rounds,
+                            fill=fill)
 
 
 def density_matrix(ctx, result: Result, muL: float, muR: float, kT: float, eta: float):
@@ -160,8 +188,9 @@ def density_matrix(ctx, result: Result, muL: float, muR: float, kT: float, eta: 
     each contact, one pass of the HIP library's density-matrix solve).  For
     the result of a "density" integration, the trace of rho_ii equals its
     value up to rounding."""
-    E = np.asarray(result.energies, dtype=np.float64)
-    q = np.asarray(result.weights, dtype=np.float64)
+    used = np.asarray(result.weights) != 0.0         # abscissae taken ahead but not needed carry weight 0
+    E = np.asarray(result.energies, dtype=np.float64)[used]
+    q = np.asarray(result.weights, dtype=np.float64)[used]
     rd, ro, _, _, _, _ = ctx.density_matrix(E, q * fermi(E - muL, kT), q * fermi(E - muR, kT), eta)
     return rd, ro
 

@@ -105,3 +105,30 @@ def test_weights_reproduce_the_value():
         direct = r.weights @ F(r.energies)
         assert np.allclose(direct, r.value, rtol=1e-13, atol=1e-15), (direct, r.value)
     assert abs(r.weights.sum() - 3.0) < 1e-12           # the constant 1 integrates exactly
+
+
+@pytest.mark.parametrize("fill", [64, 512])
+def test_taking_levels_ahead_keeps_the_result_and_cuts_calls(fill):
+    """fill > 0 evaluates further levels of the failing panels in the same
+    call: the accepted panels, the value and the weights of every abscissa
+    used are those of the plain driver, no call exceeds fill new abscissae
+    unless the plain driver's calls do, and there are fewer calls."""
+    g, x0 = 1e-3, 0.3171
+
+    def f(E):
+        return np.stack([g / np.pi / ((E - x0) ** 2 + g * g), np.sqrt(np.abs(E + 0.8))], axis=1)
+
+    F0, calls0 = _counting(f)
+    F1, calls1 = _counting(f)
+    r0 = I.adaptive_simpson(F0, -1.0, 1.0, 1e-9)
+    r1 = I.adaptive_simpson(F1, -1.0, 1.0, 1e-9, fill=fill)
+    assert r0.converged and r1.converged
+    assert np.array_equal(r0.value, r1.value)
+    assert len(calls1) < len(calls0)
+    used = r1.weights != 0
+    assert np.array_equal(r1.energies[used], r0.energies[r0.weights != 0])
+    assert np.array_equal(r1.weights[used], r0.weights[r0.weights != 0])
+    assert set(r0.energies) <= set(r1.energies)
+    assert max(len(c) for c in calls1) <= max(fill, max(len(c) for c in calls0))
+    allE = np.concatenate(calls1)
+    assert len(np.unique(allE)) == len(allE)
