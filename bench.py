@@ -622,6 +622,7 @@ def serving_leg(precision_name="fp64", probe_seconds=10.0, seconds=20.0):
             "offered_rate_per_s": rate, "offered_requests": len(reqs), "completed": st["completed"],
             "unfinished": st["unfinished"], "energy_solves_per_s": st["energy_solves_per_s"],
             "p50_latency_s": st["p50_latency_s"], "p99_latency_s": st["p99_latency_s"],
+            "solve_fraction_of_wall_saturated": st0["solve_fraction_of_wall"],
             "note": f"rate-scaled to 80 % of the saturated throughput, {seconds:.0f} s of arrivals; the "
                     "configured 200 req/s offers ~100x one GPU's capacity (queueing only)"}
 

@@ -101,6 +101,7 @@ class Server:
         self.steps = 0
         self.energies_solved = 0
         self.batch_sizes: List[int] = []
+        self.solve_seconds = 0.0          # wall time inside backend.solve (the GPU's share of the loop)
 
     # ------------------------------------------------------------ intake
     def submit(self, req: Request):
@@ -133,8 +134,10 @@ class Server:
             a = r.next
             b = min(len(r.E), a + self.energies_per_step)
             chunks.append((r, a, b))
+        t_call = self.clock()
         Ts, Ls, st = self.backend.solve([r.handle for r, _, _ in chunks], [r.E[a:b] for r, a, b in chunks])
         now = self.clock()
+        self.solve_seconds += now - t_call
         n = 0
         still = []
         for (r, a, b), T, L in zip(chunks, Ts, Ls):
@@ -208,5 +211,6 @@ class Server:
             "p50_latency_s": float(np.percentile(lat, 50)) if len(lat) else None,
             "p99_latency_s": float(np.percentile(lat, 99)) if len(lat) else None,
             "steps": self.steps,
+            "solve_fraction_of_wall": self.solve_seconds / wall if wall > 0 else 0.0,
             "mean_energies_per_step": float(np.mean(self.batch_sizes)) if self.batch_sizes else 0.0,
         }
