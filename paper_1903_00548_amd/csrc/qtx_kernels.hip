@@ -595,7 +595,7 @@ __global__ __launch_bounds__(NT, M > 64 ? 1 : 2) void k_decimate(Prob P0, BatchD
   constexpr int MT = M / 16, MM = M * M, S = M + 1, LB = 2 * M;
   constexpr bool BIG = M > 64;                    // working matrix in the global workspace
   __shared__ cpx<double> mat_l[BIG ? 1 : M * S];
-  __shared__ union {
+  __shared__ __align__(16) union {
     cpx<double> y[gj_scratch<M>()];
     LDLScratch<M> ldl;
   } u;
@@ -801,7 +801,7 @@ __global__ __launch_bounds__(NT, M > 64 ? 1 : 2) void k_sigma_finish(Prob P0, Ba
   constexpr int MM = M * M, S = M + 1;
   constexpr bool BIG = M > 64;
   __shared__ cpx<double> mat_l[BIG ? 1 : M * S];
-  __shared__ union {
+  __shared__ __align__(16) union {
     cpx<double> y[gj_scratch<M>()];
     LDLScratch<M> ldl;
   } u;
@@ -1086,7 +1086,10 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(Prob P0, SweepArgs a, BatchDesc
   // the working matrix; during the mixed refinement (M <= 64) the FP64
   // block staged for the residual products
   constexpr int STG = (MIX && !BIG) ? M * S : 1;
-  __shared__ union {
+  // 16-byte alignment stated: a union of cpx arrays is only 8-byte aligned
+  // by type, and without it the complex loads and stores split into pairs
+  // of 8-byte LDS accesses
+  __shared__ __align__(16) union {
     cpx<R> m[BIG ? 1 : M * S];
     cpx<double> stg[STG];
   } lu;
