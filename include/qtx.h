@@ -303,9 +303,15 @@ qtx_status qtx_self_energy(qtx_ctx* ctx, const double* E, int nE, double eta,
  *                           QTX_FP64 (QTX_MIXED: QTX_EINVAL), for qtx_solve,
  *                           qtx_solve_device, qtx_self_energy and
  *                           qtx_density_matrix; qtx_solve_batch rejects it.
- *                           It needs H01 - E S01 invertible at every energy
- *                           (else the energy is flagged QTX_FLAG_DEC_NOTCONV);
- *                           qtx_info.dec_iters then counts QR iterations;
+ *                           Couplings H01 - E S01 of lower rank than the
+ *                           slab (the paper's symmetric pencil is then
+ *                           singular) are handled by solving the quadratic
+ *                           in a shifted variable nu, lambda = (nu + s) /
+ *                           (1 + conj(s) nu), |s| < 1, which keeps the mode
+ *                           vectors and the unit circle; an energy whose
+ *                           modes cannot be split m / m is flagged
+ *                           QTX_FLAG_DEC_NOTCONV.  qtx_info.dec_iters then
+ *                           counts QR iterations;
  *   "mode_tol"              (0, 1e-2]     1e-8   method 1: modes with
  *                           ||lambda| - 1| <= mode_tol travel;
  *   "sweep_workspace_bytes" (0, 1e13]     160 GiB device memory for the

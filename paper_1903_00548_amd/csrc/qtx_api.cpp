@@ -329,11 +329,14 @@ qtx_status stage_decimate(qtx_ctx* c, const double* E_dev, int nE, double eta, b
     if (s != QTX_OK) return s;
     const int jb = qtx::modes_batch_jobs(M, nE * sides);
     QTX_HIP(c, c->mscr.ensure((size_t)jb * qtx::modes_ws_elems(M) * sizeof(double2)));
-    QTX_HIP(c, c->mjst.ensure((size_t)jb * sizeof(int)));
+    // per job: the status, then (16-byte aligned) the eigenvalue shift taken
+    const size_t shift_off = ((size_t)jb * sizeof(int) + 15) / 16 * 16;
+    QTX_HIP(c, c->mjst.ensure(shift_off + (size_t)jb * sizeof(double2)));
     QTX_HIP(c, record(c, c->ev_dec, c->n_dec));
     QTX_HIP(c, qtx::run_modes(M, make_prob(c), E_dev, nE, eta, sides, c->mode_tol, c->m, c->num_cu,
-                              c->mscr.as<double2>(), c->mjst.as<int>(), b.sig, b.wf, b.sgn, b.iters, b.nheavy,
-                              c->stream));
+                              c->mscr.as<double2>(), c->mjst.as<int>(),
+                              reinterpret_cast<double2*>(c->mjst.as<char>() + shift_off), b.sig, b.wf, b.sgn, b.iters,
+                              b.nheavy, c->stream));
     QTX_HIP(c, record(c, c->ev_dec, c->n_dec));
     return QTX_OK;
   }

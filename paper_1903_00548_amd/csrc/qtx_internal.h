@@ -228,10 +228,11 @@ hipError_t run_dm_reduce(const double2* rho, int nwg, size_t stride, int N, int 
 // (energy, lead) run in batches of modes_batch_jobs(M, nE * sides), each
 // through three kernels (Hessenberg form, Schur form, modes and outputs);
 // scratch: that many times modes_ws_elems(M) complex doubles, jst: that
-// many ints.  iters: QR sweeps per surface, -1 on failure.
+// many ints, shift: that many complex doubles (the eigenvalue shift each job
+// took).  iters: QR sweeps per surface, -1 on failure.
 hipError_t run_modes(int M, const Prob& P, const double* E, int nE, double eta, int sides, double tol, int m,
-                     int num_cu, double2* scratch, int* jst, double2* sig, double2* wf, double* sgn, int* iters,
-                     int* nheavy, hipStream_t st);
+                     int num_cu, double2* scratch, int* jst, double2* shift, double2* sig, double2* wf, double* sgn,
+                     int* iters, int* nheavy, hipStream_t st);
 inline size_t modes_ws_elems(int M) { return 16 * (size_t)M * M; }
 inline int modes_batch_jobs(int M, int njobs) {
   const int jb = M <= 64 ? 2048 : 512;

@@ -7,7 +7,20 @@
 //      eq. linearized_eigenvalue_symmetric, [[D0, L], [U, 0]] x =
 //      lambda [[-U, 0], [0, U]] x with x = [lambda c; c], brought to the
 //      standard problem C x = lambda x by the block-diagonal right-hand
-//      matrix: C = [[-U^-1 D0, -U^-1 L], [I, 0]];
+//      matrix: C = [[-U^-1 D0, -U^-1 L], [I, 0]].  When U is singular (a
+//      coupling of lower rank than the slab) that pencil is singular too:
+//      its determinant carries det U as a factor for every lambda.  The
+//      quadratic is then taken in the variable nu of the disk automorphism
+//      lambda = (nu + s) / (1 + conj(s) nu), |s| < 1: multiplying
+//      L + lambda D0 + lambda^2 U by (1 + conj(s) nu)^2 gives
+//      L' + nu D0' + nu^2 U' with U' = U + conj(s) D0 + conj(s)^2 L,
+//      D0' = 2 conj(s) L + (1 + |s|^2) D0 + 2 s U, L' = L + s D0 + s^2 U,
+//      whose leading coefficient is invertible unless 1/conj(s) is a Bloch
+//      factor.  The mode vectors c are unchanged, |lambda| < 1, = 1, > 1
+//      exactly when |nu| is, and lambda = infinity (a mode annihilated by
+//      U) is the finite nu = -1/conj(s).  s = 0 (the plain form) is taken
+//      when kappa_F(U) <= kModeKappa, else the first of the other shifts
+//      that meets it, else the best of them;
 //   2. all 2m eigenpairs of C: Householder reduction to Hessenberg form,
 //      complex single-shift QR (Wilkinson shifts, Givens bulge chase) to
 //      the Schur form T = Q^H C Q, eigenvectors of T by back substitution,
@@ -146,7 +159,8 @@ __device__ bool gj_invert(double2* A, int n, int ld, cd* fcol, double* sd, int* 
 
 struct ModeShared {
   cd vec[256];          // Householder vector / Gauss-Jordan factor column
-  cd lam[256];          // eigenvalues
+  cd lam[256];          // Bloch factors lambda
+  cd lami[256];         // their inverses (0 for lambda = infinity)
   double J[256];        // fluxes
   int kind[256];        // 1 right-going, 0 left-going; +2 if travelling
   int ridx[128], lidx[128];
@@ -470,10 +484,24 @@ __device__ bool schur_qr_wave(const HLds& H, int n, double2* Qm, int ld, ModeSha
 
 }  // namespace
 
-// Stage 1 (per job): C = [[-U^-1 D0, -U^-1 L], [I, 0]] and its Hessenberg
-// form with the accumulated reflectors.  jst[jl] = 0, or -1 if U is singular.
+// Shifts s of the eigenvalue variable (step 1 of the header): 0, then three
+// points of modulus about 1/2 spread around the disk.
+constexpr int kModeShifts = 4;
+constexpr double kModeKappa = 1e8;     // largest kappa_F of U' taken without trying the next shift
+__device__ __forceinline__ cd mode_shift(int q) {
+  switch (q) {
+    case 1: return mk<double>(0.3108049841353322, 0.3916634548137417);      // 0.5 e^{0.9 i}
+    case 2: return mk<double>(-0.42844437668447366, 0.2577506859107321);    // 0.5 e^{2.6 i}
+    case 3: return mk<double>(-0.05798002243298609, -0.44624916470361087);  // 0.45 e^{-1.7 i}
+    default: return mk<double>(0.0, 0.0);
+  }
+}
+
+// Stage 1 (per job): C = [[-U'^-1 D0', -U'^-1 L'], [I, 0]] of the shifted
+// quadratic and its Hessenberg form with the accumulated reflectors; the
+// shift taken in shift[jl].  jst[jl] = 0, or -1 if no U' could be inverted.
 template <int M>
-__global__ __launch_bounds__(NT) void k_modes_hess(Prob P, const double* E, double eta, int sides, double tol, int m, int j0, int nb, double2* ws, int* jst) {
+__global__ __launch_bounds__(NT) void k_modes_hess(Prob P, const double* E, double eta, int sides, double tol, int m, int j0, int nb, double2* ws, int* jst, double2* shift) {
   __shared__ ModeShared sh;
   constexpr int LD = 2 * M, MM = M * M;
   constexpr size_t WS = 16 * (size_t)M * M;
@@ -518,16 +546,78 @@ __global__ __launch_bounds__(NT) void k_modes_hess(Prob P, const double* E, doub
     (void)Lel;
     (void)D0el;
     __syncthreads();
-    bool ok = true;
-    // ---- 1. C = [[-U^-1 D0, -U^-1 L], [I, 0]]
-    for (int idx = t; idx < m * m; idx += NT) {
-      const int r = idx / m, c = idx - r * m;
-      sto(Ui + (size_t)r * LD + c, Uel(r, c));
-      sto(Yv + (size_t)r * LD + c, D0el(r, c));
-      sto(Yv + (size_t)r * LD + m + c, Lel(r, c));
+    // sum over the workgroup, the same value in every thread
+    auto bsum = [&](double v) {
+      v = wave_sum(v);
+      if (lane == 0) sh.rc[w] = v;
+      __syncthreads();
+      double r = 0.0;
+      for (int q = 0; q < NWAVE; ++q) r += sh.rc[q];
+      __syncthreads();
+      return r;
+    };
+    // U' into Ui, [D0' | L'] into Yv for shift number q; ||U'||_F^2
+    auto build = [&](int q) {
+      const cd s = mode_shift(q), sb = cconj(s), sb2 = cmul(sb, sb), s2 = cmul(s, s);
+      const double s1 = 1.0 + s.re * s.re + s.im * s.im;
+      double n2 = 0.0;
+      for (int idx = t; idx < m * m; idx += NT) {
+        const int r = idx / m, c = idx - r * m;
+        cd u = Uel(r, c), d = D0el(r, c), l = Lel(r, c);
+        if (q != 0) {
+          const cd u1 = cadd(u, cadd(cmul(sb, d), cmul(sb2, l)));
+          const cd d1 = cadd(cscl(cmul(sb, l), 2.0), cadd(cscl(d, s1), cscl(cmul(s, u), 2.0)));
+          const cd l1 = cadd(l, cadd(cmul(s, d), cmul(s2, u)));
+          u = u1;
+          d = d1;
+          l = l1;
+        }
+        sto(Ui + (size_t)r * LD + c, u);
+        sto(Yv + (size_t)r * LD + c, d);
+        sto(Yv + (size_t)r * LD + m + c, l);
+        n2 += u.re * u.re + u.im * u.im;
+      }
+      return bsum(n2);
+    };
+    // ||U'||_F^2 ||U'^-1||_F^2, or infinity if the inverse failed
+    auto kappa2 = [&](double nu2, bool inv) {
+      if (!inv) return (double)INFINITY;
+      double n2 = 0.0;
+      for (int idx = t; idx < m * m; idx += NT) {
+        const int r = idx / m, c = idx - r * m;
+        const cd v = ldd(Ui + (size_t)r * LD + m + c);
+        n2 += v.re * v.re + v.im * v.im;
+      }
+      const double k2 = nu2 * bsum(n2);
+      return k2 >= 0.0 ? k2 : (double)INFINITY;   // NaN counts as failed
+    };
+    // ---- 1. the shift, U'^-1, then C = [[-U'^-1 D0', -U'^-1 L'], [I, 0]]
+    bool ok = false;
+    int qs = 0, qbest = -1;
+    double k2best = INFINITY;
+    for (int q = 0; q < kModeShifts; ++q) {
+      const double nu2 = build(q);
+      const bool inv = gj_invert(Ui, m, LD, sh.vec, sh.sd, sh.si);
+      const double k2 = kappa2(nu2, inv);
+      if (k2 <= kModeKappa * kModeKappa) {
+        ok = true;
+        qs = q;
+        break;
+      }
+      if (k2 < k2best) {
+        k2best = k2;
+        qbest = q;
+      }
     }
-    __syncthreads();
-    ok = gj_invert(Ui, m, LD, sh.vec, sh.sd, sh.si);
+    if (!ok && qbest >= 0) {
+      qs = qbest;
+      build(qs);
+      ok = gj_invert(Ui, m, LD, sh.vec, sh.sd, sh.si);
+    }
+    if (t == 0) {
+      const cd s = mode_shift(qs);
+      shift[jl] = make_double2(s.re, s.im);
+    }
     if (ok) {
       for (int idx = t; idx < m * n; idx += NT) {
         const int r = idx / n, c = idx - r * n;
@@ -674,8 +764,8 @@ __global__ __launch_bounds__(NT) void k_modes_qr(Prob P, const double* E, double
 // Stage 3 (per job): eigenvectors, the mode split, self-energies, injection
 // and the outputs of both or one surface.
 template <int M>
-__global__ __launch_bounds__(NT) void k_modes_post(Prob P, const double* E, double eta, int sides, double tol, int m, int j0, int nb, double2* ws, int* jst, double2* sig, double2* wf,
-                                                   double* sgn, int* iters, int* nheavy) {
+__global__ __launch_bounds__(NT) void k_modes_post(Prob P, const double* E, double eta, int sides, double tol, int m, int j0, int nb, double2* ws, int* jst, const double2* shift,
+                                                   double2* sig, double2* wf, double* sgn, int* iters, int* nheavy) {
   __shared__ ModeShared sh;
   constexpr int LD = 2 * M, MM = M * M;
   constexpr size_t WS = 16 * (size_t)M * M;
@@ -723,11 +813,16 @@ __global__ __launch_bounds__(NT) void k_modes_post(Prob P, const double* E, doub
     // ---- 2c. eigenvectors of T (thread per eigenvalue), then c = (Q y) rows m..2m-1
     auto Tel = [&](int i, int j) -> cd { return ldd(Cm + (size_t)i * LD + j); };
     const int total = jst[jl];
+    const cd sft = mk<double>(shift[jl].x, shift[jl].y);
     bool ok = total >= 0;
     if (ok) {
       for (int k = t; k < n; k += NT) {
-        const cd lk = Tel(k, k);
-        sh.lam[k] = lk;
+        const cd lk = Tel(k, k);                      // nu_k
+        // lambda = (nu + s) / (1 + conj(s) nu) and its inverse (s = 0: nu
+        // and 1/nu exactly; lambda = infinity gives lami = 0)
+        const cd num = cadd(lk, sft), den = cadd(mk<double>(1.0, 0.0), cmul(cconj(sft), lk));
+        sh.lam[k] = cdivx(num, den);
+        sh.lami[k] = cdivx(den, num);
         const double smin = fmax(eps * cabs1(lk), 1e-290);
         for (int i = k + 1; i < n; ++i) sto(Yv + (size_t)i * LD + k, mk<double>(0.0, 0.0));
         sto(Yv + (size_t)k * LD + k, mk<double>(1.0, 0.0));
@@ -818,8 +913,7 @@ __global__ __launch_bounds__(NT) void k_modes_post(Prob P, const double* E, doub
           const int r = q / m, c = q - r * m;
           cd acc = mk<double>(0.0, 0.0);
           for (int j = 0; j < m; ++j) {
-            const cd lj = sh.lam[idx[j]];
-            const cd f = s == 0 ? cdivx(mk<double>(1.0, 0.0), lj) : lj;
+            const cd f = s == 0 ? sh.lami[idx[j]] : sh.lam[idx[j]];
             acc = cadd(acc, cmul(cmul(ldd(Cv + (size_t)r * LD + idx[j]), f), ldd(Ui + (size_t)j * LD + m + c)));
           }
           sto(Yv + (size_t)r * LD + c, acc);
@@ -848,8 +942,7 @@ __global__ __launch_bounds__(NT) void k_modes_post(Prob P, const double* E, doub
           }
           cd v = mk<double>(0.0, 0.0);
           if (r < m && k >= 0) {
-            const cd lk = sh.lam[k];
-            const cd f = s == 0 ? cdivx(mk<double>(-1.0, 0.0), lk) : mk<double>(-lk.re, -lk.im);
+            const cd f = s == 0 ? mk<double>(-sh.lami[k].re, -sh.lami[k].im) : mk<double>(-sh.lam[k].re, -sh.lam[k].im);
             cd acc = mk<double>(0.0, 0.0);
             for (int j = 0; j < m; ++j) {
               const cd cj = ldd(Cv + (size_t)j * LD + k);
@@ -886,8 +979,8 @@ __global__ __launch_bounds__(NT) void k_modes_post(Prob P, const double* E, doub
 
 template <int M>
 hipError_t launch_modes(const Prob& P, const double* E, int nE, double eta, int sides, double tol, int m, int num_cu,
-                        double2* scratch, int* jst, double2* sig, double2* wf, double* sgn, int* iters, int* nheavy,
-                        hipStream_t st) {
+                        double2* scratch, int* jst, double2* shift, double2* sig, double2* wf, double* sgn, int* iters,
+                        int* nheavy, hipStream_t st) {
   int o1 = 0, o2 = 0, o3 = 0;
   hipError_t err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&o1, k_modes_hess<M>, NT, 0);
   if (err == hipSuccess) err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&o2, k_modes_qr<M>, NT, 0);
@@ -902,11 +995,11 @@ hipError_t launch_modes(const Prob& P, const double* E, int nE, double eta, int 
     // complex doubles each) then stay in the last-level cache, which the
     // reduction re-reads once per column
     hipLaunchKernelGGL(k_modes_hess<M>, dim3(grid(o1 < 2 ? o1 : 2)), dim3(NT), 0, st, P, E, eta, sides, tol, m, j0, nb, scratch,
-                       jst);
+                       jst, shift);
     hipLaunchKernelGGL(k_modes_qr<M>, dim3(grid(o2)), dim3(NT), 0, st, P, E, eta, sides, tol, m, j0, nb, scratch,
                        jst);
     hipLaunchKernelGGL(k_modes_post<M>, dim3(grid(o3)), dim3(NT), 0, st, P, E, eta, sides, tol, m, j0, nb, scratch,
-                       jst, sig, wf, sgn, iters, nheavy);
+                       jst, shift, sig, wf, sgn, iters, nheavy);
     err = hipGetLastError();
     if (err != hipSuccess) return err;
   }
@@ -914,10 +1007,10 @@ hipError_t launch_modes(const Prob& P, const double* E, int nE, double eta, int 
 }
 
 hipError_t run_modes(int M, const Prob& P, const double* E, int nE, double eta, int sides, double tol, int m,
-                     int num_cu, double2* scratch, int* jst, double2* sig, double2* wf, double* sgn, int* iters,
-                     int* nheavy, hipStream_t st) {
+                     int num_cu, double2* scratch, int* jst, double2* shift, double2* sig, double2* wf, double* sgn,
+                     int* iters, int* nheavy, hipStream_t st) {
 #define QTX_MODES(MM) \
-  return launch_modes<MM>(P, E, nE, eta, sides, tol, m, num_cu, scratch, jst, sig, wf, sgn, iters, nheavy, st)
+  return launch_modes<MM>(P, E, nE, eta, sides, tol, m, num_cu, scratch, jst, shift, sig, wf, sgn, iters, nheavy, st)
   switch (M) {
     case 16: QTX_MODES(16);
     case 32: QTX_MODES(32);

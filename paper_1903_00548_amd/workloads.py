@@ -128,6 +128,19 @@ def random_lead(rng: np.random.Generator, m: int, V: float = 0.0) -> Lead:
     return Lead(H00=H00, H01=H01, S00=S00, S01=S01, V=float(V))
 
 
+def low_rank_coupling_lead(rng: np.random.Generator, m: int, rank: int, V: float = 0.0) -> Lead:
+    """A lead whose slab coupling reaches the next slab through `rank` < m
+    directions only: H01 = A B, S01 = A B' with A of m x rank columns (so
+    z S01 - H01 has rank <= rank at every z), on-site blocks as in
+    random_lead (drawn first, in its order)."""
+    base = random_lead(rng, m, V)
+    a = complex_gaussian(rng, (m, rank))
+    h = a @ complex_gaussian(rng, (rank, m))
+    s = a @ complex_gaussian(rng, (rank, m))
+    return Lead(H00=base.H00, H01=h / np.linalg.norm(h, 2), S00=base.S00,
+                S01=0.05 * s / np.linalg.norm(s, 2), V=float(V))
+
+
 def tanh_barrier(N: int, height: float, width: float, ell: float = 5.0) -> np.ndarray:
     """Smooth gate-induced barrier, centred on the device, plateau `height`."""
     i = np.arange(N, dtype=np.float64)

@@ -16,9 +16,12 @@ import pytest
 
 import oracle
 from oracle import bands, leads, qtbm
+from oracle import decimation as odec
 from oracle.density_matrix import density_matrix_blocks
 from paper_1903_00548_amd import _lib
 from paper_1903_00548_amd import workloads as W
+
+import side_chain
 
 pytestmark = pytest.mark.gpu
 
@@ -177,3 +180,72 @@ def test_singular_device_block_is_flagged(gpu_lib):
     assert info["flags"][1] & _lib.FLAG_NONFINITE
     assert info["flags"][0] == 0 and info["flags"][2] == 0
     assert np.all(np.isfinite(T[[0, 2]])) and np.all(np.abs(T[[0, 2]]) < 1e-12)   # decoupled: no transmission
+
+
+# ---- couplings of lower rank than the slab: the paper's symmetric pencil
+# is singular there (tests/test_oracle_singular_coupling.py), and the GPU
+# solves the quadratic in a shifted variable instead.
+
+
+def test_rank_one_coupling_matches_closed_form(gpu_lib):
+    """A chain with a side orbital per slab (coupling of rank one): Sigma of
+    both leads against the closed form at eta = 0, inside and outside the
+    band, and the perfect wire's T = number of open channels."""
+    H00, H01, S00, S01, _ = side_chain.lead()
+    lead = W.Lead(H00=H00, H01=H01, S00=S00, S01=S01)
+    dev = W.Device(N=4, m=2, lead_L=lead, lead_R=lead, V=np.zeros(4), pot_mode=W.POT_DIAG)
+    ctx = _mode_ctx(dev)
+    E = np.array([-2.6, -1.2, -0.5, 0.4, 1.5, 2.5])
+    sig, Wf, s, it = ctx.self_energy(E, 0.0)
+    assert np.all(it > 0), it
+    T, L, info, st = ctx.solve(E, 0.0, _lib.FP64)
+    assert st == _lib.OK
+    for k, e in enumerate(E):
+        ref = side_chain.sigma(e + 0j)
+        for side in (0, 1):
+            d = np.abs(sig[k, side] - ref).max() / max(1.0, np.abs(ref).max())
+            assert d <= 1e-10, f"E={e} side {side}: rel |dSigma| {d:.2e}"
+        nopen = side_chain.open_channels(e)
+        assert int(s[k, 0].sum()) == nopen
+        assert abs(T[k] - nopen) <= 1e-9, (e, T[k], nopen)
+
+
+@pytest.mark.parametrize("m,rank,seed", [(6, 3, 61), (40, 17, 62)])
+def test_low_rank_coupling_against_decimation(gpu_lib, m, rank, seed):
+    """Random leads whose coupling has rank < m (padded blocks 16 and 48):
+    Sigma against the oracle's decimation at eta = 1e-11 (which inverts no
+    coupling; the two differ by O(eta) and by the conditioning of the
+    energy: up to 3.5e-9 relative on the host, bar 1e-7), the injection
+    rebuilding Gamma with the open-channel rank, and T and slab densities
+    of a barrier device against the oracle's Green's-function solve with
+    those self-energies."""
+    lead = W.low_rank_coupling_lead(np.random.default_rng(seed), m, rank)
+    N = 5
+    dev = W.Device(N=N, m=m, lead_L=lead, lead_R=lead, V=W.tanh_barrier(N, 0.2, 2.0, ell=1.0),
+                   pot_mode=W.POT_DIAG)
+    ctx = _mode_ctx(dev)
+    E = np.array([-1.9, -0.83, 0.37, 1.21, 2.2])
+    sig, Wf, s, it = ctx.self_energy(E, 0.0)
+    assert np.all(it > 0), it
+    T, L, info, st = ctx.solve(E, 0.0, _lib.FP64)
+    assert st == _lib.OK
+    worst = [0.0, 0.0, 0.0]
+    for k, e in enumerate(E):
+        sL, sR, _ = odec.decimate(e + 1e-11j, _lead(lead))
+        for side, ref in ((0, sL), (1, sR)):
+            d = np.abs(sig[k, side] - ref).max() / max(1.0, np.abs(ref).max())
+            worst[0] = max(worst[0], d)
+            assert d <= 1e-7, f"E={e} side {side}: rel |dSigma| {d:.2e}"
+            gam = leads.broadening(sig[k, side])
+            rec = (Wf[k, side] * s[k, side][None, :]) @ Wf[k, side].conj().T
+            assert np.abs(rec - gam).max() <= 1e-9 * max(1.0, np.abs(gam).max())
+        nopen = bands.open_channels_scan(e, lead.H00, lead.H01, lead.S00, lead.S01, lead.V)
+        assert int(s[k, 0].sum()) == nopen
+        Tg, nL, nR = oracle.solve_energy(dev, float(e), 0.0, sigma=(sL, sR))
+        worst[1] = max(worst[1], abs(T[k] - Tg))
+        assert abs(T[k] - Tg) <= 1e-7, (e, T[k], Tg)
+        for got, ref in ((L[k, 0], nL), (L[k, 1], nR)):
+            d = np.abs(got - ref).max() / max(1.0, np.abs(ref).max())
+            worst[2] = max(worst[2], d)
+            assert d <= 1e-6, f"E={e}: rel |dn| {d:.2e}"
+    print(f"m={m} rank={rank}: max rel |dSigma| {worst[0]:.1e}, max |dT| {worst[1]:.1e}, max rel |dn| {worst[2]:.1e}")
