@@ -302,6 +302,38 @@ __device__ __forceinline__ void cgemm_col(ctile<R> (&acc)[MT], const AF& A, cons
   }
 }
 
+// B with its contraction index shifted by k0: B'[k][col] = B[k0 + k][col].
+template <class BF> struct BOff {
+  BF b; int k0;
+  __device__ __forceinline__ auto get(int k, int col) const { return b.get(k0 + k, col); }
+};
+
+// Row stride (complex elements) of a staged 16-column slice of A in LDS.
+constexpr int kStageStride = 17;
+
+// cgemm_col over the whole contraction (M = 16 MT) with A staged through
+// LDS in slices of 16 columns (buf: M * kStageStride elements): the
+// workgroup loads each slice once, coalesced, and all its waves read it
+// from LDS, where cgemm_col has every wave read all of A from the caches.
+// For A in global memory that every wave needs (blocks above 64).  Takes
+// two barriers per slice: every wave of the workgroup must make the same
+// sequence of calls.
+template <typename R, int MT, class AF, class BF>
+__device__ __forceinline__ void cgemm_col_staged(ctile<R> (&acc)[MT], const AF& A, const BF& B, int tj, cpx<R>* buf) {
+  constexpr int M = 16 * MT;
+  const int t = threadIdx.x;
+#pragma unroll 1
+  for (int k0 = 0; k0 < M; k0 += 16) {
+    __syncthreads();                                // the previous slice is consumed
+    for (int idx = t; idx < M * 16; idx += NT) {
+      const int r = idx >> 4, kk = idx & 15;
+      buf[r * kStageStride + kk] = A.get(r, k0 + kk);
+    }
+    __syncthreads();
+    cgemm_col<R, MT, 1>(acc, ALds<R>{buf, kStageStride}, BOff<BF>{B, k0}, tj);
+  }
+}
+
 // Visit the elements held by this lane in a column of tiles:
 // fn(row, col, re, im, ti, r).
 template <typename R, int MT, class F>

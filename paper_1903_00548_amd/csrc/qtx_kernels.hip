@@ -1094,7 +1094,11 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(Prob P0, SweepArgs a, BatchDesc
     cpx<double> stg[STG];
   } lu;
   cpx<R>* const mat_l = lu.m;
-  __shared__ cpx<R> Ysc[gj_scratch<M, PW>()];
+  // the elimination's scratch; above 64 (FP64) also the staged slices of
+  // the A operand of the sweep's three products (-L_i, the inverse, -X_i)
+  constexpr bool STAGE = BIG && !MIX && !DM;
+  constexpr int YS = gj_scratch<M, PW>() > (STAGE ? M * kStageStride : 0) ? gj_scratch<M, PW>() : M * kStageStride;
+  __shared__ __align__(16) cpx<R> Ysc[YS];
   __shared__ BGJ<R, M> sc;
   __shared__ double tred[NWAVE];
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
@@ -1177,16 +1181,18 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(Prob P0, SweepArgs a, BatchDesc
       }
       // Column tiles of [Dt | y]: the y tiles go straight to the workspace,
       // the (at most DT) Dt tile columns of this wave stay in registers until
-      // every wave has finished reading L_i from the LDS buffer.
+      // every wave has finished reading L_i from the LDS buffer.  (M > 64:
+      // both go straight to their buffers, in one pass, so that every wave
+      // takes the same number of tiles through the staged product.)
       constexpr int DT = BIG ? 1 : (MT + NWAVE - 1) / NWAVE;
       ctile<R> dacc[DT][MT];
 #pragma unroll 1
-      for (int pass = 0; pass < 2; ++pass) {
+      for (int pass = 0; pass < (BIG ? 1 : 2); ++pass) {
         int nd = 0;
 #pragma unroll 1
         for (int tj = w; tj < 2 * MT; tj += NWAVE) {
           const bool is_d = tj < MT;
-          if (is_d != (pass == 1)) continue;
+          if (!BIG && is_d != (pass == 1)) continue;
           ctile<R> acc[MT];
           if (is_d) {
             tiles_foreach<R, MT>(acc, tj, [&](int row, int col, int ti, int r) {
@@ -1217,7 +1223,10 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(Prob P0, SweepArgs a, BatchDesc
 #pragma unroll
             for (int ti = 0; ti < MT; ++ti) tzero(acc[ti]);
           }
-          if (i > 0) cgemm_col<R, MT, MT>(acc, ALds<R>{Lst, S}, BGlob<R>{Xi - (size_t)M * LD, LD}, tj);
+          if (i > 0) {
+            if constexpr (STAGE) cgemm_col_staged<R, MT>(acc, ALds<R>{Lst, S}, BGlob<R>{Xi - (size_t)M * LD, LD}, tj, Ysc);
+            else cgemm_col<R, MT, MT>(acc, ALds<R>{Lst, S}, BGlob<R>{Xi - (size_t)M * LD, LD}, tj);
+          }
           if (is_d && BIG) {
             // the Schur complement goes straight to its own buffer
             tiles_foreach<R, MT>(acc, tj, [&](int row, int col, int ti, int r) {
@@ -1268,16 +1277,21 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(Prob P0, SweepArgs a, BatchDesc
 #pragma unroll
         for (int ti = 0; ti < MT; ++ti) tzero(acc[ti]);
         ALds<R> A{mat, S};
+        // every wave takes 2 MT / NWAVE column tiles (whole: MT is 6 or 8
+        // above 64), so the staged product's barriers line up
+        auto prod = [&](const auto& B) {
+          if constexpr (STAGE) cgemm_col_staged<R, MT>(acc, A, B, tj, Ysc);
+          else cgemm_col<R, MT, MT>(acc, A, B, tj);
+        };
         if (tj < MT) {
           if (i < N - 1) {
             const double vu = P.vu(i);
-            cgemm_col<R, MT, MT>(
-                acc, A, BPerm<BGen<R>>{BGen<R>{P.Su(i), P.Hu(i), mk<double>(z.re - vu, z.im), M}, sc.piv}, tj);
+            prod(BPerm<BGen<R>>{BGen<R>{P.Su(i), P.Hu(i), mk<double>(z.re - vu, z.im), M}, sc.piv});
           } else {
-            cgemm_col<R, MT, MT>(acc, A, BPerm<BGlobD<R>>{BGlobD<R>{WR, M}, sc.piv}, tj);
+            prod(BPerm<BGlobD<R>>{BGlobD<R>{WR, M}, sc.piv});
           }
         } else {
-          cgemm_col<R, MT, MT>(acc, A, BPerm<BGlob<R>>{BGlob<R>{Xi, LD}, sc.piv}, tj);
+          prod(BPerm<BGlob<R>>{BGlob<R>{Xi, LD}, sc.piv});
         }
         // rows land through the inverse pivot order; a column tile is read
         // and written by one wave only, so the scatter needs no barrier
@@ -1346,7 +1360,8 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(Prob P0, SweepArgs a, BatchDesc
           for (int ti = 0; ti < MT; ++ti) tzero(acc[ti]);
         }
         if (i < N - 1) {
-          if constexpr (BIG) cgemm_col<R, MT, MT>(acc, AGlob<R>{Xi, LD, (R)-1}, BGlob<R>{PSn, LD}, tj);
+          if constexpr (STAGE) cgemm_col_staged<R, MT>(acc, AGlob<R>{Xi, LD, (R)-1}, BGlob<R>{PSn, LD}, tj, Ysc);
+          else if constexpr (BIG) cgemm_col<R, MT, MT>(acc, AGlob<R>{Xi, LD, (R)-1}, BGlob<R>{PSn, LD}, tj);
           else cgemm_col<R, MT, MT>(acc, ALds<R>{mat, S}, BGlob<R>{PSn, LD}, tj);
         }
         const int cl = 16 * tj + (lane & 15);
