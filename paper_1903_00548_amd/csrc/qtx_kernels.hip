@@ -141,12 +141,72 @@ __device__ __forceinline__ void gj_panel(cpx<R>* mat, int S, int k, BGJ<R, M>& s
 // waves; each wave runs its tiles in groups of at most four through one
 // interleaved MFMA loop, so that up to eight accumulator chains are in
 // flight.  A group's surplus slots recompute a valid tile and do not store.
+// Above 64 (matrix in global memory) the tiles go in groups of RG along a
+// tile row instead, when the rows split into whole groups and the groups
+// evenly over the waves: a group then loads its panel operand once per
+// step for all its tiles, where the round-robin deal has each tile of a
+// tile row read it again from the caches.
+template <int M, int PW> constexpr int gj_row_group() {
+  constexpr int W = M / 16 - PW / 16, NG3 = (M / 16) * W / 3, NG2 = (M / 16) * W / 2;
+  if (M <= 64 || W <= 0) return 0;
+  if (W % 3 == 0 && NG3 % NWAVE == 0) return 3;
+  if (W % 2 == 0 && NG2 % NWAVE == 0) return 2;
+  return 0;
+}
+
 template <typename R, int M, int PW>
 __device__ __forceinline__ void gj_update(cpx<R>* mat, int S, int k, const cpx<R>* Y, const BGJ<R, M>& sc) {
   constexpr int PT = PW / 16;
   constexpr int MT = M / 16, NTILE = MT * (MT - PT), TPW = (NTILE + NWAVE - 1) / NWAVE, WY = M - PW;
   constexpr int GRP = TPW < 4 ? TPW : 4;
-  if constexpr (NTILE > 0) {
+  constexpr int RG = gj_row_group<M, PW>();
+  if constexpr (RG > 0) {
+    constexpr int WC = MT - PT, GPW = NTILE / RG / NWAVE;     // tile columns, groups per wave
+    const int w = threadIdx.x >> 6, lane = lane_id(), g = lane >> 4, c = lane & 15;
+#pragma unroll 1
+    for (int j = 0; j < GPW; ++j) {
+      const int t0 = (w + NWAVE * j) * RG;                   // first tile of the group (row-major)
+      const int ti = t0 / WC, arow = 16 * ti;
+      int bcol[RG], xcol[RG];
+      ctile<R> acc[RG];
+#pragma unroll
+      for (int q = 0; q < RG; ++q) {
+        const int tcx = t0 - ti * WC + q, tc = tcx + (tcx >= PT * k ? PT : 0);
+        bcol[q] = 16 * tcx + c;
+        xcol[q] = 16 * tc + c;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = arow + mf<R>::row(r, g);
+          const cpx<R> v = sc.ppanel[row] == k ? mk<R>(0, 0) : mat[row * S + xcol[q]];
+          acc[q].re[r] = v.re;
+          acc[q].im[r] = v.im;
+        }
+      }
+#pragma unroll
+      for (int sl = 0; sl < 4 * PT; ++sl) {
+        const int kk = 16 * (sl >> 2) + 4 * g + (sl & 3);
+        const cpx<R> av = mat[(arow + c) * S + PW * k + kk];
+        cpx<R> bv[RG];
+#pragma unroll
+        for (int q = 0; q < RG; ++q) bv[q] = Y[kk * WY + bcol[q]];
+#pragma unroll
+        for (int q = 0; q < RG; ++q) {
+          acc[q].re = mf<R>::op(av.re, bv[q].re, acc[q].re);
+          acc[q].im = mf<R>::op(av.re, bv[q].im, acc[q].im);
+        }
+#pragma unroll
+        for (int q = 0; q < RG; ++q) {
+          acc[q].re = mf<R>::op(-av.im, bv[q].im, acc[q].re);
+          acc[q].im = mf<R>::op(av.im, bv[q].re, acc[q].im);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < RG; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          mat[(arow + mf<R>::row(r, g)) * S + xcol[q]] = mk<R>(acc[q].re[r], acc[q].im[r]);
+    }
+  } else if constexpr (NTILE > 0) {
     const int w = threadIdx.x >> 6, lane = lane_id(), g = lane >> 4, c = lane & 15;
 #pragma unroll 1
     for (int q0 = 0; q0 < TPW; q0 += GRP) {
