@@ -173,10 +173,11 @@ def bench_cfg2(args):
     """N = 400, m = 128: 3840 energies in [-1.5, 1.5] plus 256 within 1 meV of
     the lead band edges.  Mixed and FP64 paths; the mixed path's error
     against FP64 on every energy (uniform and band-edge sets reported
-    separately) and both against the oracle on sampled energies."""
+    separately).  Agreement with the oracle is the GPU tests' job
+    (tests/test_gpu_parity.py, tests/test_gpu_mixed.py: 16 sampled
+    energies of this grid); the oracle runs here only as the CPU baseline."""
     import torch
     from paper_1903_00548_amd import _lib, workloads
-    import oracle
     assert torch.cuda.is_available(), "bench needs a GPU"
     edges = np.loadtxt(os.path.join(ROOT, "tests", "golden", "cfg2_band_edge_energies.txt"))
     wl = workloads.config2(band_edge_energies=edges)
@@ -216,13 +217,6 @@ def bench_cfg2(args):
     scale = np.maximum(1.0, np.abs(L64).max(axis=2))
     dT = np.abs(Tm - T64)
     dn = (np.abs(Lm - L64).max(axis=2) / scale).max(axis=1)
-    idx = np.array([0, n_uni // 2, n_uni + 3, nE - 7])
-    Tref, Lref = oracle.solve_device(dev, wl.E[idx], wl.eta)
-    sref = np.maximum(1.0, np.abs(Lref).max(axis=2))
-    ora = {}
-    for name, T, L in (("fp64", T64, L64), ("mixed", Tm, Lm)):
-        ora[name] = {"max_dT": float(np.abs(T[idx] - Tref).max()),
-                     "max_rel_dn": float((np.abs(L[idx] - Lref).max(axis=2) / sref).max())}
     mi = res["mixed"]["info"]
     paths = {}
     for name in ("fp64", "mixed"):
@@ -245,7 +239,6 @@ def bench_cfg2(args):
             "fp64_fallbacks_band_edge": int(mi["fell_back_fp64"][n_uni:].sum()),
             "flagged": int((mi["flags"] != 0).sum()),
         },
-        "vs_oracle_sampled": {"energy_indices": idx.tolist(), **ora},
         "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline(wl, args.cpu_seconds, "config2"),
     }
     print(json.dumps(line))
@@ -253,10 +246,11 @@ def bench_cfg2(args):
 
 def bench_bands(args):
     """Band structure of a lead (Bloch eigenproblem per k point) on the GPU:
-    k points per second at m = 64 and m = 128, 8192 k points per call."""
+    k points per second at m = 64 and m = 128, 8192 k points per call; the
+    oracle's eigensolver on one core as the CPU baseline (accuracy against
+    it: tests/test_gpu_bands.py)."""
     import torch
     from paper_1903_00548_amd import _lib, workloads
-    from oracle import bands as obands
     assert torch.cuda.is_available(), "bench needs a GPU"
     out = {}
     k = np.linspace(-np.pi, np.pi, 8192, endpoint=False)
@@ -270,14 +264,13 @@ def bench_bands(args):
             a = time.perf_counter()
             E = ctx.bands(_lib.LEFT, k)
             t.append(time.perf_counter() - a)
-        sample = k[::1024]
-        ref = obands.bands(sample, lead.H00, lead.H01, lead.S00, lead.S01)
-        a = time.perf_counter()
-        obands.bands(sample, lead.H00, lead.H01, lead.S00, lead.S01)
-        cpu = len(sample) / (time.perf_counter() - a)
-        out[f"m{m}"] = {"k_points_per_s": len(k) / float(np.median(t)), "s_per_call": float(np.median(t)),
-                        "max_abs_dE_vs_oracle_sampled": float(np.abs(E[::1024] - ref).max()),
-                        "oracle_k_points_per_s_one_core": cpu}
+        out[f"m{m}"] = {"k_points_per_s": len(k) / float(np.median(t)), "s_per_call": float(np.median(t))}
+        if not args.no_cpu_baseline:
+            from oracle import bands as obands
+            sample = k[::1024]
+            a = time.perf_counter()
+            obands.bands(sample, lead.H00, lead.H01, lead.S00, lead.S01)
+            out[f"m{m}"]["cpu_baseline_oracle_k_points_per_s_one_core"] = len(sample) / (time.perf_counter() - a)
     print(json.dumps({
         "metric": "band-structure k points/s (Bloch eigenproblem per k, FP64)", "value": out["m64"]["k_points_per_s"],
         "unit": "k points/s", "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": 1e3 * out["m64"]["s_per_call"],
@@ -312,7 +305,6 @@ def bench_density_matrix(args):
     Inputs and outputs stay in HBM."""
     import torch
     from paper_1903_00548_amd import _lib, workloads
-    from oracle.density_matrix import density_matrix_blocks
     assert torch.cuda.is_available(), "bench needs a GPU"
     wl = workloads.config1()
     dev = wl.device
@@ -320,6 +312,7 @@ def bench_density_matrix(args):
     wL, wR = dm_weights(wl.E)
     cpu = None
     if not args.no_cpu_baseline:
+        from oracle.density_matrix import density_matrix_blocks
         k = 8
         sub = np.linspace(0, nE - 1, k).astype(int)
         a = time.perf_counter()
@@ -420,13 +413,13 @@ def bench_modes(args):
     eta = 1e-6.  Energies and outputs stay in HBM."""
     import torch
     from paper_1903_00548_amd import _lib, workloads
-    import oracle
     assert torch.cuda.is_available(), "bench needs a GPU"
     wl = workloads.config1()
     dev = wl.device
     N, m, nE = dev.N, dev.m, len(wl.E)
     cpu = None
     if not args.no_cpu_baseline:
+        import oracle
         sub = np.linspace(0, nE - 1, 8).astype(int)
         a = time.perf_counter()
         for k in sub:
