@@ -138,6 +138,19 @@ struct ALdsF {                                 // FP64 row-major in LDS, read as
   }
 };
 
+// A[r][k] = -L[r][k], L the coupling of a slab to the previous one, made
+// from the forward coupling blocks S, H (row-major) of that previous slab:
+// L[r][k] = zu S[k][r]^* - H[k][r]^* (the transposed read of A = zS - H).
+template <typename R> struct AGenL {
+  const double2* S; const double2* H; cpx<double> zu; int M;
+  __device__ __forceinline__ cpx<R> get(int r, int k) const {
+    const cpx<double> sv = ldd(S + (size_t)k * M + r), hv = ldd(H + (size_t)k * M + r);
+    const double re = zu.re * sv.re + zu.im * sv.im - hv.re;
+    const double im = zu.im * sv.re - zu.re * sv.im + hv.im;
+    return mk<R>((R)-re, (R)-im);
+  }
+};
+
 template <typename R> struct AGlob {           // row-major global, optionally negated
   const typename vec2t<R>::type* p; int ld; R sgn;
   __device__ __forceinline__ cpx<R> get(int row, int k) const {
@@ -317,8 +330,10 @@ constexpr int kStageStride = 17;
 // from LDS, where cgemm_col has every wave read all of A from the caches.
 // For A in global memory that every wave needs (blocks above 64).  Takes
 // two barriers per slice: every wave of the workgroup must make the same
-// sequence of calls.
-template <typename R, int MT, class AF, class BF>
+// sequence of calls.  ACOL: the threads walk the slice down its columns
+// (for an A stored transposed, so that the reads stay coalesced), else
+// along its rows.
+template <typename R, int MT, bool ACOL = false, class AF, class BF>
 __device__ __forceinline__ void cgemm_col_staged(ctile<R> (&acc)[MT], const AF& A, const BF& B, int tj, cpx<R>* buf) {
   constexpr int M = 16 * MT;
   const int t = threadIdx.x;
@@ -326,7 +341,14 @@ __device__ __forceinline__ void cgemm_col_staged(ctile<R> (&acc)[MT], const AF& 
   for (int k0 = 0; k0 < M; k0 += 16) {
     __syncthreads();                                // the previous slice is consumed
     for (int idx = t; idx < M * 16; idx += NT) {
-      const int r = idx >> 4, kk = idx & 15;
+      int r, kk;
+      if constexpr (ACOL) {
+        kk = idx / M;
+        r = idx - kk * M;
+      } else {
+        r = idx >> 4;
+        kk = idx & 15;
+      }
       buf[r * kStageStride + kk] = A.get(r, k0 + kk);
     }
     __syncthreads();

@@ -1224,8 +1224,9 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(Prob P0, SweepArgs a, BatchDesc
       // Stage A = -L_i = -(A_{i,i-1}) once per slab in the LDS buffer (free
       // until the new Schur complement is written): every wave reads the
       // whole of it, which from L1/L2 would exceed the cache bandwidth.
-      // (M > 64: a separate global buffer, in the layout the products read.)
-      if (i > 0) {
+      // (M > 64 FP64: generated straight into the product's staged slices;
+      // the mixed sweep above 64 stages it in a global buffer.)
+      if (i > 0 && !STAGE) {
         const double vu = P.vu(i - 1);
         const cpx<double> zu = mk<double>(z.re - vu, z.im);
         const double2* Su = P.Su(i - 1);
@@ -1284,8 +1285,13 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(Prob P0, SweepArgs a, BatchDesc
             for (int ti = 0; ti < MT; ++ti) tzero(acc[ti]);
           }
           if (i > 0) {
-            if constexpr (STAGE) cgemm_col_staged<R, MT>(acc, ALds<R>{Lst, S}, BGlob<R>{Xi - (size_t)M * LD, LD}, tj, Ysc);
-            else cgemm_col<R, MT, MT>(acc, ALds<R>{Lst, S}, BGlob<R>{Xi - (size_t)M * LD, LD}, tj);
+            if constexpr (STAGE) {
+              const cpx<double> zu = mk<double>(z.re - P.vu(i - 1), z.im);
+              cgemm_col_staged<R, MT, true>(acc, AGenL<R>{P.Su(i - 1), P.Hu(i - 1), zu, M},
+                                            BGlob<R>{Xi - (size_t)M * LD, LD}, tj, Ysc);
+            } else {
+              cgemm_col<R, MT, MT>(acc, ALds<R>{Lst, S}, BGlob<R>{Xi - (size_t)M * LD, LD}, tj);
+            }
           }
           if (is_d && BIG) {
             // the Schur complement goes straight to its own buffer
