@@ -211,6 +211,14 @@ int wgs_per_cu(const qtx_ctx* c, int M, bool mixed) {
   return c->wg_per_cu;
 }
 
+// Decimation workgroups per CU: the decimation kernel is compiled for two
+// per CU at every block size, so above 64 it keeps two whatever the sweep
+// runs (the mixed sweeps there run one); at 64 and below it follows the
+// sweep's count, which the autotuner times together with it.
+int dec_wgs_per_cu(const qtx_ctx* c, int M, bool mixed) {
+  return M > 64 ? 2 : wgs_per_cu(c, M, mixed);
+}
+
 // Launch shape of the sweeps at block size M: the autotuned one, else the
 // default workgroups per CU with the tile shapes of the options panel_width
 // and refine_tiles where the block size allows them, else the defaults.
@@ -314,7 +322,7 @@ struct SolveBufs {
 
 // Decimation workgroups for nE energies (sides lead iterations each).
 int dec_grid(const qtx_ctx* c, int nE, int sides, bool mixed) {
-  return std::max(1, std::min(nE * sides, c->num_cu * wgs_per_cu(c, c->M, mixed)));
+  return std::max(1, std::min(nE * sides, c->num_cu * dec_wgs_per_cu(c, c->M, mixed)));
 }
 
 // lead self-energies, injection factors and signs for energies E_dev[0..nE)
@@ -572,7 +580,7 @@ qtx_status plan_noalloc(qtx_ctx* c, int nE, bool mixed, char* base, size_t cap, 
                                         (long long)std::floor(budget / (double)wsb)});
   grid = std::max<long long>(grid, 1);
   size_t rest = avail - (size_t)grid * per_wg;
-  long long gdec = std::min<long long>({(long long)c->num_cu * wgs_per_cu(c, M, mixed), (long long)nE * sides,
+  long long gdec = std::min<long long>({(long long)c->num_cu * dec_wgs_per_cu(c, M, mixed), (long long)nE * sides,
                                         (long long)(rest / 4 / dec_wg)});
   gdec = std::max<long long>(gdec, 1);
   rest -= (size_t)gdec * dec_wg;
@@ -1129,7 +1137,7 @@ qtx_status enqueue_batch(qtx_ctx* c, const std::vector<BatchChunk>& chunks, cons
   for (const DecGroup& g : groups) {
     if (g.njobs == 0) continue;
     qtx_ctx::SigCache& sc = c->sigcache[g.M];
-    const int wg = wgs_per_cu(c, g.M, mixed);
+    const int wg = dec_wgs_per_cu(c, g.M, mixed);
     qtx::BatchDesc b{};
     b.probs = c->bprobs.as<qtx::Prob>();
     b.job_item = c->bjob_item.as<int>() + g.job0;
@@ -1146,7 +1154,7 @@ qtx_status enqueue_batch(qtx_ctx* c, const std::vector<BatchChunk>& chunks, cons
   for (const BatchChunk& k : chunks) {
     const int M = k.M;
     const bool big = M > 64;
-    const int wg = wgs_per_cu(c, M, mixed);
+    const int wg = dec_wgs_per_cu(c, M, mixed);
     qtx::BatchDesc b{};
     b.probs = c->bprobs.as<qtx::Prob>();
     b.item_prob = c->bitem_prob.as<int>() + k.item0;
@@ -1413,13 +1421,13 @@ qtx_status qtx_solve_batch(qtx_ctx* c, int nprob, qtx_ctx* const* probs, const d
   // buffer sizes (all allocations before any capture)
   size_t sig_b = 0, dscr_b = 0, sws_b = 0, part_b = 0, per_b = 0;
   for (const DecGroup& g : groups) {
-    const int wg = wgs_per_cu(c, g.M, mixed);
+    const int wg = dec_wgs_per_cu(c, g.M, mixed);
     const size_t gdec = std::max(1, std::min(g.njobs, c->num_cu * wg));
     dscr_b = std::max(dscr_b, gdec * qtx::dec_ws_elems(g.M) * sizeof(double2));
   }
   for (const BatchChunk& k : chunks) {
     const size_t MM = (size_t)k.M * k.M;
-    const int wg = wgs_per_cu(c, k.M, mixed);
+    const int wg = dec_wgs_per_cu(c, k.M, mixed);
     const size_t gdec = std::max(1, std::min(k.njobs, c->num_cu * wg));
     sig_b = std::max(sig_b, (size_t)k.nitems * 2 * MM * sizeof(double2));
     per_b = std::max(per_b, (size_t)k.nitems);

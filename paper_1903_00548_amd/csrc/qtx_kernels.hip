@@ -645,8 +645,14 @@ __device__ void sigma_newton(double2* sig, const double2* lead, cpx<double> zx, 
 // one step of iterative refinement, X <- X + e^-1 ([a | b] - e X), brings
 // it back to the accuracy of an LU solve.  Well-conditioned doublings, most
 // of them away from the lead's band edges, skip the step's two products.
+// Two workgroups per CU at every block size: above 64 the working matrix
+// lives in the global workspace, and the second workgroup on each SIMD
+// hides part of its latency (at 128 the kernel spills a few registers
+// and is still faster than at one workgroup per CU with no spill).  There
+// the products also take their A operand through LDS in 16-column slices,
+// loaded once per workgroup instead of once per wave and column tile.
 template <int M>
-__global__ __launch_bounds__(NT, M > 64 ? 1 : 2) void k_decimate(Prob P0, BatchDesc b, const double* E, int nE,
+__global__ __launch_bounds__(NT, 2) void k_decimate(Prob P0, BatchDesc b, const double* E, int nE,
                                                                  double eta, int sides, DecOpts o, double2* scratch,
                                                                  double2* sig, double2* wf, double* sgn, int* iters,
                                                                  int* nheavy) {
@@ -654,6 +660,11 @@ __global__ __launch_bounds__(NT, M > 64 ? 1 : 2) void k_decimate(Prob P0, BatchD
   const int maxit = o.maxit;
   constexpr int MT = M / 16, MM = M * M, S = M + 1, LB = 2 * M;
   constexpr bool BIG = M > 64;                    // working matrix in the global workspace
+  // above 64 the A operand of every product comes through LDS in 16-column
+  // slices (the elimination scratch, free during the products)
+  constexpr bool STAGE = BIG;
+  static_assert(!STAGE || gj_scratch<M>() >= M * kStageStride, "staging slice exceeds the scratch");
+  static_assert(!STAGE || (2 * MT) % NWAVE == 0, "staged products need the same tile count on every wave");
   __shared__ cpx<double> mat_l[BIG ? 1 : M * S];
   __shared__ __align__(16) union {
     cpx<double> y[gj_scratch<M>()];
@@ -663,6 +674,11 @@ __global__ __launch_bounds__(NT, M > 64 ? 1 : 2) void k_decimate(Prob P0, BatchD
   __shared__ double red[2][NWAVE];
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   double2* ws = scratch + (size_t)blockIdx.x * dec_ws_elems(M);
+  // C += A B over column tile tj, staged or direct
+  auto prod = [&](ctile<double>(&acc)[MT], const auto& A, const auto& B, int tj) {
+    if constexpr (STAGE) cgemm_col_staged<double, MT>(acc, A, B, tj, u.y);
+    else cgemm_col<double, MT, MT>(acc, A, B, tj);
+  };
   cpx<double>* mat;
   if constexpr (BIG) mat = (cpx<double>*)(ws + 8 * MM);
   else mat = mat_l;
@@ -738,7 +754,7 @@ __global__ __launch_bounds__(NT, M > 64 ? 1 : 2) void k_decimate(Prob P0, BatchD
         ctile<double> acc[MT];
 #pragma unroll
         for (int ti = 0; ti < MT; ++ti) tzero(acc[ti]);
-        cgemm_col<double, MT, MT>(acc, ALds<double>{mat, S}, BPerm<BGlob<double>>{BGlob<double>{AB, LB}, sc.piv}, tj);
+        prod(acc, ALds<double>{mat, S}, BPerm<BGlob<double>>{BGlob<double>{AB, LB}, sc.piv}, tj);
         tiles_foreach<double, MT>(acc, tj, [&](int row, int col, int ti, int r) {
           X[(unsigned)(sc.pinv[row] * LB + col)] = make_double2(acc[ti].re[r], acc[ti].im[r]);
         });
@@ -750,7 +766,7 @@ __global__ __launch_bounds__(NT, M > 64 ? 1 : 2) void k_decimate(Prob P0, BatchD
           acc[ti].re[r] = v.x;
           acc[ti].im[r] = v.y;
         });
-        cgemm_col<double, MT, MT>(acc, AGlob<double>{eps, M, -1.0}, BGlob<double>{X, LB}, tj);
+        prod(acc, AGlob<double>{eps, M, -1.0}, BGlob<double>{X, LB}, tj);
         tiles_foreach<double, MT>(acc, tj, [&](int row, int col, int ti, int r) {
           Rr[(unsigned)(row * LB + col)] = make_double2(acc[ti].re[r], acc[ti].im[r]);
         });
@@ -761,7 +777,7 @@ __global__ __launch_bounds__(NT, M > 64 ? 1 : 2) void k_decimate(Prob P0, BatchD
           acc[ti].re[r] = v.x;
           acc[ti].im[r] = v.y;
         });
-        cgemm_col<double, MT, MT>(acc, ALds<double>{mat, S}, BPerm<BGlob<double>>{BGlob<double>{Rr, LB}, sc.piv}, tj);
+        prod(acc, ALds<double>{mat, S}, BPerm<BGlob<double>>{BGlob<double>{Rr, LB}, sc.piv}, tj);
         tiles_foreach<double, MT>(acc, tj, [&](int row, int col, int ti, int r) {
           X[(unsigned)(sc.pinv[row] * LB + col)] = make_double2(acc[ti].re[r], acc[ti].im[r]);
         });
@@ -781,17 +797,18 @@ __global__ __launch_bounds__(NT, M > 64 ? 1 : 2) void k_decimate(Prob P0, BatchD
           mat[r * S + c] = ldd(Aop + r * LB + c);
         }
         __syncthreads();
+        // one accumulator column live at a time: a g b, a g a | b g a, b g b;
+        // the 2 MT (product, column tile) pairs are dealt over the waves
 #pragma unroll 1
-        for (int tj = w; tj < MT; tj += NWAVE) {
-          // one accumulator column live at a time: a g b, a g a | b g a, b g b
-#pragma unroll 1
-          for (int qq = 0; qq < 2; ++qq) {
+        for (int pj = w; pj < 2 * MT; pj += NWAVE) {
+          {
+            const int qq = pj / MT, tj = pj - qq * MT;
             const int q = half == 0 ? 2 * qq : 1 + 2 * qq;
             ctile<double> acc[MT];
 #pragma unroll
             for (int ti = 0; ti < MT; ++ti) tzero(acc[ti]);
             const double2* Bop = (q == 0 || q == 3) ? X + M : X;
-            cgemm_col<double, MT, MT>(acc, ALds<double>{mat, S}, BGlob<double>{Bop, LB}, tj);
+            prod(acc, ALds<double>{mat, S}, BGlob<double>{Bop, LB}, tj);
             tiles_foreach<double, MT>(acc, tj, [&](int row, int col, int ti, int r) {
               const unsigned idx = row * M + col;
               const double re = acc[ti].re[r], im = acc[ti].im[r];
