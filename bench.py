@@ -40,7 +40,8 @@ def flops_per_energy(N, m, n_dec):
     return (N + n_dec) * (152.0 / 3.0) * m ** 3
 
 
-KERNEL_SOURCES = ("paper_1903_00548_amd/csrc/qtx_kernels.hip", "paper_1903_00548_amd/csrc/qtx_device.h")
+KERNEL_SOURCES = ("paper_1903_00548_amd/csrc/qtx_kernels.hip", "paper_1903_00548_amd/csrc/qtx_device.h",
+                  "paper_1903_00548_amd/csrc/qtx_internal.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_cfg1_fp64_hbm_traffic.md")
 TRAFFIC_FILE_DM = os.path.join(ROOT, "profiles", "k_sweep_density_matrix_cfg1.md")
 

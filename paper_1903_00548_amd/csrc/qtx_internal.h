@@ -22,13 +22,13 @@ struct Prob {
   const double* V;
   int pot_mode;
 
-  __host__ __device__ const double2* Hd(int i) const { return dHd ? dHd + (size_t)i * M * M : leadL; }
-  __host__ __device__ const double2* Hu(int i) const { return dHu ? dHu + (size_t)i * M * M : leadL + (size_t)M * M; }
-  __host__ __device__ const double2* Sd(int i) const { return dSd ? dSd + (size_t)i * M * M : leadL + 2 * (size_t)M * M; }
-  __host__ __device__ const double2* Su(int i) const { return dSu ? dSu + (size_t)i * M * M : leadL + 3 * (size_t)M * M; }
+  __host__ __device__ __forceinline__ const double2* Hd(int i) const { return dHd ? dHd + (size_t)i * M * M : leadL; }
+  __host__ __device__ __forceinline__ const double2* Hu(int i) const { return dHu ? dHu + (size_t)i * M * M : leadL + (size_t)M * M; }
+  __host__ __device__ __forceinline__ const double2* Sd(int i) const { return dSd ? dSd + (size_t)i * M * M : leadL + 2 * (size_t)M * M; }
+  __host__ __device__ __forceinline__ const double2* Su(int i) const { return dSu ? dSu + (size_t)i * M * M : leadL + 3 * (size_t)M * M; }
 
   // potential weight on the on-site overlap block of slab i
-  __device__ double vd(int i) const {
+  __device__ __forceinline__ double vd(int i) const {
     if (!V) return 0.0;
     if (pot_mode == QTX_POT_DIAG) return V[i];
     const double vm = i > 0 ? V[i - 1] : VL;
@@ -36,7 +36,7 @@ struct Prob {
     return 0.75 * V[i] + 0.125 * (vm + vp);
   }
   // potential weight on the coupling overlap block i -> i+1
-  __device__ double vu(int i) const {
+  __device__ __forceinline__ double vu(int i) const {
     if (!V || pot_mode == QTX_POT_DIAG) return 0.0;
     return 0.5 * (V[i] + V[i + 1]);
   }

@@ -512,7 +512,7 @@ __device__ __forceinline__ void prod_cols(const AF& A, const BF& B, F fn) {
 // ws: 7 M^2 complex doubles of free global workspace; mat, Y, sc: the
 // Gauss-Jordan matrix, scratch and pivots; red: NWAVE doubles of LDS.
 template <int M>
-__device__ void sigma_newton(double2* sig, const double2* lead, cpx<double> zx, int side, double tol, double2* ws,
+__device__ __forceinline__ void sigma_newton(double2* sig, const double2* lead, cpx<double> zx, int side, double tol, double2* ws,
                              cpx<double>* mat, cpx<double>* Y, BGJ<double, M>& sc, double* red) {
   constexpr int MT = M / 16, MM = M * M, S = M + 1;
   const int t = threadIdx.x, w = t >> 6;
