@@ -512,8 +512,9 @@ __device__ __forceinline__ void prod_cols(const AF& A, const BF& B, F fn) {
 // ws: 7 M^2 complex doubles of free global workspace; mat, Y, sc: the
 // Gauss-Jordan matrix, scratch and pivots; red: NWAVE doubles of LDS.
 template <int M>
-__device__ __forceinline__ void sigma_newton(double2* sig, const double2* lead, cpx<double> zx, int side, double tol, double2* ws,
-                             cpx<double>* mat, cpx<double>* Y, BGJ<double, M>& sc, double* red) {
+__device__ __forceinline__ void sigma_newton(double2* sig, const double2* lead, cpx<double> zx, int side, double tol,
+                                             double2* ws, cpx<double>* mat, cpx<double>* Y, BGJ<double, M>& sc,
+                                             double* red) {
   constexpr int MT = M / 16, MM = M * M, S = M + 1;
   const int t = threadIdx.x, w = t >> 6;
   const double2 *H00 = lead, *H01 = lead + MM, *S00 = lead + 2 * MM, *S01 = lead + 3 * MM;
@@ -652,10 +653,9 @@ __device__ __forceinline__ void sigma_newton(double2* sig, const double2* lead, 
 // the products also take their A operand through LDS in 16-column slices,
 // loaded once per workgroup instead of once per wave and column tile.
 template <int M>
-__global__ __launch_bounds__(NT, 2) void k_decimate(Prob P0, BatchDesc b, const double* E, int nE,
-                                                                 double eta, int sides, DecOpts o, double2* scratch,
-                                                                 double2* sig, double2* wf, double* sgn, int* iters,
-                                                                 int* nheavy) {
+__global__ __launch_bounds__(NT, 2) void k_decimate(Prob P0, BatchDesc b, const double* E, int nE, double eta,
+                                                    int sides, DecOpts o, double2* scratch, double2* sig, double2* wf,
+                                                    double* sgn, int* iters, int* nheavy) {
   const double tol = o.tol, rcond = o.rcond;
   const int maxit = o.maxit;
   constexpr int MT = M / 16, MM = M * M, S = M + 1, LB = 2 * M;
@@ -784,9 +784,10 @@ __global__ __launch_bounds__(NT, 2) void k_decimate(Prob P0, BatchDesc b, const 
       }
       // doubling update: output column tile tj reads column tiles tj (g a)
       // and MT + tj (g b) of X, written by other waves unless M/16 == NWAVE.
-      // g is dead from here on: a, then b, is staged in its LDS buffer as
-      // the shared A operand of the two products that use it, so a' and b'
-      // overwrite a and b in global memory once their staging is done.
+      // g is dead from here on: a, then b, is copied into the working matrix
+      // (LDS, or the global workspace above 64) as the shared A operand of
+      // the two products that use it, so a' and b' overwrite a and b in
+      // place once the copy is done.
       __syncthreads();
       double na = 0.0, nb = 0.0;
 #pragma unroll 1
@@ -801,28 +802,26 @@ __global__ __launch_bounds__(NT, 2) void k_decimate(Prob P0, BatchDesc b, const 
         // the 2 MT (product, column tile) pairs are dealt over the waves
 #pragma unroll 1
         for (int pj = w; pj < 2 * MT; pj += NWAVE) {
-          {
-            const int qq = pj / MT, tj = pj - qq * MT;
-            const int q = half == 0 ? 2 * qq : 1 + 2 * qq;
-            ctile<double> acc[MT];
+          const int qq = pj / MT, tj = pj - qq * MT;
+          const int q = half == 0 ? 2 * qq : 1 + 2 * qq;
+          ctile<double> acc[MT];
 #pragma unroll
-            for (int ti = 0; ti < MT; ++ti) tzero(acc[ti]);
-            const double2* Bop = (q == 0 || q == 3) ? X + M : X;
-            prod(acc, ALds<double>{mat, S}, BGlob<double>{Bop, LB}, tj);
-            tiles_foreach<double, MT>(acc, tj, [&](int row, int col, int ti, int r) {
-              const unsigned idx = row * M + col;
-              const double re = acc[ti].re[r], im = acc[ti].im[r];
-              if (q < 2) {
-                double2 v = eps[idx];
-                v.x -= re; v.y -= im; eps[idx] = v;
-                if (q == 0) { v = esR[idx]; v.x -= re; v.y -= im; esR[idx] = v; }
-              } else {
-                AB[(unsigned)(row * LB + col) + (q == 3 ? M : 0)] = make_double2(-re, -im);
-                if (q == 2) na = fmax(na, fabs(re) + fabs(im));
-                else nb = fmax(nb, fabs(re) + fabs(im));
-              }
-            });
-          }
+          for (int ti = 0; ti < MT; ++ti) tzero(acc[ti]);
+          const double2* Bop = (q == 0 || q == 3) ? X + M : X;
+          prod(acc, ALds<double>{mat, S}, BGlob<double>{Bop, LB}, tj);
+          tiles_foreach<double, MT>(acc, tj, [&](int row, int col, int ti, int r) {
+            const unsigned idx = row * M + col;
+            const double re = acc[ti].re[r], im = acc[ti].im[r];
+            if (q < 2) {
+              double2 v = eps[idx];
+              v.x -= re; v.y -= im; eps[idx] = v;
+              if (q == 0) { v = esR[idx]; v.x -= re; v.y -= im; esR[idx] = v; }
+            } else {
+              AB[(unsigned)(row * LB + col) + (q == 3 ? M : 0)] = make_double2(-re, -im);
+              if (q == 2) na = fmax(na, fabs(re) + fabs(im));
+              else nb = fmax(nb, fabs(re) + fabs(im));
+            }
+          });
         }
         __syncthreads();
       }
