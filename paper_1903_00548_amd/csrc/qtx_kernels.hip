@@ -665,7 +665,7 @@ __global__ __launch_bounds__(NT, 2) void k_decimate(Prob P0, BatchDesc b, const 
   constexpr bool STAGE = BIG;
   static_assert(!STAGE || gj_scratch<M>() >= M * kStageStride, "staging slice exceeds the scratch");
   static_assert(!STAGE || (2 * MT) % NWAVE == 0, "staged products need the same tile count on every wave");
-  __shared__ cpx<double> mat_l[BIG ? 1 : M * S];
+  __shared__ __align__(16) cpx<double> mat_l[BIG ? 1 : M * S];
   __shared__ __align__(16) union {
     cpx<double> y[gj_scratch<M>()];
     LDLScratch<M> ldl;
@@ -793,9 +793,18 @@ __global__ __launch_bounds__(NT, 2) void k_decimate(Prob P0, BatchDesc b, const 
 #pragma unroll 1
       for (int half = 0; half < 2; ++half) {
         const double2* Aop = AB + half * M;
-        for (int idx = t; idx < MM; idx += NT) {
-          const int r = idx / M, c = idx - r * M;
-          mat[r * S + c] = ldd(Aop + r * LB + c);
+        if constexpr (M == 64) {
+          // a plain copy: direct global-to-LDS loads, one 64-element row
+          // (1 KB) per wave instruction
+          for (int r = w; r < M; r += NWAVE)
+            __builtin_amdgcn_global_load_lds((const void*)(Aop + r * LB + lane),
+                                             (__attribute__((address_space(3))) void*)(mat + r * S), 16, 0, 0);
+          __builtin_amdgcn_s_waitcnt(0);
+        } else {
+          for (int idx = t; idx < MM; idx += NT) {
+            const int r = idx / M, c = idx - r * M;
+            mat[r * S + c] = ldd(Aop + r * LB + c);
+          }
         }
         __syncthreads();
         // one accumulator column live at a time: a g b, a g a | b g a, b g b;
@@ -1148,8 +1157,8 @@ __device__ __forceinline__ double refine(const Prob& P, const SweepArgs& a, cons
 // keeping the refinement diagnostics in info and marking the fallback.
 //
 // Two workgroups per CU at every block size.  Above 64 this caps the
-// registers at 256 per lane, and the FP64 sweep spills about 100 bytes per
-// lane at M = 128.  A second wave per SIMD issues MFMAs while the first
+// registers at 256 per lane, and the FP64 sweep spills about 70 bytes per
+// lane at M = 128 (outside its MFMA loops).  A second wave per SIMD issues MFMAs while the first
 // waits on its operands in L2, which more than pays for the spill.
 template <typename R, int M, bool MIX, bool DM, int PW = gj_pw<M>(), int TPP = (M <= 64 ? 2 : 1)>
 __global__ __launch_bounds__(NT, 2) void k_sweep(Prob P0, SweepArgs a, BatchDesc b) {
@@ -1173,6 +1182,12 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(Prob P0, SweepArgs a, BatchDesc
   // the elimination's scratch; above 64 (FP64) also the staged slices of
   // the A operand of the sweep's three products (-L_i, the inverse, -X_i)
   constexpr bool STAGE = BIG && !MIX && !DM;
+  // FP64 at M = 64: X_i reaches the working matrix for the back
+  // substitution by direct global-to-LDS loads (one 64-element row, 1 KB,
+  // per wave instruction), without passing through registers; it lands
+  // un-negated, so the product runs on -(initial value) and the result is
+  // negated back (exact: the rounding of every step is symmetric in sign)
+  constexpr bool XDMA = !BIG && !MIX && M == 64 && sizeof(cpx<R>) == 16;
   constexpr int YS = gj_scratch<M, PW>() > (STAGE ? M * kStageStride : 0) ? gj_scratch<M, PW>() : M * kStageStride;
   __shared__ __align__(16) cpx<R> Ysc[YS];
   __shared__ BGJ<R, M> sc;
@@ -1417,7 +1432,14 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(Prob P0, SweepArgs a, BatchDesc
       if (i < N - 1) {
         // stage -X_i in LDS once per slab (every wave reads all of it);
         // M > 64 reads X_i where it is
-        if constexpr (!BIG) {
+        if constexpr (XDMA) {
+          __syncthreads();
+          for (int r = w; r < M; r += NWAVE)
+            __builtin_amdgcn_global_load_lds((const void*)(Xi + (unsigned)(r * LD) + lane),
+                                             (__attribute__((address_space(3))) void*)(mat + r * S), 16, 0, 0);
+          __builtin_amdgcn_s_waitcnt(0);
+          __syncthreads();
+        } else if constexpr (!BIG) {
           __syncthreads();
           for (int idx = t; idx < MM; idx += NT) {
             const int r = idx / M, c = idx - r * M;
@@ -1428,14 +1450,16 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(Prob P0, SweepArgs a, BatchDesc
         }
       }
       double pL = 0.0, pR = 0.0;
+      // XDMA: the product accumulates -psi_i from -[0 | z_i] and +X_i
+      const R sgn = (XDMA && i < N - 1) ? (R)-1 : (R)1;
 #pragma unroll 1
       for (int tj = w; tj < 2 * MT; tj += NWAVE) {
         ctile<R> acc[MT];
         if (i == N - 1 || tj >= MT) {
           tiles_foreach<R, MT>(acc, tj, [&](int row, int col, int ti, int r) {
             cpx<R> v = ld2<R>(Xi + (unsigned)(row * LD + col));
-            acc[ti].re[r] = v.re;
-            acc[ti].im[r] = v.im;
+            acc[ti].re[r] = sgn * v.re;
+            acc[ti].im[r] = sgn * v.im;
           });
         } else {
 #pragma unroll
@@ -1455,8 +1479,8 @@ __global__ __launch_bounds__(NT, 2) void k_sweep(Prob P0, SweepArgs a, BatchDesc
         }
         double pp = 0.0;
         tiles_foreach<R, MT>(acc, tj, [&](int row, int col, int ti, int r) {
-          const double re = acc[ti].re[r], im = acc[ti].im[r];
-          st2<R>(PSc + (unsigned)(row * LD + col), mk<R>(acc[ti].re[r], acc[ti].im[r]));
+          const double re = sgn * acc[ti].re[r], im = sgn * acc[ti].im[r];
+          st2<R>(PSc + (unsigned)(row * LD + col), mk<R>(sgn * acc[ti].re[r], sgn * acc[ti].im[r]));
           if constexpr (MIX)
             if (keep) P64[(size_t)i * M * LD + (unsigned)(row * LD + col)] = make_double2(re, im);
           pp += re * re + im * im;
