@@ -668,6 +668,9 @@ def main():
                     help="headline workload only: skip the serving and N=400, m=128 legs")
     args = ap.parse_args()
     if args.workload == "bands":
+        if args.gpus != 1:
+            print("bench.py: one GPU only", file=sys.stderr)
+            sys.exit(2)
         bench_bands(args)
         return
     if args.workload == "modes":
