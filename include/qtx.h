@@ -266,7 +266,8 @@ qtx_status qtx_self_energy(qtx_ctx* ctx, const double* E, int nE, double eta,
  *                           resonances miss 1e-8 relative);
  *   "workgroups_per_cu"     [1, 4]        2      resident energies per CU for
  *                           blocks up to 64 (blocks of 96 and 128 use two
- *                           with QTX_FP64, one with QTX_MIXED); setting it
+ *                           with QTX_FP64, one with QTX_MIXED, and their lead
+ *                           decimation two with either); setting it
  *                           discards autotuned values;
  *   "panel_width"           0, 16 or 32   0      columns of a Gauss-Jordan panel
  *                           in the sweeps' block inverse; 0 takes 16 up to
